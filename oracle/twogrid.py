@@ -1,0 +1,135 @@
+"""Damped-Jacobi relaxation and the POD two-grid cycle (Sec. 2.2 Alg. 2,
+Sec. 3.3 Eq. 30).
+
+One cycle applied to a right-hand side r from a zero initial guess is the
+preconditioner of Alg. 3 (s = AMG(0; K, r, r1, r2)):
+
+1. r1 damped-Jacobi sweeps x <- x + omega D^{-1} (r - K x) from x = 0
+   (pre-relaxation);
+2. residual r' = r - K x;
+3. restriction r_c = P^T r' and the Galerkin coarse solve
+   (P^T K P) e_c = r_c, by Cholesky factors L L^T = P^T K P;
+4. prolongation and correction x <- x + P e_c;
+5. r2 damped-Jacobi sweeps on K x = r (post-relaxation).
+
+The paper analyses Gauss-Seidel relaxation but leaves the smoother of its
+experiments open; damped Jacobi keeps the cycle symmetric, so it is a valid
+CG preconditioner.
+
+``precision="fp32"`` emulates an FP32 preconditioner: K, D^{-1}, P and the
+residual scaled by ``scale`` are rounded to binary32 and every cycle step
+except the coarse Cholesky solve runs in binary32; the coarse solve stays
+FP64.  The returned vector is converted back and divided by ``scale``.  The
+default scale is the power of two 2^-e with ||r|| = m 2^e, m in [0.5, 1):
+scaling by a power of two commutes with binary32 rounding, so it only keeps
+the cycle's values inside the binary32 range and changes no result bit.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse as sp
+
+ENOTSPD = -4
+
+
+class NotSPD(ArithmeticError):
+    status = ENOTSPD
+
+
+def jacobi_sweeps(K, dinv, b, x, omega, nsweeps):
+    """nsweeps damped-Jacobi iterations x <- x + omega D^{-1} (b - K x)."""
+    for _ in range(nsweeps):
+        x = x + omega * dinv * (b - K @ x)
+    return x
+
+
+def coarse_matrix(K, P):
+    """K_c = P^T K P (Alg. 2, restrict-and-solve step; Sec. 3.3 Eq. 28)."""
+    return P.T @ (K @ P)
+
+
+def coarse_factor(K, P):
+    """Lower Cholesky factor of K_c; raises NotSPD on a non-positive pivot."""
+    Kc = coarse_matrix(K, P)
+    try:
+        return np.linalg.cholesky(Kc)
+    except np.linalg.LinAlgError as e:
+        raise NotSPD(str(e)) from e
+
+
+def coarse_solve(L, rc):
+    """e_c with L L^T e_c = r_c (forward then backward substitution)."""
+    y = sla.solve_triangular(L, rc, lower=True)
+    return sla.solve_triangular(L.T, y, lower=False)
+
+
+class TwoGrid:
+    """The POD two-grid cycle with fixed K, D^{-1}, P and smoother settings."""
+
+    def __init__(self, K, P, omega, nu_pre=2, nu_post=2, precision="fp64"):
+        self.K = sp.csr_matrix(K)
+        self.dinv = 1.0 / self.K.diagonal()
+        self.P = np.asarray(P, dtype=np.float64)
+        self.omega = float(omega)
+        self.nu_pre = int(nu_pre)
+        self.nu_post = int(nu_post)
+        self.precision = precision
+        self.L = coarse_factor(self.K, self.P) if self.P.shape[1] > 0 else None
+        if precision == "fp32":
+            self.K32 = self.K.astype(np.float32)
+            self.dinv32 = self.dinv.astype(np.float32)
+            self.P32 = self.P.astype(np.float32)
+            self.omega32 = np.float32(self.omega)
+
+    # -- FP64 cycle ---------------------------------------------------------
+    def _cycle64(self, r):
+        K, dinv, P, w = self.K, self.dinv, self.P, self.omega
+        x = np.zeros_like(r)
+        x = jacobi_sweeps(K, dinv, r, x, w, self.nu_pre)
+        if self.L is not None:
+            rr = r - K @ x
+            rc = P.T @ rr
+            ec = coarse_solve(self.L, rc)
+            x = x + P @ ec
+        x = jacobi_sweeps(K, dinv, r, x, w, self.nu_post)
+        return x
+
+    # -- FP32-emulated cycle (coarse solve in FP64) --------------------------
+    def _cycle32(self, r, scale):
+        K, dinv, P, w = self.K32, self.dinv32, self.P32, self.omega32
+        b = (r * scale).astype(np.float32)
+        x = np.zeros_like(b)
+        x = jacobi_sweeps(K, dinv, b, x, w, self.nu_pre).astype(np.float32)
+        if self.L is not None:
+            rr = (b - K @ x).astype(np.float32)
+            rc = (P.T @ rr).astype(np.float32)
+            ec = coarse_solve(self.L, rc.astype(np.float64)).astype(np.float32)
+            x = (x + P @ ec).astype(np.float32)
+        x = jacobi_sweeps(K, dinv, b, x, w, self.nu_post).astype(np.float32)
+        return x.astype(np.float64) / scale
+
+    def apply(self, r, scale=None):
+        """s = B r: one cycle from the zero initial guess."""
+        r = np.asarray(r, dtype=np.float64)
+        if self.precision == "fp32":
+            if scale is None:
+                nr = np.linalg.norm(r)
+                scale = float(np.ldexp(1.0, -np.frexp(nr)[1])) if nr > 0 else 1.0
+            return self._cycle32(r, scale)
+        return self._cycle64(r)
+
+    __call__ = apply
+
+
+def power_lambda_max(K, dinv, iters=50):
+    """Power-iteration estimate of lambda_max(D^{-1} K) from the all-ones
+    start vector (setup guard: the damped-Jacobi smoother needs
+    omega * lambda_max < 2)."""
+    x = np.ones(K.shape[0])
+    lam = 0.0
+    for _ in range(iters):
+        y = dinv * (K @ x)
+        lam = float(np.linalg.norm(y) / np.linalg.norm(x))
+        x = y / np.linalg.norm(y)
+    return lam

@@ -1,0 +1,177 @@
+"""Pins of the oracle's FE discretisation (Sec. 2.1, Eqs. 5-6) against closed
+forms, invariants and a published element matrix."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import fem
+from paper_2207_02543_amd import inputs as I
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load_q4_closed_form(nu):
+    ks, idx = [], []
+    with open(os.path.join(GOLDEN, "q4_plane_stress_unit_square.txt")) as fh:
+        for line in fh:
+            if line.startswith("k "):
+                c0, c1 = map(float, line.split()[1:])
+                ks.append(c0 + c1 * nu)
+            elif line.startswith("idx "):
+                idx.append([int(t) for t in line.split()[1:]])
+    return np.array([[ks[i - 1] for i in row] for row in idx]) / (1.0 - nu * nu)
+
+
+@pytest.mark.parametrize("nu", [0.3, 0.0, 0.45])
+def test_q4_matches_published_closed_form(nu):
+    # published node order is counter-clockwise from the lower-left corner:
+    # (-1,-1), (1,-1), (1,1), (-1,1) = our local nodes 0, 1, 3, 2
+    Ke = fem.element_stiffness(2, nu, 1.0)
+    perm = [0, 1, 3, 2]
+    dofs = [2 * l + c for l in perm for c in range(2)]
+    np.testing.assert_allclose(Ke[np.ix_(dofs, dofs)], _load_q4_closed_form(nu),
+                               rtol=0, atol=1e-15)
+
+
+def test_q4_independent_of_h():
+    np.testing.assert_allclose(fem.element_stiffness(2, 0.3, 1 / 7),
+                               fem.element_stiffness(2, 0.3, 1.0), rtol=1e-14, atol=1e-15)
+
+
+@pytest.mark.parametrize("dim,nzero", [(2, 3), (3, 6)])
+def test_element_rigid_modes_and_dilatation(dim, nzero):
+    nu, h = 0.3, 1.0 / 6
+    Ke = fem.element_stiffness(dim, nu, h)
+    assert np.abs(Ke - Ke.T).max() == 0.0 or np.abs(Ke - Ke.T).max() < 1e-17
+    ev = np.linalg.eigvalsh(Ke)
+    assert np.sum(np.abs(ev) < 1e-12 * ev.max()) == nzero
+    assert ev.min() > -1e-12 * ev.max()
+    # dilatation mode u = x (node coordinates relative to the centre)
+    nodes = np.array([[((l >> d) & 1) - 0.5 for d in range(dim)] for l in range(2 ** dim)]) * h
+    v = nodes.reshape(-1)
+    Kv = Ke @ v
+    lam = (v @ Kv) / (v @ v)
+    np.testing.assert_allclose(Kv, lam * v, rtol=0, atol=1e-13)
+    if dim == 2:
+        expected = 1.0 / (1.0 - nu)                  # E / (1 - nu), E = 1
+    else:
+        expected = h / (2.0 * (1.0 - 2.0 * nu))      # E h / (2 (1 - 2 nu))
+    assert lam == pytest.approx(expected, rel=1e-13)
+
+
+def test_hex8_scales_with_h():
+    np.testing.assert_allclose(fem.element_stiffness(3, 0.3, 0.5),
+                               0.5 * fem.element_stiffness(3, 0.3, 1.0), rtol=1e-13, atol=1e-16)
+
+
+def test_kl_multi_index_order():
+    assert [tuple(a) for a in fem.kl_multi_indices(2, 8)] == [
+        (0, 1), (0, 2), (0, 3), (1, 0), (1, 1), (1, 2), (1, 3), (2, 0)]
+    a3 = fem.kl_multi_indices(3, 16)
+    assert tuple(a3[0]) == (0, 0, 1) and tuple(a3[14]) == (0, 3, 3) and tuple(a3[15]) == (1, 0, 0)
+
+
+def test_young_modulus_special_cases():
+    # xi = 0 gives the unit modulus everywhere
+    assert np.all(fem.young_modulus(3, 3, np.zeros(16)) == 1.0)
+    # one term, a = (0, 1): E = exp(0.3 cos(pi y_c) / 2); element (0,0) of a
+    # 2 x 2 mesh has centroid (1/4, 1/4): exp(0.15 cos(pi/4)) = exp(0.15/sqrt 2)
+    E = fem.young_modulus(2, 2, [1.0] + [0.0] * 7)
+    assert E[0] == pytest.approx(math.exp(0.15 / math.sqrt(2.0)), rel=1e-15)
+    # element (1,1): centroid (3/4, 3/4): cos(3 pi / 4) = -1/sqrt 2
+    assert E[3] == pytest.approx(math.exp(-0.15 / math.sqrt(2.0)), rel=1e-15)
+    # term 4 is a = (1, 0): depends on x only, element (1,0) centroid x = 3/4
+    E = fem.young_modulus(2, 2, [0, 0, 0, 2.0, 0, 0, 0, 0])
+    assert E[1] == pytest.approx(math.exp(0.3 * 2.0 * -1 / math.sqrt(2.0) / 2.0), rel=1e-15)
+
+
+@pytest.mark.parametrize("dim,N,n,nnz", [(2, 32, 2112, 36472), (2, 8, 144, 2200), (3, 4, 300, None)])
+def test_sizes(dim, N, n, nnz):
+    w = I.small(dim, N)
+    K = fem.assemble(dim, N, 0.3, np.ones(N ** dim))
+    assert K.shape == (n, n) == (w.n, w.n)
+    if dim == 2:
+        assert K.nnz == 4 * (3 * N - 2) * (3 * N + 1)
+    else:
+        assert K.nnz == 9 * (3 * N + 1) ** 2 * (3 * N - 2)
+    if nnz is not None:
+        assert K.nnz == nnz
+
+
+@pytest.mark.parametrize("dim,N", [(2, 5), (3, 3)])
+def test_assembly_symmetry_and_rigid_modes(dim, N):
+    E = fem.young_modulus(dim, N, I.query_xi(I.small(dim, N), 0))
+    Kf = fem.assemble_full(dim, N, 0.3, E)
+    # symmetric up to the summation order of coincident element entries
+    assert abs(Kf - Kf.T).max() <= 4 * np.finfo(float).eps * abs(Kf).max()
+    h = 1.0 / N
+    coords = np.array([[(nid // (N + 1) ** d) % (N + 1) * h for d in range(dim)]
+                       for nid in range((N + 1) ** dim)])
+    modes = []
+    for c in range(dim):                       # translations
+        m = np.zeros_like(coords)
+        m[:, c] = 1.0
+        modes.append(m)
+    pairs = [(0, 1)] if dim == 2 else [(0, 1), (1, 2), (2, 0)]
+    for a, b in pairs:                         # infinitesimal rotations
+        m = np.zeros_like(coords)
+        m[:, a] = -coords[:, b]
+        m[:, b] = coords[:, a]
+        modes.append(m)
+    scale = abs(Kf).max()
+    for m in modes:
+        assert np.abs(Kf @ m.reshape(-1)).max() < 1e-12 * scale
+    K = fem.assemble(dim, N, 0.3, E)
+    assert abs(K - K.T).max() <= 4 * np.finfo(float).eps * abs(K).max()
+    ev = np.linalg.eigvalsh(K.toarray())
+    assert ev.min() > 0.0
+
+
+@pytest.mark.parametrize("dim,N", [(2, 4), (2, 7), (3, 3)])
+def test_patch_energy(dim, N):
+    """Homogeneous E = 1 and a uniform strain field: the energy u^T K u equals
+    the strain energy density times the unit volume, exact for (bi/tri)linear
+    elements.  2D: u = (x, 0) -> 1/(1-nu^2).  3D: u = (0, 0, z) -> lambda+2mu."""
+    nu = 0.3
+    Kf = fem.assemble_full(dim, N, nu, np.ones(N ** dim))
+    h = 1.0 / N
+    u = np.zeros(dim * (N + 1) ** dim)
+    for nid in range((N + 1) ** dim):
+        if dim == 2:
+            u[2 * nid] = (nid % (N + 1)) * h
+        else:
+            u[3 * nid + 2] = (nid // (N + 1) ** 2) * h
+    if dim == 2:
+        expected = 1.0 / (1.0 - nu * nu)
+    else:
+        lam = nu / ((1 + nu) * (1 - 2 * nu))
+        mu = 1.0 / (2 * (1 + nu))
+        expected = lam + 2 * mu
+    assert u @ (Kf @ u) == pytest.approx(expected, rel=1e-13)
+
+
+@pytest.mark.parametrize("dim,N", [(2, 3), (2, 32), (3, 2), (3, 5)])
+def test_traction_total_and_distribution(dim, N):
+    f = fem.traction_load(dim, N)
+    assert f.sum() == pytest.approx(1.0, rel=1e-14)
+    h = 1.0 / N
+    ff = fem.traction_load_full(dim, N).reshape(-1, dim)
+    if dim == 2:
+        edge = [fem.node_id(2, N, [N, j]) for j in range(N + 1)]
+        assert ff[edge[0], 0] == pytest.approx(h / 2) and ff[edge[1], 0] == pytest.approx(h)
+        assert np.count_nonzero(ff) == N + 1
+    else:
+        assert ff[fem.node_id(3, N, [0, 0, N]), 2] == pytest.approx(h * h / 4)
+        assert ff[fem.node_id(3, N, [1, 0, N]), 2] == pytest.approx(h * h / 2)
+        assert ff[fem.node_id(3, N, [1, 1, N]), 2] == pytest.approx(h * h)
+        assert np.count_nonzero(ff) == (N + 1) ** 2
+
+
+def test_free_dof_numbering():
+    # 2D: free node of (i, j) is (i - 1) + N j; 3D: i + (N+1) j + (N+1)^2 (l - 1)
+    fd = fem.free_dofs(2, 4)
+    assert fd[0] == 2 * 1 and fd[2 * (2 + 4 * 3) + 1] == 2 * fem.node_id(2, 4, [3, 3]) + 1
+    fd = fem.free_dofs(3, 3)
+    assert fd[3 * (1 + 4 * 2 + 16 * 0) + 2] == 3 * fem.node_id(3, 3, [1, 2, 1]) + 2

@@ -1,0 +1,147 @@
+"""Pins of the oracle's POD basis (Sec. 3.3), two-grid cycle (Sec. 2.2 Alg. 2,
+Sec. 3.3 Eq. 30) and smoother against textbook routines, the paper's
+error-propagation formulas (Eqs. 20-22 and 30) and invariants."""
+import numpy as np
+import pytest
+
+from oracle import pod, problem, twogrid
+from paper_2207_02543_amd import inputs as I
+
+
+def _tiny(dim, N, k, omega):
+    w = I.small(dim, N, k=k, n_train=8, omega=omega)
+    P, lam, U = problem.basis(w, I.train_xis(w))
+    K = problem.stiffness(w, I.query_xi(w, 0))
+    return w, K, P, U
+
+
+def _dense_B(M, n):
+    return np.stack([M(np.eye(n)[:, i]) for i in range(n)], axis=1)
+
+
+# ---------------------------------------------------------------- POD ------
+def test_pod_orthonormal_and_singular_values():
+    rng = np.random.default_rng(0)
+    U = rng.standard_normal((300, 12)) @ np.diag(np.logspace(0, -3, 12))
+    P, lam = pod.pod_basis(U, 7)
+    np.testing.assert_allclose(P.T @ P, np.eye(7), atol=1e-12)
+    sv = np.linalg.svd(U, compute_uv=False)
+    np.testing.assert_allclose(lam, sv ** 2, rtol=1e-10)
+    # span equals the top left singular vectors
+    Q = np.linalg.svd(U, full_matrices=False)[0][:, :7]
+    np.testing.assert_allclose(P @ P.T, Q @ Q.T, atol=1e-10)
+
+
+def test_pod_of_elasticity_snapshots():
+    w, K, P, U = _tiny(2, 6, 5, 2 / 3)
+    Q, sv, _ = np.linalg.svd(U, full_matrices=False)
+    _, lam = pod.pod_basis(U, 5)
+    np.testing.assert_allclose(lam[:5], sv[:5] ** 2, rtol=1e-8)
+    # the basis spans the leading left singular subspace
+    proj = Q[:, :5].T @ P
+    np.testing.assert_allclose(np.linalg.svd(proj, compute_uv=False), 1.0, atol=1e-6)
+
+
+def test_pod_rank_deficient_raises():
+    U = np.ones((10, 3))
+    with pytest.raises(ValueError):
+        pod.pod_basis(U, 2)
+
+
+# ------------------------------------------------------------ smoother -----
+def test_one_sweep_from_zero_is_scaled_diagonal():
+    w, K, P, U = _tiny(2, 5, 3, 2 / 3)
+    rng = np.random.default_rng(1)
+    b = rng.standard_normal(K.shape[0])
+    dinv = 1.0 / K.diagonal()
+    x = twogrid.jacobi_sweeps(K, dinv, b, np.zeros_like(b), w.omega, 1)
+    assert np.array_equal(x, np.zeros_like(b) + w.omega * dinv * (b - 0.0))
+
+
+def test_power_iteration_matches_dense_eigenvalue():
+    w, K, P, U = _tiny(3, 2, 3, 0.5)
+    dinv = 1.0 / K.diagonal()
+    exact = np.max(np.linalg.eigvals(dinv[:, None] * K.toarray()).real)
+    assert twogrid.power_lambda_max(K, dinv, iters=400) == pytest.approx(exact, rel=1e-6)
+
+
+# --------------------------------------------------------------- cycle -----
+@pytest.mark.parametrize("dim,N,k,omega,nu1,nu2", [
+    (2, 4, 4, 2 / 3, 2, 2), (2, 3, 2, 2 / 3, 1, 3), (3, 2, 4, 0.5, 2, 2)])
+def test_cycle_error_operator(dim, N, k, omega, nu1, nu2):
+    """I - B K = M^{nu2} C M^{nu1} with M = I - omega D^{-1} K and
+    C = I - P (P^T K P)^{-1} P^T K (Eqs. 21-22 with the POD prolongation of
+    Eq. 30)."""
+    w, K, P, U = _tiny(dim, N, k, omega)
+    n = K.shape[0]
+    Kd = K.toarray()
+    M = np.eye(n) - omega * (1.0 / np.diag(Kd))[:, None] * Kd
+    C = np.eye(n) - P @ np.linalg.solve(P.T @ Kd @ P, P.T @ Kd)
+    E = np.linalg.matrix_power(M, nu2) @ C @ np.linalg.matrix_power(M, nu1)
+    B = _dense_B(twogrid.TwoGrid(K, P, omega, nu1, nu2), n)
+    np.testing.assert_allclose(np.eye(n) - B @ Kd, E, atol=1e-11)
+
+
+@pytest.mark.parametrize("dim,N,k,omega", [(2, 4, 4, 2 / 3), (2, 6, 3, 2 / 3), (3, 2, 4, 0.5), (3, 3, 5, 0.5)])
+def test_preconditioner_spd_and_unit_eigenvalues(dim, N, k, omega):
+    w, K, P, U = _tiny(dim, N, k, omega)
+    n = K.shape[0]
+    B = _dense_B(twogrid.TwoGrid(K, P, omega), n)
+    assert np.abs(B - B.T).max() <= 1e-12 * np.abs(B).max()
+    assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0.0
+    ev = np.sort(np.linalg.eigvals(B @ K.toarray()).real)
+    assert ev[0] > 0.0 and ev[-1] <= 1.0 + 1e-10
+    # C annihilates span(P), so I - BK has rank <= n - k: >= k unit eigenvalues
+    assert np.sum(np.abs(ev - 1.0) < 1e-8) >= k
+
+
+def test_3d_two_thirds_damping_is_indefinite():
+    """Hex8 elasticity at nu = 0.3 has omega * lambda_max(D^-1 K) > 2 for
+    omega = 2/3: the two-grid preconditioner loses definiteness."""
+    w, K, P, U = _tiny(3, 2, 4, 2 / 3)
+    dinv = 1.0 / K.diagonal()
+    assert 2 / 3 * twogrid.power_lambda_max(K, dinv, iters=400) > 2.0
+    B = _dense_B(twogrid.TwoGrid(K, P, 2 / 3), K.shape[0])
+    assert np.linalg.eigvals(B @ K.toarray()).real.min() < 0.0
+
+
+def test_full_basis_gives_exact_inverse():
+    """k = n: P spans R^n, the coarse correction is exact and B = K^{-1} for
+    any smoother."""
+    w, K, P, U = _tiny(2, 3, 2, 2 / 3)
+    n = K.shape[0]
+    Q = np.linalg.qr(np.random.default_rng(2).standard_normal((n, n)))[0]
+    B = _dense_B(twogrid.TwoGrid(K, Q, 2 / 3), n)
+    np.testing.assert_allclose(B @ K.toarray(), np.eye(n), atol=1e-10)
+
+
+def test_basis_rotation_invariance():
+    """B depends on span(P) only (P -> P Q leaves K_c^{-1}-weighted projector
+    unchanged)."""
+    w, K, P, U = _tiny(2, 4, 4, 2 / 3)
+    Q = np.linalg.qr(np.random.default_rng(3).standard_normal((4, 4)))[0] * 3.0
+    r = np.random.default_rng(4).standard_normal(K.shape[0])
+    a = twogrid.TwoGrid(K, P, 2 / 3)(r)
+    b = twogrid.TwoGrid(K, P @ Q, 2 / 3)(r)
+    np.testing.assert_allclose(a, b, rtol=1e-10, atol=1e-14 * np.abs(a).max())
+
+
+def test_coarse_factor_not_spd():
+    w, K, P, U = _tiny(2, 4, 3, 2 / 3)
+    Pd = np.concatenate([P, np.zeros((P.shape[0], 1))], axis=1)   # zero pivot
+    with pytest.raises(twogrid.NotSPD):
+        twogrid.coarse_factor(K, Pd)
+
+
+def test_fp32_cycle_close_and_scale_exact():
+    w, K, P, U = _tiny(2, 8, 4, 2 / 3)
+    r = np.random.default_rng(5).standard_normal(K.shape[0])
+    s64 = twogrid.TwoGrid(K, P, 2 / 3)(r)
+    M32 = twogrid.TwoGrid(K, P, 2 / 3, precision="fp32")
+    s32 = M32(r)
+    assert np.linalg.norm(s32 - s64) / np.linalg.norm(s64) < 1e-5
+    # scaling by powers of two commutes with binary32 rounding
+    a = M32.apply(r, scale=1.0)
+    b = M32.apply(r, scale=2.0 ** -7)
+    c = M32.apply(r, scale=2.0 ** 11)
+    assert np.array_equal(a, b) and np.array_equal(a, c)
