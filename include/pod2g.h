@@ -1,0 +1,210 @@
+/*
+ * pod2g.h -- C ABI of the MI355X (gfx950) POD-2G preconditioned CG library.
+ *
+ * The method (Nikolopoulos, Kalogeris, Stavroulakis, Papadopoulos,
+ * "AI-enhanced iterative solvers for accelerating the solution of
+ * large-scale parametrized systems"):
+ *   - parametrised SPD finite-element systems K(theta) u = f   (Sec. 2.1, Eq. 6)
+ *   - a POD basis P = Phi_r of training solutions               (Sec. 3.3, Eq. 26)
+ *   - a two-grid cycle with P as prolongation, P^T as restriction,
+ *     damped-Jacobi relaxation and a Galerkin coarse solve       (Sec. 2.2 Alg. 2, Eq. 30)
+ *   - PCG preconditioned by one such cycle per iteration, warm-started
+ *     from a surrogate prediction                               (Sec. 3.4 Alg. 3)
+ *
+ * Conventions (all entry points):
+ *   - Array arguments are DEVICE pointers owned by the caller unless the
+ *     name ends in _h (host).  The library never allocates device memory:
+ *     every call that needs scratch space has a *_bytes() query and takes a
+ *     caller-provided device workspace of at least that size (256-byte
+ *     aligned).  Workspace contents are private to the library between the
+ *     calls that share it (a pod2g_prec lives in its setup workspace).
+ *   - Every call is ordered on the given HIP stream.  Calls documented as
+ *     synchronous block until their stream work is done; the others are
+ *     asynchronous.  Host out-parameters are written only by synchronous calls.
+ *   - Every function returns an int status: 0 = POD2G_OK, negative = error.
+ *     pod2g_strerror() gives a message.  No exception crosses the ABI.
+ *   - No global mutable state: handles are plain structs that the caller
+ *     owns; different handles may be used concurrently on different streams.
+ *   - Vectors of one instance have n entries in the DOF numbering below;
+ *     batched vectors are [batch][n], contiguous per instance.
+ *
+ * Problem family (synthetic stand-ins for the paper's Sec. 4 problems):
+ *   dim = 2: plane-stress bilinear Q4 elements, unit square, N x N mesh,
+ *            edge x = 0 clamped, unit traction +x on edge x = 1.
+ *   dim = 3: isotropic trilinear Hex8 elements (Lame constants of Sec. 4.1),
+ *            unit cube, N^3 mesh, face z = 0 clamped, unit traction +z on z = 1.
+ *   Young's modulus per element, at the centroid c:
+ *     E = exp(kl_scale * sum_t xi_t prod_d cos(pi a_td c_d) / (1 + sum_d a_td))
+ *   with a_t the t-th multi-index of {0..3}^dim \ {0} in lexicographic order
+ *   (x most significant).  Dirichlet conditions by elimination.
+ *   DOF numbering: free node (i,j[,l]) has rank (i-1) + N j in 2D and
+ *   i + (N+1) j + (N+1)^2 (l-1) in 3D; DOF = dim * rank + component.
+ *
+ * Matrix layout (block-ELL, one slot per neighbour offset in {-1,0,1}^dim,
+ * slot s = (dx+1) + 3 (dy+1) [+ 9 (dz+1)]):
+ *   colblk[s * n_nodes + node] = free-node rank of the neighbour, or the
+ *     node itself for an absent neighbour (its values are zero);
+ *   vals[(s * dim + b) * n + row] = K(row, dim * colblk[s][row / dim] + b).
+ *   nvals = n * n_slots * dim values per instance; batched values are
+ *   [batch][nvals].
+ * P is n x k column-major (column j at P + j * n), shared by all instances.
+ */
+#ifndef POD2G_H
+#define POD2G_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define POD2G_OK          0
+#define POD2G_EINVAL     -1   /* bad argument (size, null pointer, range)   */
+#define POD2G_ESIZE      -2   /* workspace smaller than the *_bytes query    */
+#define POD2G_EHIP       -3   /* a HIP runtime call failed                   */
+#define POD2G_ENOTSPD    -4   /* coarse matrix P^T K P: pivot <= 0           */
+#define POD2G_ESMOOTHER  -5   /* omega * lambda_max(D^-1 K) >= 2 (estimate)  */
+#define POD2G_EMAXIT     -6   /* iteration limit reached                     */
+#define POD2G_EBREAKDOWN -7   /* p^T K p <= 0 or r^T s <= 0                   */
+#define POD2G_ENAN       -8   /* non-finite residual or coefficient          */
+
+#define POD2G_FP64   0        /* preconditioner in FP64                      */
+#define POD2G_MIXED  1        /* preconditioner in FP32, outer PCG in FP64   */
+
+#define POD2G_BETA_FR 0       /* beta = r_{k+1}^T s_{k+1} / r_k^T s_k (Alg. 3) */
+#define POD2G_BETA_PR 1       /* flexible Polak-Ribiere:
+                                 (r_{k+1}^T s_{k+1} - r_{k+1}^T s_k) / r_k^T s_k */
+
+#define POD2G_MAX_K 64        /* largest coarse size k                       */
+
+typedef struct pod2g_mesh {
+  int dim;          /* 2 or 3 */
+  int N;            /* elements per side, >= 1 */
+  int n_terms;      /* length of xi per instance, 1..(4^dim - 1) */
+  double nu;        /* Poisson ratio, 0 <= nu < 0.5 */
+  double kl_scale;  /* amplitude of the log-modulus field (0.3) */
+} pod2g_mesh;
+
+typedef struct pod2g_pattern {
+  pod2g_mesh mesh;
+  int n_nodes;      /* free nodes */
+  int n;            /* free DOFs = dim * n_nodes */
+  int n_slots;      /* 3^dim */
+  int n_elems;      /* N^dim */
+  long long nvals;  /* stored values per instance = n * n_slots * dim */
+  int *colblk;      /* device [n_slots][n_nodes], inside the pattern buffer */
+  double *kref;     /* device unit-modulus element matrix, (dim 2^dim)^2,
+                       row-major, element DOF dim * l + c, l = lx + 2ly + 4lz */
+} pod2g_pattern;
+
+typedef struct pod2g_prec {
+  pod2g_pattern pat;
+  int batch, k, nu_pre, nu_post, precision;
+  double omega;
+  const double *vals;   /* [batch][nvals] FP64 K (caller's) */
+  const float *vals32;  /* [batch][nvals] FP32 K (caller's; MIXED only) */
+  const double *dinv;   /* [batch][n] FP64 D^-1 (caller's) */
+  const double *P;      /* [k][n] FP64 basis (caller's) */
+  float *P32;           /* [k][n] (MIXED), in the setup workspace */
+  float *dinv32;        /* [batch][n] (MIXED), in the setup workspace */
+  double *KP;           /* [batch][k][n] K P, in the setup workspace */
+  double *L;            /* [batch][k][k] row-major lower Cholesky factor of P^T K P */
+  double *lam;          /* [batch] power-iteration estimate of lambda_max(D^-1 K) */
+  int *status;          /* [batch] per-instance setup status (device) */
+} pod2g_prec;
+
+const char *pod2g_strerror(int status);
+
+/* ---- pattern ------------------------------------------------------------
+ * Builds the free-DOF map, the block-ELL column indices and the unit-modulus
+ * element matrix (2^dim-point Gauss quadrature) of Sec. 2.1 Eq. 5.
+ * dbuf: device buffer of pod2g_pattern_bytes(mesh) bytes that holds colblk
+ * and kref for the lifetime of *out.  Asynchronous.
+ * Errors: EINVAL (mesh out of range, n >= 2^31 / 81), ESIZE.                */
+size_t pod2g_pattern_bytes(const pod2g_mesh *mesh);
+int pod2g_pattern_build(const pod2g_mesh *mesh, void *dbuf, size_t bytes,
+                        pod2g_pattern *out, hipStream_t stream);
+
+/* ---- assembly (Sec. 2.1, Eqs. 5-6) ---------------------------------------
+ * For each of `batch` instances b with field coefficients xi[b * n_terms ..]
+ * (device, FP64): element moduli E_e, then every stored value of
+ * K = sum_e E_e A_e^T K_ref A_e restricted to free DOFs, gathered per stored
+ * entry (deterministic, no atomics); D^-1 = 1/diag(K).  Optional outputs may
+ * be NULL: vals32 (FP32 copy of vals, RNE), f (the load vector, [n], the
+ * same for every instance).  Asynchronous.  Errors: EINVAL, ESIZE.          */
+size_t pod2g_assemble_bytes(const pod2g_pattern *pat, int batch);
+int pod2g_assemble(const pod2g_pattern *pat, const double *xi, int batch,
+                   double *vals, float *vals32, double *dinv, double *f,
+                   void *work, size_t bytes, hipStream_t stream);
+
+/* ---- preconditioner setup (Alg. 2 restrict-and-solve step, Eq. 28) -------
+ * Per instance: KP = K P, K_c = P^T (K P) (k x k), its FP64 Cholesky factor
+ * L (pivot <= 0 -> POD2G_ENOTSPD in status[b]); with power_iters > 0 also a
+ * power-iteration estimate of lambda_max(D^-1 K) from the all-ones vector
+ * (omega * lambda >= 2 -> POD2G_ESMOOTHER).  MIXED also makes FP32 copies of
+ * P and D^-1.  k = 0 gives the smoother-only cycle.  vals32 may be NULL for
+ * FP64.  The handle *out points into work, which must outlive it.
+ * Asynchronous: per-instance errors land in out->status and are reported by
+ * pcg_solve / pod2g_setup_status.  Returns EINVAL/ESIZE/EHIP synchronously. */
+size_t pod2g_setup_bytes(const pod2g_pattern *pat, int k, int batch, int precision);
+int pod2g_setup(const pod2g_pattern *pat, const double *vals, const float *vals32,
+                const double *dinv, const double *P, int k, double omega,
+                int nu_pre, int nu_post, int precision, int batch, int power_iters,
+                void *work, size_t bytes, pod2g_prec *out, hipStream_t stream);
+/* Synchronous: copies the per-instance setup status (and, if lam_h is not
+ * NULL, the lambda_max estimates) to host arrays of length batch.          */
+int pod2g_setup_status(const pod2g_prec *prec, int *status_h, double *lam_h,
+                       hipStream_t stream);
+
+/* ---- one two-grid cycle (Alg. 3 preconditioning steps; Alg. 2 body) -------
+ * s = B r for every instance: nu_pre damped-Jacobi sweeps from x = 0,
+ * r' = r - K x, r_c = P^T r', L L^T e_c = r_c, x += P e_c, nu_post sweeps.
+ * r, s: [batch][n].  Asynchronous.                                          */
+size_t pod2g_apply_bytes(const pod2g_prec *prec);
+int pod2g_apply(const pod2g_prec *prec, const double *r, double *s,
+                void *work, size_t bytes, hipStream_t stream);
+
+/* ---- PCG (Sec. 3.4 Alg. 3; Sec. 2.1 Alg. 1 when prec == NULL) ------------
+ * Solves K_b u_b = f for b < batch from the initial guesses in u (overwritten
+ * by the solutions).  Stops when ||r|| <= rtol ||f|| on the recursive
+ * residual, then checks the true residual f - K u; on a gap the true residual
+ * replaces r and CG restarts from it.  maxit bounds the completed updates.
+ * beta: POD2G_BETA_FR or POD2G_BETA_PR.  f: [n] shared by all instances.
+ * Synchronous.  Host outputs (length batch, each may be NULL): iters_h =
+ * completed iterations, relres_h = true ||f - K u|| / ||f|| at exit,
+ * status_h = per-instance status.  Returns POD2G_OK if every instance
+ * converged, else the first failing instance's status.                     */
+size_t pcg_solve_bytes(const pod2g_pattern *pat, int batch, int k, int precision);
+int pcg_solve(const pod2g_pattern *pat, const double *vals, int batch,
+              const pod2g_prec *prec, const double *f, double *u,
+              double rtol, int maxit, int beta,
+              int *iters_h, double *relres_h, int *status_h,
+              void *work, size_t bytes, hipStream_t stream);
+
+/* ---- single kernels (measurement and parity checks) ---------------------
+ * y_b = K_b x_b (FP64).  Asynchronous.                                      */
+int pod2g_spmv(const pod2g_pattern *pat, const double *vals, int batch,
+               const double *x, double *y, hipStream_t stream);
+/* nsweeps damped-Jacobi sweeps x <- x + omega D^-1 (b - K x) (the relaxation
+ * of Alg. 2) in place on x, using tmp ([batch][n]) as the second buffer.
+ * Asynchronous.                                                              */
+int pod2g_jacobi(const pod2g_pattern *pat, const double *vals, const double *dinv,
+                 int batch, double omega, int nsweeps, const double *b, double *x,
+                 double *tmp, hipStream_t stream);
+
+/* ---- offline POD (Sec. 3.3, steps 1-2) ----------------------------------
+ * From N snapshots U ([N][n], one solution per row block), the Gram matrix
+ * G = U^T U, its eigenpairs by cyclic Jacobi rotations, and
+ * P = U Psi_k Lambda_k^{-1/2} (Eq. 26) with the k largest eigenvalues.
+ * lam: [N] all eigenvalues, descending (device).  N <= 256, k <= min(N, 64).
+ * Rank below k (lambda_k <= N eps lambda_1) -> POD2G_EINVAL.  Synchronous.  */
+size_t pod2g_pod_basis_bytes(int n, int N, int k);
+int pod2g_pod_basis(const double *U, int n, int N, int k, double *P, double *lam,
+                    void *work, size_t bytes, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* POD2G_H */

@@ -1,0 +1,200 @@
+"""Thin ctypes binding of ``libpod2g.so`` (declared in ``include/pod2g.h``).
+
+Argument marshalling only: every function has the C entry point's name and
+argument order, takes torch tensors (or raw ints) for device pointers and
+returns the C status (or raises ``Pod2gError`` where noted).  All compute
+runs in the library's HIP kernels.  If the library is not built the import
+of this module fails loudly -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpod2g.so")
+
+OK, EINVAL, ESIZE, EHIP, ENOTSPD, ESMOOTHER, EMAXIT, EBREAKDOWN, ENAN = 0, -1, -2, -3, -4, -5, -6, -7, -8
+FP64, MIXED = 0, 1
+BETA_FR, BETA_PR = 0, 1
+MAX_K = 64
+
+
+class Pod2gError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        super().__init__(f"{where}: {strerror(status)} ({status})")
+
+
+class Mesh(C.Structure):
+    _fields_ = [("dim", C.c_int), ("N", C.c_int), ("n_terms", C.c_int),
+                ("nu", C.c_double), ("kl_scale", C.c_double)]
+
+
+class Pattern(C.Structure):
+    _fields_ = [("mesh", Mesh), ("n_nodes", C.c_int), ("n", C.c_int), ("n_slots", C.c_int),
+                ("n_elems", C.c_int), ("nvals", C.c_longlong),
+                ("colblk", C.c_void_p), ("kref", C.c_void_p)]
+
+
+class Prec(C.Structure):
+    _fields_ = [("pat", Pattern), ("batch", C.c_int), ("k", C.c_int), ("nu_pre", C.c_int),
+                ("nu_post", C.c_int), ("precision", C.c_int), ("omega", C.c_double),
+                ("vals", C.c_void_p), ("vals32", C.c_void_p), ("dinv", C.c_void_p),
+                ("P", C.c_void_p), ("P32", C.c_void_p), ("dinv32", C.c_void_p),
+                ("KP", C.c_void_p), ("L", C.c_void_p), ("lam", C.c_void_p),
+                ("status", C.c_void_p)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                      "(the HIP library is required; there is no CPU path)")
+_lib = C.CDLL(LIB_PATH)
+
+_vp, _i, _d, _sz = C.c_void_p, C.c_int, C.c_double, C.c_size_t
+_PM, _PP, _PR = C.POINTER(Mesh), C.POINTER(Pattern), C.POINTER(Prec)
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_f = {
+    "pod2g_strerror": _sig("pod2g_strerror", C.c_char_p, [_i]),
+    "pod2g_pattern_bytes": _sig("pod2g_pattern_bytes", _sz, [_PM]),
+    "pod2g_pattern_build": _sig("pod2g_pattern_build", _i, [_PM, _vp, _sz, _PP, _vp]),
+    "pod2g_assemble_bytes": _sig("pod2g_assemble_bytes", _sz, [_PP, _i]),
+    "pod2g_assemble": _sig("pod2g_assemble", _i, [_PP, _vp, _i, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "pod2g_setup_bytes": _sig("pod2g_setup_bytes", _sz, [_PP, _i, _i, _i]),
+    "pod2g_setup": _sig("pod2g_setup", _i, [_PP, _vp, _vp, _vp, _vp, _i, _d, _i, _i, _i, _i, _i,
+                                            _vp, _sz, _PR, _vp]),
+    "pod2g_setup_status": _sig("pod2g_setup_status", _i, [_PR, C.POINTER(_i), C.POINTER(_d), _vp]),
+    "pod2g_apply_bytes": _sig("pod2g_apply_bytes", _sz, [_PR]),
+    "pod2g_apply": _sig("pod2g_apply", _i, [_PR, _vp, _vp, _vp, _sz, _vp]),
+    "pcg_solve_bytes": _sig("pcg_solve_bytes", _sz, [_PP, _i, _i, _i]),
+    "pcg_solve": _sig("pcg_solve", _i, [_PP, _vp, _i, _PR, _vp, _vp, _d, _i, _i, C.POINTER(_i),
+                                        C.POINTER(_d), C.POINTER(_i), _vp, _sz, _vp]),
+    "pod2g_spmv": _sig("pod2g_spmv", _i, [_PP, _vp, _i, _vp, _vp, _vp]),
+    "pod2g_jacobi": _sig("pod2g_jacobi", _i, [_PP, _vp, _vp, _i, _d, _i, _vp, _vp, _vp, _vp]),
+    "pod2g_pod_basis_bytes": _sig("pod2g_pod_basis_bytes", _sz, [_i, _i, _i]),
+    "pod2g_pod_basis": _sig("pod2g_pod_basis", _i, [_vp, _i, _i, _i, _vp, _vp, _vp, _sz, _vp]),
+}
+
+
+def exported_symbols():
+    return sorted(_f)
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def strerror(status: int) -> str:
+    return _f["pod2g_strerror"](int(status)).decode()
+
+
+def check(status: int, where: str = ""):
+    if status != OK:
+        raise Pod2gError(status, where)
+    return status
+
+
+# ---- pattern --------------------------------------------------------------
+def make_mesh(dim, N, n_terms, nu=0.3, kl_scale=0.3) -> Mesh:
+    return Mesh(dim, N, n_terms, nu, kl_scale)
+
+
+def pod2g_pattern_bytes(mesh: Mesh) -> int:
+    return _f["pod2g_pattern_bytes"](C.byref(mesh))
+
+
+def pod2g_pattern_build(mesh: Mesh, dbuf, nbytes: int, out: Pattern, stream=None) -> int:
+    return _f["pod2g_pattern_build"](C.byref(mesh), _ptr(dbuf), nbytes, C.byref(out), _stream(stream))
+
+
+# ---- assembly -------------------------------------------------------------
+def pod2g_assemble_bytes(pat: Pattern, batch: int) -> int:
+    return _f["pod2g_assemble_bytes"](C.byref(pat), batch)
+
+
+def pod2g_assemble(pat: Pattern, xi, batch, vals, vals32, dinv, f, work, nbytes, stream=None) -> int:
+    return _f["pod2g_assemble"](C.byref(pat), _ptr(xi), batch, _ptr(vals), _ptr(vals32), _ptr(dinv),
+                                _ptr(f), _ptr(work), nbytes, _stream(stream))
+
+
+# ---- setup ----------------------------------------------------------------
+def pod2g_setup_bytes(pat: Pattern, k: int, batch: int, precision: int) -> int:
+    return _f["pod2g_setup_bytes"](C.byref(pat), k, batch, precision)
+
+
+def pod2g_setup(pat, vals, vals32, dinv, P, k, omega, nu_pre, nu_post, precision, batch,
+                power_iters, work, nbytes, out: Prec, stream=None) -> int:
+    return _f["pod2g_setup"](C.byref(pat), _ptr(vals), _ptr(vals32), _ptr(dinv), _ptr(P), k,
+                             float(omega), nu_pre, nu_post, precision, batch, power_iters,
+                             _ptr(work), nbytes, C.byref(out), _stream(stream))
+
+
+def pod2g_setup_status(prec: Prec, stream=None):
+    st = (C.c_int * prec.batch)()
+    lam = (C.c_double * prec.batch)()
+    check(_f["pod2g_setup_status"](C.byref(prec), st, lam, _stream(stream)), "pod2g_setup_status")
+    return list(st), list(lam)
+
+
+# ---- cycle / solve ----------------------------------------------------------
+def pod2g_apply_bytes(prec: Prec) -> int:
+    return _f["pod2g_apply_bytes"](C.byref(prec))
+
+
+def pod2g_apply(prec: Prec, r, s, work, nbytes, stream=None) -> int:
+    return _f["pod2g_apply"](C.byref(prec), _ptr(r), _ptr(s), _ptr(work), nbytes, _stream(stream))
+
+
+def pcg_solve_bytes(pat: Pattern, batch: int, k: int, precision: int) -> int:
+    return _f["pcg_solve_bytes"](C.byref(pat), batch, k, precision)
+
+
+def pcg_solve(pat, vals, batch, prec, f, u, rtol, maxit, beta, work, nbytes, stream=None):
+    """Returns (status, iters[batch], relres[batch], status[batch])."""
+    it = (C.c_int * batch)()
+    rr = (C.c_double * batch)()
+    st = (C.c_int * batch)()
+    ret = _f["pcg_solve"](C.byref(pat), _ptr(vals), batch, C.byref(prec) if prec is not None else None,
+                          _ptr(f), _ptr(u), float(rtol), int(maxit), int(beta), it, rr, st,
+                          _ptr(work), nbytes, _stream(stream))
+    return ret, list(it), list(rr), list(st)
+
+
+def pod2g_spmv(pat, vals, batch, x, y, stream=None) -> int:
+    return _f["pod2g_spmv"](C.byref(pat), _ptr(vals), batch, _ptr(x), _ptr(y), _stream(stream))
+
+
+def pod2g_jacobi(pat, vals, dinv, batch, omega, nsweeps, b, x, tmp, stream=None) -> int:
+    return _f["pod2g_jacobi"](C.byref(pat), _ptr(vals), _ptr(dinv), batch, float(omega), nsweeps,
+                              _ptr(b), _ptr(x), _ptr(tmp), _stream(stream))
+
+
+# ---- offline POD ----------------------------------------------------------
+def pod2g_pod_basis_bytes(n, N, k) -> int:
+    return _f["pod2g_pod_basis_bytes"](n, N, k)
+
+
+def pod2g_pod_basis(U, n, N, k, P, lam, work, nbytes, stream=None) -> int:
+    return _f["pod2g_pod_basis"](_ptr(U), n, N, k, _ptr(P), _ptr(lam), _ptr(work), nbytes,
+                                 _stream(stream))

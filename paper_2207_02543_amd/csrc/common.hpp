@@ -1,0 +1,142 @@
+// Shared device helpers of the POD-2G library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pod2g.h"
+
+namespace pod2g {
+
+constexpr int NT = 256;          // threads per workgroup of the row kernels
+constexpr int WAVE = 64;
+constexpr int NWAVE = NT / WAVE;
+constexpr int MAXK = POD2G_MAX_K;
+
+// Per-instance solver state (one cache line pair, device memory).
+struct alignas(128) InstState {
+  double rho;      // r^T s of the current iterate
+  double gamma;    // p^T K p
+  double alpha, beta;
+  double rr;       // ||r||^2 (recursive residual)
+  double ff;       // ||f||^2
+  double tol2;     // (rtol ||f||)^2
+  double rs_prev;  // r_{k+1}^T s_k (flexible beta)
+  double rr_true;  // ||f - K u||^2 at the last true-residual check
+  double xnorm2;   // power iteration: ||x||^2
+  double scale;    // power-of-two scale of the FP32 cycle input
+  double pad0;
+  int iter, maxit, done, status;
+  int restart;     // next beta is forced to 0
+  int beta_kind;
+  int pad1, pad2;
+  unsigned cnt[8]; // last-workgroup counters, one per reduction site
+};
+
+enum CounterSlot { CNT_A = 0, CNT_B = 1, CNT_C = 2, CNT_D = 3, CNT_E = 4 };
+
+// Blocks are handed to the 8 XCDs round-robin; map them so that every XCD
+// works on one contiguous range of rows (its L2 then holds that range's
+// neighbourhood of the gathered vector).  A bijection for any nblocks.
+__device__ __forceinline__ int xcd_block(int bid, int nblocks) {
+  const int q = nblocks >> 3, rem = nblocks & 7;
+  const int x = bid & 7, idx = bid >> 3;
+  return x * q + (x < rem ? x : rem) + idx;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+  return v;
+}
+
+// Sum over the workgroup in a fixed order; result valid on thread 0.
+__device__ __forceinline__ double block_sum(double v, double *lds /*[NWAVE]*/) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / WAVE;
+  if ((threadIdx.x & (WAVE - 1)) == 0) lds[w] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NWAVE; ++i) t += lds[i];
+  }
+  __syncthreads();
+  return t;
+}
+
+// Two sums at once (one pass of barriers).
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *lds /*[2*NWAVE]*/) {
+  a = wave_sum(a);
+  b = wave_sum(b);
+  const int w = threadIdx.x / WAVE;
+  if ((threadIdx.x & (WAVE - 1)) == 0) { lds[w] = a; lds[NWAVE + w] = b; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double ta = 0.0, tb = 0.0;
+#pragma unroll
+    for (int i = 0; i < NWAVE; ++i) { ta += lds[i]; tb += lds[NWAVE + i]; }
+    a = ta; b = tb;
+  }
+  __syncthreads();
+}
+
+// Release this workgroup's partial results and report whether it is the
+// last of `total` workgroups to arrive at `counter`; the last one resets
+// the counter and may then read every partial (acquire).
+__device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned total, int *lds_flag) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(counter, 1u);
+    const int last = (prev == total - 1u);
+    if (last) *counter = 0u;
+    *lds_flag = last;
+  }
+  __syncthreads();
+  const bool last = *lds_flag != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+// Deterministic sum of m partials (strided by `stride` doubles) by one
+// workgroup: fixed per-thread order, then the fixed block tree.
+__device__ __forceinline__ double reduce_partials(const double *part, int m, int stride,
+                                                  double *lds) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < m; i += NT) v += part[(size_t)i * stride];
+  return block_sum(v, lds);
+}
+
+__device__ __forceinline__ bool finite(double x) { return x - x == 0.0; }
+
+template <int DIM> struct Stencil {
+  static constexpr int S = DIM == 2 ? 9 : 27;   // block slots per node
+  static constexpr int NE = DIM == 2 ? 4 : 8;   // nodes per element
+  static constexpr int ED = DIM * NE;           // element DOFs
+};
+
+// (K x)_row for the block-ELL layout; x is gathered at the neighbour DOFs.
+template <int DIM, typename T, typename XT>
+__device__ __forceinline__ T row_dot(const int *__restrict__ colblk, const T *__restrict__ vals,
+                                     const XT *__restrict__ x, int row, int node, int n, int nn) {
+  constexpr int S = Stencil<DIM>::S;
+  T acc = T(0);
+#pragma unroll 9
+  for (int s = 0; s < S; ++s) {
+    const int c = colblk[s * nn + node];
+#pragma unroll
+    for (int b = 0; b < DIM; ++b)
+      acc += vals[(size_t)(s * DIM + b) * n + row] * (T)x[c * DIM + b];
+  }
+  return acc;
+}
+
+inline int ceil_div(long long a, int b) { return (int)((a + b - 1) / b); }
+
+}  // namespace pod2g
+
+#define POD2G_HIP_CHECK(expr)                  \
+  do {                                         \
+    if ((expr) != hipSuccess) return POD2G_EHIP; \
+  } while (0)

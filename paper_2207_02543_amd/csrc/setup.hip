@@ -1,0 +1,339 @@
+// Preconditioner setup: K P, the Galerkin coarse matrix K_c = P^T K P
+// (Sec. 2.2 Alg. 2 restrict-and-solve step; Sec. 3.3 Eq. 28), its FP64
+// Cholesky factor, FP32 copies for the mixed cycle, and a power-iteration
+// estimate of lambda_max(D^-1 K) (damped-Jacobi stability guard).
+#include "common.hpp"
+
+#include <math.h>
+#include <string.h>
+
+namespace pod2g {
+
+constexpr int KP_CH = 8;   // columns of K P per pass over K
+constexpr int KC_TR = 64;  // rows per LDS tile of the coarse-matrix kernel
+
+struct SetupLayout {
+  size_t status, lam, pst, kp, L, kcpart, ppart, p32, d32, pw, total;
+  int nbk, rows_per_wg;
+};
+
+static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static SetupLayout setup_layout(int n, int k, int batch, int precision) {
+  SetupLayout S;
+  int rpt = n / (NT * 1024);
+  if (rpt < 1) rpt = 1;
+  S.rows_per_wg = NT * rpt;
+  S.nbk = ceil_div(n, S.rows_per_wg);
+  const size_t ntri = (size_t)k * (k + 1) / 2;
+  size_t o = 0;
+  S.status = o; o += align256(sizeof(int) * batch);
+  S.lam = o;    o += align256(sizeof(double) * batch);
+  S.pst = o;    o += align256(sizeof(InstState) * batch);
+  S.kp = o;     o += align256(sizeof(double) * (size_t)batch * k * n);
+  S.L = o;      o += align256(sizeof(double) * (size_t)batch * k * k);
+  S.kcpart = o; o += align256(sizeof(double) * (size_t)batch * S.nbk * (ntri > 0 ? ntri : 1));
+  S.ppart = o;  o += align256(sizeof(double) * (size_t)batch * ceil_div(n, NT));
+  S.p32 = o;    if (precision == POD2G_MIXED) o += align256(sizeof(float) * (size_t)k * n);
+  S.d32 = o;    if (precision == POD2G_MIXED) o += align256(sizeof(float) * (size_t)batch * n);
+  S.pw = o;     o += 2 * align256(sizeof(double) * (size_t)batch * n);
+  S.total = o;
+  return S;
+}
+
+__global__ void k_setup_init(InstState *pst, int *status, double *lam, int batch, int n) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  InstState s;
+  memset(&s, 0, sizeof(s));
+  s.xnorm2 = (double)n;
+  pst[b] = s;
+  status[b] = POD2G_OK;
+  lam[b] = 0.0;
+}
+
+// KP[:, j0 .. j0 + KP_CH) = K P[:, j0 ..] for one instance per grid row.
+template <int DIM>
+__global__ void __launch_bounds__(NT) k_kp(int n, int nn, int k, long long vstride,
+                                           const int *__restrict__ colblk,
+                                           const double *__restrict__ vals,
+                                           const double *__restrict__ P, double *__restrict__ KP) {
+  const int b = blockIdx.y;
+  const int row = xcd_block(blockIdx.x, gridDim.x) * NT + threadIdx.x;
+  const int j0 = blockIdx.z * KP_CH;
+  if (row >= n) return;
+  const int node = row / DIM;
+  const double *v = vals + (size_t)b * vstride;
+  double acc[KP_CH];
+#pragma unroll
+  for (int jj = 0; jj < KP_CH; ++jj) acc[jj] = 0.0;
+  const int jn = k - j0 < KP_CH ? k - j0 : KP_CH;
+  for (int s = 0; s < Stencil<DIM>::S; ++s) {
+    const int c = colblk[s * nn + node];
+#pragma unroll
+    for (int bc = 0; bc < DIM; ++bc) {
+      const double a = v[(size_t)(s * DIM + bc) * n + row];
+      const int col = c * DIM + bc;
+#pragma unroll
+      for (int jj = 0; jj < KP_CH; ++jj)
+        if (jj < jn) acc[jj] += a * P[(size_t)(j0 + jj) * n + col];
+    }
+  }
+  double *out = KP + (size_t)b * k * n;
+#pragma unroll
+  for (int jj = 0; jj < KP_CH; ++jj)
+    if (jj < jn) out[(size_t)(j0 + jj) * n + row] = acc[jj];
+}
+
+__device__ __forceinline__ void tri_index(int e, int &j, int &l) {
+  // e = j (j + 1) / 2 + l, 0 <= l <= j
+  int jj = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+  while (jj * (jj + 1) / 2 > e) --jj;
+  while ((jj + 1) * (jj + 2) / 2 <= e) ++jj;
+  j = jj;
+  l = e - jj * (jj + 1) / 2;
+}
+
+// Lower triangle of K_c = P^T (K P): per-workgroup partial sums over a row
+// range; the last workgroup of an instance sums them (fixed order) and
+// factors K_c = L L^T in LDS.
+__global__ void __launch_bounds__(NT) k_kc(int n, int k, int rows_per_wg, int nbk,
+                                           const double *__restrict__ P,
+                                           const double *__restrict__ KP, double *__restrict__ part,
+                                           double *__restrict__ Lout, int *__restrict__ status,
+                                           InstState *pst) {
+  constexpr int MAXE = (MAXK * (MAXK + 1) / 2 + NT - 1) / NT;
+  __shared__ double sp[MAXK * KC_TR];
+  __shared__ double skp[MAXK * KC_TR];
+  __shared__ int flag;
+  __shared__ int fail;
+  const int b = blockIdx.y, wg = blockIdx.x;
+  const int ntri = k * (k + 1) / 2;
+  const double *KPb = KP + (size_t)b * k * n;
+  int ej[MAXE], el[MAXE];
+  double acc[MAXE];
+#pragma unroll
+  for (int m = 0; m < MAXE; ++m) {
+    acc[m] = 0.0;
+    const int e = threadIdx.x + m * NT;
+    if (e < ntri) tri_index(e, ej[m], el[m]);
+    else { ej[m] = 0; el[m] = 0; }
+  }
+  const int r_begin = wg * rows_per_wg;
+  const int r_end = r_begin + rows_per_wg < n ? r_begin + rows_per_wg : n;
+  for (int r0 = r_begin; r0 < r_end; r0 += KC_TR) {
+    for (int t = threadIdx.x; t < k * KC_TR; t += NT) {
+      const int j = t / KC_TR, rr = r0 + t % KC_TR;
+      sp[t] = rr < r_end ? P[(size_t)j * n + rr] : 0.0;
+      skp[t] = rr < r_end ? KPb[(size_t)j * n + rr] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MAXE; ++m) {
+      if (threadIdx.x + m * NT < ntri) {
+        const double *a = sp + ej[m] * KC_TR, *c = skp + el[m] * KC_TR;
+        double s = 0.0;
+        for (int rr = 0; rr < KC_TR; ++rr) s += a[rr] * c[rr];
+        acc[m] += s;
+      }
+    }
+    __syncthreads();
+  }
+  double *pb = part + (size_t)b * nbk * ntri;
+#pragma unroll
+  for (int m = 0; m < MAXE; ++m) {
+    const int e = threadIdx.x + m * NT;
+    if (e < ntri) pb[(size_t)wg * ntri + e] = acc[m];
+  }
+  if (!arrive_last(&pst[b].cnt[CNT_A], nbk, &flag)) return;
+  // K_c into LDS (full symmetric), then Cholesky
+  double *A = sp;  // k x k, row-major
+  for (int e = threadIdx.x; e < ntri; e += NT) {
+    double s = 0.0;
+    for (int w = 0; w < nbk; ++w) s += pb[(size_t)w * ntri + e];
+    int j, l;
+    tri_index(e, j, l);
+    A[j * k + l] = s;
+    A[l * k + j] = s;
+  }
+  if (threadIdx.x == 0) fail = 0;
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (threadIdx.x == 0) {
+      const double d = A[j * k + j];
+      if (!(d > 0.0)) fail = 1;
+      A[j * k + j] = d > 0.0 ? sqrt(d) : 1.0;
+    }
+    __syncthreads();
+    const double d = A[j * k + j];
+    for (int i = j + 1 + threadIdx.x; i < k; i += NT) A[i * k + j] /= d;
+    __syncthreads();
+    const int m = k - j - 1;
+    for (int t = threadIdx.x; t < m * m; t += NT) {
+      const int i = j + 1 + t / m, l = j + 1 + t % m;
+      if (l <= i) A[i * k + l] -= A[i * k + j] * A[l * k + j];
+    }
+    __syncthreads();
+  }
+  double *Lb = Lout + (size_t)b * k * k;
+  for (int t = threadIdx.x; t < k * k; t += NT) {
+    const int i = t / k, l = t % k;
+    Lb[t] = l <= i ? A[t] : 0.0;
+  }
+  if (threadIdx.x == 0 && fail) status[b] = POD2G_ENOTSPD;
+}
+
+__global__ void __launch_bounds__(NT) k_to_f32(size_t count, const double *__restrict__ a,
+                                               float *__restrict__ o) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < count; i += (size_t)gridDim.x * NT)
+    o[i] = (float)a[i];
+}
+
+__global__ void __launch_bounds__(NT) k_fill(size_t count, double v, double *__restrict__ o) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < count; i += (size_t)gridDim.x * NT)
+    o[i] = v;
+}
+
+// y = D^-1 K x / ||x||, ||y||^2; last block: lambda estimate = ||y||.
+template <int DIM>
+__global__ void __launch_bounds__(NT) k_power(int n, int nn, int nb, long long vstride,
+                                              const int *__restrict__ colblk,
+                                              const double *__restrict__ vals,
+                                              const double *__restrict__ dinv,
+                                              const double *__restrict__ x, double *__restrict__ y,
+                                              double *__restrict__ part, InstState *pst,
+                                              double *lam) {
+  __shared__ double lds[NWAVE];
+  __shared__ int flag;
+  const int b = blockIdx.y;
+  const int blk = xcd_block(blockIdx.x, nb);
+  const int row = blk * NT + threadIdx.x;
+  const size_t off = (size_t)b * n;
+  const double inv = 1.0 / sqrt(pst[b].xnorm2);
+  double yy = 0.0;
+  if (row < n) {
+    const double kx = row_dot<DIM>(colblk, vals + (size_t)b * vstride, x + off, row, row / DIM, n, nn);
+    const double v = dinv[off + row] * kx * inv;
+    y[off + row] = v;
+    yy = v * v;
+  }
+  yy = block_sum(yy, lds);
+  if (threadIdx.x == 0) part[(size_t)b * nb + blk] = yy;
+  if (!arrive_last(&pst[b].cnt[CNT_B], nb, &flag)) return;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += NT) s += part[(size_t)b * nb + i];
+  s = block_sum(s, lds);
+  if (threadIdx.x == 0) {
+    pst[b].xnorm2 = s;
+    lam[b] = sqrt(s);
+  }
+}
+
+__global__ void k_smoother_guard(int batch, double omega, const double *lam, int *status) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  if (status[b] == POD2G_OK && !(omega * lam[b] < 2.0)) status[b] = POD2G_ESMOOTHER;
+}
+
+}  // namespace pod2g
+
+using namespace pod2g;
+
+extern "C" {
+
+size_t pod2g_setup_bytes(const pod2g_pattern *pat, int k, int batch, int precision) {
+  if (!pat || k < 0 || k > MAXK || batch < 1) return 0;
+  return setup_layout(pat->n, k, batch, precision).total;
+}
+
+int pod2g_setup(const pod2g_pattern *pat, const double *vals, const float *vals32,
+                const double *dinv, const double *P, int k, double omega, int nu_pre, int nu_post,
+                int precision, int batch, int power_iters, void *work, size_t bytes,
+                pod2g_prec *out, hipStream_t stream) {
+  if (!pat || !vals || !dinv || !work || !out) return POD2G_EINVAL;
+  if (k < 0 || k > MAXK || (k > 0 && !P) || batch < 1 || batch > 65535) return POD2G_EINVAL;
+  if (precision != POD2G_FP64 && precision != POD2G_MIXED) return POD2G_EINVAL;
+  if (precision == POD2G_MIXED && !vals32) return POD2G_EINVAL;
+  if (!(omega > 0.0) || nu_pre < 0 || nu_post < 0 || nu_pre > 64 || nu_post > 64 || power_iters < 0)
+    return POD2G_EINVAL;
+  if (bytes < pod2g_setup_bytes(pat, k, batch, precision)) return POD2G_ESIZE;
+  const int n = pat->n, dim = pat->mesh.dim;
+  SetupLayout S = setup_layout(n, k, batch, precision);
+  char *w = (char *)work;
+  pod2g_prec pr;
+  memset(&pr, 0, sizeof(pr));
+  pr.pat = *pat;
+  pr.batch = batch;
+  pr.k = k;
+  pr.nu_pre = nu_pre;
+  pr.nu_post = nu_post;
+  pr.precision = precision;
+  pr.omega = omega;
+  pr.vals = vals;
+  pr.vals32 = precision == POD2G_MIXED ? vals32 : nullptr;
+  pr.dinv = dinv;
+  pr.P = P;
+  pr.status = (int *)(w + S.status);
+  pr.lam = (double *)(w + S.lam);
+  InstState *pst = (InstState *)(w + S.pst);
+  pr.KP = k > 0 ? (double *)(w + S.kp) : nullptr;
+  pr.L = k > 0 ? (double *)(w + S.L) : nullptr;
+  double *kcpart = (double *)(w + S.kcpart);
+  double *ppart = (double *)(w + S.ppart);
+  pr.P32 = (precision == POD2G_MIXED && k > 0) ? (float *)(w + S.p32) : nullptr;
+  pr.dinv32 = precision == POD2G_MIXED ? (float *)(w + S.d32) : nullptr;
+  double *pw0 = (double *)(w + S.pw);
+  double *pw1 = (double *)(w + S.pw + align256(sizeof(double) * (size_t)batch * n));
+
+  hipLaunchKernelGGL(k_setup_init, dim3(ceil_div(batch, 64)), dim3(64), 0, stream, pst, pr.status,
+                     pr.lam, batch, n);
+  const int nb = ceil_div(n, NT);
+  if (k > 0) {
+    dim3 gk(nb, batch, ceil_div(k, KP_CH));
+    if (dim == 2)
+      hipLaunchKernelGGL(k_kp<2>, gk, dim3(NT), 0, stream, n, pat->n_nodes, k, pat->nvals,
+                         pat->colblk, vals, P, pr.KP);
+    else
+      hipLaunchKernelGGL(k_kp<3>, gk, dim3(NT), 0, stream, n, pat->n_nodes, k, pat->nvals,
+                         pat->colblk, vals, P, pr.KP);
+    hipLaunchKernelGGL(k_kc, dim3(S.nbk, batch), dim3(NT), 0, stream, n, k, S.rows_per_wg, S.nbk,
+                       P, (const double *)pr.KP, kcpart, pr.L, pr.status, pst);
+    if (precision == POD2G_MIXED)
+      hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(NT), 0, stream, (size_t)k * n, P, pr.P32);
+  }
+  if (precision == POD2G_MIXED)
+    hipLaunchKernelGGL(k_to_f32, dim3(2048), dim3(NT), 0, stream, (size_t)batch * n, dinv, pr.dinv32);
+  if (power_iters > 0) {
+    hipLaunchKernelGGL(k_fill, dim3(1024), dim3(NT), 0, stream, (size_t)batch * n, 1.0, pw0);
+    double *x = pw0, *y = pw1;
+    for (int it = 0; it < power_iters; ++it) {
+      if (dim == 2)
+        hipLaunchKernelGGL(k_power<2>, dim3(nb, batch), dim3(NT), 0, stream, n, pat->n_nodes, nb,
+                           pat->nvals, pat->colblk, vals, dinv, (const double *)x, y, ppart, pst,
+                           pr.lam);
+      else
+        hipLaunchKernelGGL(k_power<3>, dim3(nb, batch), dim3(NT), 0, stream, n, pat->n_nodes, nb,
+                           pat->nvals, pat->colblk, vals, dinv, (const double *)x, y, ppart, pst,
+                           pr.lam);
+      double *t = x; x = y; y = t;
+    }
+    hipLaunchKernelGGL(k_smoother_guard, dim3(ceil_div(batch, 64)), dim3(64), 0, stream, batch,
+                       omega, (const double *)pr.lam, pr.status);
+  }
+  POD2G_HIP_CHECK(hipGetLastError());
+  *out = pr;
+  return POD2G_OK;
+}
+
+int pod2g_setup_status(const pod2g_prec *prec, int *status_h, double *lam_h, hipStream_t stream) {
+  if (!prec || !status_h || !prec->status) return POD2G_EINVAL;
+  POD2G_HIP_CHECK(hipMemcpyAsync(status_h, prec->status, sizeof(int) * prec->batch,
+                                 hipMemcpyDeviceToHost, stream));
+  if (lam_h)
+    POD2G_HIP_CHECK(hipMemcpyAsync(lam_h, prec->lam, sizeof(double) * prec->batch,
+                                   hipMemcpyDeviceToHost, stream));
+  POD2G_HIP_CHECK(hipStreamSynchronize(stream));
+  return POD2G_OK;
+}
+
+}  // extern "C"

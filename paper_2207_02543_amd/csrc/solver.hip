@@ -1,0 +1,830 @@
+// The POD two-grid cycle (Sec. 2.2 Alg. 2 with the POD prolongation of
+// Sec. 3.3, Eq. 30) and PCG preconditioned by one cycle per iteration
+// (Sec. 3.4 Alg. 3).  One thread per scalar row, 256-row workgroups, one
+// grid row (blockIdx.y) per batched instance.  Every reduction is a
+// deterministic two-stage tree: per-workgroup partials, then the last
+// workgroup to arrive sums them in a fixed order and updates the
+// instance's scalar state.  Every kernel first reads the instance's `done`
+// flag and exits if it is set, so a fixed launch sequence can run past
+// convergence without changing the result.
+#include "common.hpp"
+
+#include <math.h>
+#include <string.h>
+#include <vector>
+
+namespace pod2g {
+
+struct Ctx {
+  int n, nn, k, batch, nb, ps;   // ps: partial stride per workgroup (doubles)
+  int mixed;                     // FP32 cycle: its input is scaled by a power of two
+  long long vstride;
+  const int *colblk;
+  const double *vals;            // FP64 K
+  const void *svals;             // smoother K (FP64 or FP32)
+  const void *sdinv;             // smoother D^-1
+  const void *sP;                // cycle P (FP64 or FP32)
+  const double *L;               // [batch][k][k]
+  double omega;
+  const double *f;               // [n]
+  double *u, *r, *p, *q, *s;     // [batch][n] FP64
+  void *xa, *xb;                 // [batch][n] cycle vectors (smoother type)
+  void *b32;                     // [batch][n] FP32 scaled residual (mixed only)
+  double *part;                  // [batch][nb][ps]
+  double *ec;                    // [batch][MAXK]
+  InstState *st;
+};
+
+__device__ __forceinline__ int inst_id() { return blockIdx.y; }
+
+__device__ __forceinline__ double pow2_scale(double rr);
+__device__ __forceinline__ double cycle_scale(const Ctx &c, double rr) {
+  return c.mixed ? pow2_scale(rr) : 1.0;
+}
+
+__device__ __forceinline__ double pow2_scale(double rr) {
+  // 2^-e with sqrt(rr) = m 2^e, m in [0.5, 1)
+  if (!(rr > 0.0) || !finite(rr)) return 1.0;
+  int e;
+  frexp(sqrt(rr), &e);
+  return ldexp(1.0, -e);
+}
+
+// ---------------------------------------------------------------- state ---
+__global__ void k_state_init(InstState *st, int batch, double rtol, int maxit, int beta_kind,
+                             const int *setup_status) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  InstState s;
+  memset(&s, 0, sizeof(s));
+  s.maxit = maxit;
+  s.beta_kind = beta_kind;
+  s.restart = 1;
+  s.scale = 1.0;
+  s.tol2 = rtol * rtol;   // multiplied by ||f||^2 in k_init
+  const int ss = setup_status ? setup_status[b] : 0;
+  if (ss != 0) { s.done = 1; s.status = ss; }
+  st[b] = s;
+}
+
+// r = f - K u; ||r||^2, ||f||^2.  Last block: tolerance and initial checks.
+template <int DIM>
+__global__ void __launch_bounds__(NT) k_init(Ctx c, int have_prec) {
+  __shared__ double lds[2 * NWAVE];
+  __shared__ int flag;
+  const int b = inst_id();
+  InstState *st = c.st + b;
+  if (st->done) return;
+  const int blk = xcd_block(blockIdx.x, c.nb);
+  const int row = blk * NT + threadIdx.x;
+  const size_t off = (size_t)b * c.n;
+  double rr = 0.0, ff = 0.0;
+  if (row < c.n) {
+    const double kx = row_dot<DIM>(c.colblk, c.vals + (size_t)b * c.vstride, c.u + off, row,
+                                   row / DIM, c.n, c.nn);
+    const double fv = c.f[row];
+    const double rv = fv - kx;
+    c.r[off + row] = rv;
+    rr = rv * rv;
+    ff = fv * fv;
+  }
+  block_sum2(rr, ff, lds);
+  double *part = c.part + ((size_t)b * c.nb + blk) * c.ps;
+  if (threadIdx.x == 0) { part[0] = rr; part[1] = ff; }
+  if (!arrive_last(&st->cnt[CNT_A], c.nb, &flag)) return;
+  const double *p0 = c.part + (size_t)b * c.nb * c.ps;
+  double trr = reduce_partials(p0, c.nb, c.ps, lds);
+  double tff = reduce_partials(p0 + 1, c.nb, c.ps, lds);
+  if (threadIdx.x == 0) {
+    st->rr = trr;
+    st->ff = tff;
+    st->tol2 = st->tol2 * tff;
+    st->scale = cycle_scale(c, trr);
+    if (!finite(trr) || !finite(tff)) { st->done = 1; st->status = POD2G_ENAN; }
+    else if (trr <= st->tol2) { st->done = 1; st->status = POD2G_OK; }
+    if (!have_prec) st->rho = trr;
+  }
+}
+
+// Cycle input b = scale * r (stored in FP32 for the mixed cycle) and, with
+// write_x, the first relaxation sweep from x = 0: x = omega D^-1 b.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_cyc_first(Ctx c, int write_x) {
+  const int b = inst_id();
+  if (c.st[b].done) return;
+  const int row = blockIdx.x * NT + threadIdx.x;
+  if (row >= c.n) return;
+  const size_t off = (size_t)b * c.n;
+  const double sc = c.st[b].scale;
+  const T bv = (T)(c.r[off + row] * sc);
+  if (sizeof(T) == 4) ((float *)c.b32)[off + row] = (float)bv;
+  if (write_x) ((T *)c.xa)[off + row] = (T)c.omega * ((const T *)c.sdinv)[off + row] * bv;
+}
+
+template <typename T>
+__device__ __forceinline__ const T *cycle_rhs(const Ctx &c, size_t off) {
+  return sizeof(T) == 8 ? (const T *)(c.r + off) : (const T *)c.b32 + off;
+}
+
+// x_out = x_in + omega D^-1 (b - K x_in).  With FINAL the result is the
+// preconditioned residual s = x_out / scale (FP64) and the block also
+// reduces r^T s; the last block forms rho and beta.
+template <int DIM, typename T, bool FINAL>
+__global__ void __launch_bounds__(NT) k_sweep(Ctx c, const T *__restrict__ xin, T *__restrict__ xout,
+                                              int want_dot) {
+  __shared__ double lds[2 * NWAVE];
+  __shared__ int flag;
+  const int b = inst_id();
+  InstState *st = c.st + b;
+  if (st->done) return;
+  const int blk = xcd_block(blockIdx.x, c.nb);
+  const int row = blk * NT + threadIdx.x;
+  const size_t off = (size_t)b * c.n;
+  double rs = 0.0;
+  if (row < c.n) {
+    const T *vals = (const T *)c.svals + (size_t)b * c.vstride;
+    const T kx = row_dot<DIM>(c.colblk, vals, xin + off, row, row / DIM, c.n, c.nn);
+    const T bv = cycle_rhs<T>(c, off)[row];
+    const T xv = xin[off + row] + (T)c.omega * ((const T *)c.sdinv)[off + row] * (bv - kx);
+    if (FINAL) {
+      const double sv = (double)xv / st->scale;
+      c.s[off + row] = sv;
+      rs = c.r[off + row] * sv;
+    } else {
+      xout[off + row] = xv;
+    }
+  }
+  if (!FINAL || !want_dot) return;
+  double dummy = 0.0;
+  block_sum2(rs, dummy, lds);
+  double *part = c.part + ((size_t)b * c.nb + blk) * c.ps;
+  if (threadIdx.x == 0) part[0] = rs;
+  if (!arrive_last(&st->cnt[CNT_B], c.nb, &flag)) return;
+  const double trs = reduce_partials(c.part + (size_t)b * c.nb * c.ps, c.nb, c.ps, lds);
+  if (threadIdx.x == 0) {
+    double beta = 0.0;
+    if (!st->restart) {
+      beta = st->beta_kind == POD2G_BETA_PR ? (trs - st->rs_prev) / st->rho : trs / st->rho;
+    }
+    st->restart = 0;
+    st->beta = beta;
+    st->rho = trs;
+    if (!(trs > 0.0)) { st->done = 1; st->status = finite(trs) ? POD2G_EBREAKDOWN : POD2G_ENAN; }
+  }
+}
+
+// Residual after pre-relaxation and restriction: r' = b - K x,
+// r_c = P^T r'; the last block solves L L^T e_c = r_c (FP64).
+template <int DIM, typename T, bool XZERO>
+__global__ void __launch_bounds__(NT) k_restrict(Ctx c, const T *__restrict__ x) {
+  __shared__ double lds[2 * NWAVE];
+  __shared__ double rsh[NT];
+  __shared__ double rc[MAXK];
+  __shared__ int flag;
+  const int b = inst_id();
+  InstState *st = c.st + b;
+  if (st->done) return;
+  const int blk = xcd_block(blockIdx.x, c.nb);
+  const int row = blk * NT + threadIdx.x;
+  const size_t off = (size_t)b * c.n;
+  T rv = T(0);
+  if (row < c.n) {
+    const T bv = cycle_rhs<T>(c, off)[row];
+    if (XZERO) {
+      rv = bv;
+    } else {
+      const T *vals = (const T *)c.svals + (size_t)b * c.vstride;
+      rv = bv - row_dot<DIM>(c.colblk, vals, x + off, row, row / DIM, c.n, c.nn);
+    }
+  }
+  rsh[threadIdx.x] = (double)rv;
+  __syncthreads();
+  // wave w reduces columns j = w, w + 4, ...; lane l covers rows l + 64 m
+  const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+  const T *P = (const T *)c.sP;
+  const int row0 = blk * NT;
+  double *part = c.part + ((size_t)b * c.nb + blk) * c.ps;
+  for (int j = w; j < c.k; j += NWAVE) {
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < NT / WAVE; ++m) {
+      const int rr = row0 + lane + m * WAVE;
+      if (rr < c.n) acc += (double)P[(size_t)j * c.n + rr] * rsh[lane + m * WAVE];
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) part[j] = acc;
+  }
+  if (!arrive_last(&st->cnt[CNT_C], c.nb, &flag)) return;
+  const double *p0 = c.part + (size_t)b * c.nb * c.ps;
+  for (int j = w; j < c.k; j += NWAVE) {
+    double acc = 0.0;
+    for (int i = lane; i < c.nb; i += WAVE) acc += p0[(size_t)i * c.ps + j];
+    acc = wave_sum(acc);
+    if (lane == 0) rc[j] = acc;
+  }
+  __syncthreads();
+  if (w == 0) {
+    // L L^T e = rc with lane t owning unknown t
+    const double *L = c.L + (size_t)b * c.k * c.k;
+    const int k = c.k;
+    double y = lane < k ? rc[lane] : 0.0;
+    for (int j = 0; j < k; ++j) {
+      const double yj = __shfl(y, j, WAVE) / L[j * k + j];
+      if (lane == j) y = yj;
+      if (lane > j && lane < k) y -= L[lane * k + j] * yj;
+    }
+    for (int j = k - 1; j >= 0; --j) {
+      const double ej = __shfl(y, j, WAVE) / L[j * k + j];
+      if (lane == j) y = ej;
+      if (lane < j) y -= L[j * k + lane] * ej;
+    }
+    if (lane < k) c.ec[(size_t)b * MAXK + lane] = y;
+  }
+}
+
+// Prolongation and correction: x_out = x_in + P e_c.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_prolong(Ctx c, const T *__restrict__ xin, T *__restrict__ xout) {
+  __shared__ T e[MAXK];
+  const int b = inst_id();
+  if (c.st[b].done) return;
+  if (threadIdx.x < c.k) e[threadIdx.x] = (T)c.ec[(size_t)b * MAXK + threadIdx.x];
+  __syncthreads();
+  const int row = blockIdx.x * NT + threadIdx.x;
+  if (row >= c.n) return;
+  const size_t off = (size_t)b * c.n;
+  const T *P = (const T *)c.sP;
+  T acc = xin ? xin[off + row] : T(0);
+  for (int j = 0; j < c.k; ++j) acc += P[(size_t)j * c.n + row] * e[j];
+  xout[off + row] = acc;
+}
+
+// s = x / scale with r^T s (used when the cycle ends without a sweep).
+template <typename T>
+__global__ void __launch_bounds__(NT) k_finalize(Ctx c, const T *__restrict__ x, int want_dot) {
+  __shared__ double lds[2 * NWAVE];
+  __shared__ int flag;
+  const int b = inst_id();
+  InstState *st = c.st + b;
+  if (st->done) return;
+  const int blk = blockIdx.x;
+  const int row = blk * NT + threadIdx.x;
+  const size_t off = (size_t)b * c.n;
+  double rs = 0.0;
+  if (row < c.n) {
+    const double sv = x ? (double)x[off + row] / st->scale : 0.0;
+    c.s[off + row] = sv;
+    rs = c.r[off + row] * sv;
+  }
+  if (!want_dot) return;
+  double dummy = 0.0;
+  block_sum2(rs, dummy, lds);
+  if (threadIdx.x == 0) c.part[((size_t)b * c.nb + blk) * c.ps] = rs;
+  if (!arrive_last(&st->cnt[CNT_B], c.nb, &flag)) return;
+  const double trs = reduce_partials(c.part + (size_t)b * c.nb * c.ps, c.nb, c.ps, lds);
+  if (threadIdx.x == 0) {
+    double beta = 0.0;
+    if (!st->restart)
+      beta = st->beta_kind == POD2G_BETA_PR ? (trs - st->rs_prev) / st->rho : trs / st->rho;
+    st->restart = 0;
+    st->beta = beta;
+    st->rho = trs;
+    if (!(trs > 0.0)) { st->done = 1; st->status = finite(trs) ? POD2G_EBREAKDOWN : POD2G_ENAN; }
+  }
+}
+
+// q = K p and p^T q; the last block forms alpha = rho / p^T q.
+template <int DIM>
+__global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c) {
+  __shared__ double lds[2 * NWAVE];
+  __shared__ int flag;
+  const int b = inst_id();
+  InstState *st = c.st + b;
+  if (st->done) return;
+  const int blk = xcd_block(blockIdx.x, c.nb);
+  const int row = blk * NT + threadIdx.x;
+  const size_t off = (size_t)b * c.n;
+  double pq = 0.0;
+  if (row < c.n) {
+    const double kp = row_dot<DIM>(c.colblk, c.vals + (size_t)b * c.vstride, c.p + off, row,
+                                   row / DIM, c.n, c.nn);
+    c.q[off + row] = kp;
+    pq = c.p[off + row] * kp;
+  }
+  double dummy = 0.0;
+  block_sum2(pq, dummy, lds);
+  if (threadIdx.x == 0) c.part[((size_t)b * c.nb + blk) * c.ps] = pq;
+  if (!arrive_last(&st->cnt[CNT_D], c.nb, &flag)) return;
+  const double g = reduce_partials(c.part + (size_t)b * c.nb * c.ps, c.nb, c.ps, lds);
+  if (threadIdx.x == 0) {
+    st->gamma = g;
+    if (!(g > 0.0)) { st->done = 1; st->status = finite(g) ? POD2G_EBREAKDOWN : POD2G_ENAN; }
+    st->alpha = st->rho / g;
+  }
+}
+
+// u += alpha p, r -= alpha q, ||r||^2 (and r^T s_old for the flexible
+// beta); with a preconditioner also the next cycle's input and, for
+// mode 1, its first pre-relaxation sweep.  Last block: convergence,
+// iteration limit, non-finite checks; without a preconditioner (mode 0)
+// s = r, so rho and beta are formed here.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_update(Ctx c, int mode) {
+  const int have_prec = mode != 0;
+  __shared__ double lds[2 * NWAVE];
+  __shared__ int flag;
+  const int b = inst_id();
+  InstState *st = c.st + b;
+  if (st->done) return;
+  const int blk = blockIdx.x;
+  const int row = blk * NT + threadIdx.x;
+  const size_t off = (size_t)b * c.n;
+  const double alpha = st->alpha;
+  const bool pr = have_prec && st->beta_kind == POD2G_BETA_PR;
+  double rr = 0.0, rs = 0.0;
+  if (row < c.n) {
+    c.u[off + row] += alpha * c.p[off + row];
+    const double rv = c.r[off + row] - alpha * c.q[off + row];
+    c.r[off + row] = rv;
+    rr = rv * rv;
+    if (pr) rs = rv * c.s[off + row];
+    if (have_prec) {
+      const T bv = (T)(rv * st->scale);
+      if (sizeof(T) == 4) ((float *)c.b32)[off + row] = (float)bv;
+      if (mode == 1) ((T *)c.xa)[off + row] = (T)c.omega * ((const T *)c.sdinv)[off + row] * bv;
+    }
+  }
+  block_sum2(rr, rs, lds);
+  double *part = c.part + ((size_t)b * c.nb + blk) * c.ps;
+  if (threadIdx.x == 0) { part[0] = rr; part[1] = rs; }
+  if (!arrive_last(&st->cnt[CNT_E], c.nb, &flag)) return;
+  const double *p0 = c.part + (size_t)b * c.nb * c.ps;
+  const double trr = reduce_partials(p0, c.nb, c.ps, lds);
+  const double trs = pr ? reduce_partials(p0 + 1, c.nb, c.ps, lds) : 0.0;
+  if (threadIdx.x == 0) {
+    st->iter += 1;
+    st->rr = trr;
+    st->rs_prev = trs;
+    if (!finite(trr)) { st->done = 1; st->status = POD2G_ENAN; }
+    else if (trr <= st->tol2) { st->done = 1; st->status = POD2G_OK; }
+    else if (st->iter >= st->maxit) { st->done = 1; st->status = POD2G_EMAXIT; }
+    if (!have_prec) {
+      st->beta = trr / st->rho;
+      st->rho = trr;
+    }
+  }
+}
+
+// p = s + beta p; the next cycle's input scale takes effect.
+__global__ void __launch_bounds__(NT) k_pupdate(Ctx c, const double *__restrict__ s) {
+  const int b = inst_id();
+  InstState *st = c.st + b;
+  if (st->done) return;
+  const int row = blockIdx.x * NT + threadIdx.x;
+  if (row >= c.n) return;
+  const size_t off = (size_t)b * c.n;
+  c.p[off + row] = s[off + row] + st->beta * c.p[off + row];
+}
+
+__global__ void k_rescale(Ctx c) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= c.batch) return;
+  InstState *st = c.st + b;
+  if (st->done) return;
+  st->scale = cycle_scale(c, st->rr);
+}
+
+// q = f - K u with ||q||^2 for every instance (done or not).
+template <int DIM>
+__global__ void __launch_bounds__(NT) k_true_resid(Ctx c) {
+  __shared__ double lds[2 * NWAVE];
+  __shared__ int flag;
+  const int b = inst_id();
+  InstState *st = c.st + b;
+  const int blk = xcd_block(blockIdx.x, c.nb);
+  const int row = blk * NT + threadIdx.x;
+  const size_t off = (size_t)b * c.n;
+  double rr = 0.0;
+  if (row < c.n) {
+    const double kx = row_dot<DIM>(c.colblk, c.vals + (size_t)b * c.vstride, c.u + off, row,
+                                   row / DIM, c.n, c.nn);
+    const double rv = c.f[row] - kx;
+    c.q[off + row] = rv;
+    rr = rv * rv;
+  }
+  double dummy = 0.0;
+  block_sum2(rr, dummy, lds);
+  if (threadIdx.x == 0) c.part[((size_t)b * c.nb + blk) * c.ps] = rr;
+  if (!arrive_last(&st->cnt[CNT_A], c.nb, &flag)) return;
+  const double t = reduce_partials(c.part + (size_t)b * c.nb * c.ps, c.nb, c.ps, lds);
+  if (threadIdx.x == 0) st->rr_true = t;
+}
+
+// Residual replacement for the instances flagged by the host: r = q,
+// CG restarts (beta = 0) and the instance becomes live again.
+__global__ void __launch_bounds__(NT) k_replace(Ctx c, const int *__restrict__ flags, int have_prec) {
+  const int b = inst_id();
+  if (!flags[b]) return;
+  const int row = blockIdx.x * NT + threadIdx.x;
+  const size_t off = (size_t)b * c.n;
+  if (row < c.n) c.r[off + row] = c.q[off + row];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    InstState *st = c.st + b;
+    st->rr = st->rr_true;
+    st->scale = cycle_scale(c, st->rr_true);
+    st->done = 0;
+    st->restart = 1;
+    st->beta = 0.0;
+    if (!have_prec) st->rho = st->rr_true;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t st, ec, part, vec, vec32, flags, total;
+};
+
+static Layout layout(int n, int batch, int k, int precision) {
+  const int nb = ceil_div(n, NT);
+  const int ps = k > 2 ? k : 2;
+  Layout L;
+  size_t o = 0;
+  L.st = o;    o += align256(sizeof(InstState) * (size_t)batch);
+  L.ec = o;    o += align256(sizeof(double) * MAXK * (size_t)batch);
+  L.part = o;  o += align256(sizeof(double) * (size_t)ps * nb * batch);
+  L.flags = o; o += align256(sizeof(int) * (size_t)batch);
+  L.vec = o;   o += 6 * align256(sizeof(double) * (size_t)n * batch);   // r p q s xa xb
+  L.vec32 = o;
+  if (precision == POD2G_MIXED) o += align256(sizeof(float) * (size_t)n * batch);  // b32
+  L.total = o;
+  return L;
+}
+
+static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int batch,
+                     const pod2g_prec *prec, const double *f, double *u, void *work) {
+  memset(&c, 0, sizeof(c));
+  const int n = pat->n;
+  const int k = prec ? prec->k : 0;
+  const int precision = prec ? prec->precision : POD2G_FP64;
+  Layout Lo = layout(n, batch, k, precision);
+  char *w = (char *)work;
+  c.n = n;
+  c.nn = pat->n_nodes;
+  c.k = k;
+  c.batch = batch;
+  c.nb = ceil_div(n, NT);
+  c.ps = k > 2 ? k : 2;
+  c.vstride = pat->nvals;
+  c.colblk = pat->colblk;
+  c.vals = vals;
+  c.f = f;
+  c.u = u;
+  c.st = (InstState *)(w + Lo.st);
+  c.ec = (double *)(w + Lo.ec);
+  c.part = (double *)(w + Lo.part);
+  const size_t vb = align256(sizeof(double) * (size_t)n * batch);
+  c.r = (double *)(w + Lo.vec);
+  c.p = (double *)(w + Lo.vec + vb);
+  c.q = (double *)(w + Lo.vec + 2 * vb);
+  c.s = (double *)(w + Lo.vec + 3 * vb);
+  c.xa = (void *)(w + Lo.vec + 4 * vb);
+  c.xb = (void *)(w + Lo.vec + 5 * vb);
+  c.b32 = precision == POD2G_MIXED ? (void *)(w + Lo.vec32) : nullptr;
+  c.mixed = precision == POD2G_MIXED;
+  if (prec) {
+    c.omega = prec->omega;
+    c.L = prec->L;
+    if (precision == POD2G_MIXED) {
+      c.svals = prec->vals32;
+      c.sdinv = prec->dinv32;
+      c.sP = prec->P32;
+    } else {
+      c.svals = prec->vals;
+      c.sdinv = prec->dinv;
+      c.sP = prec->P;
+    }
+  }
+}
+
+// The cycle s = B r on the instances that are not done.  Assumes xa holds
+// the first pre-relaxation sweep when nu_pre >= 1 (made by the producer of
+// r).  With want_dot the last kernel also forms rho and beta.
+template <int DIM, typename T>
+static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, int want_dot) {
+  dim3 grid(c.nb, c.batch), blk(NT);
+  T *xa = (T *)c.xa, *xb = (T *)c.xb;
+  T *cur = xa, *oth = xb;
+  const bool have_x = pr->nu_pre >= 1;
+  for (int i = 1; i < pr->nu_pre; ++i) {
+    hipLaunchKernelGGL((k_sweep<DIM, T, false>), grid, blk, 0, stream, c, cur, oth, 0);
+    T *t = cur; cur = oth; oth = t;
+  }
+  bool have = have_x;
+  if (c.k > 0) {
+    if (have)
+      hipLaunchKernelGGL((k_restrict<DIM, T, false>), grid, blk, 0, stream, c, cur);
+    else
+      hipLaunchKernelGGL((k_restrict<DIM, T, true>), grid, blk, 0, stream, c, (const T *)nullptr);
+    hipLaunchKernelGGL((k_prolong<T>), grid, blk, 0, stream, c, have ? (const T *)cur : (const T *)nullptr, oth);
+    T *t = cur; cur = oth; oth = t;
+    have = true;
+  }
+  if (pr->nu_post >= 1 && !have) {
+    // x = 0 so the first post sweep is omega D^-1 b: reuse the zero-input path
+    hipLaunchKernelGGL((k_cyc_first<T>), dim3(c.nb, c.batch), blk, 0, stream, c, 1);
+    cur = xa; oth = xb;
+    have = true;
+    for (int i = 1; i < pr->nu_post; ++i) {
+      const bool fin = (i == pr->nu_post - 1);
+      if (fin)
+        hipLaunchKernelGGL((k_sweep<DIM, T, true>), grid, blk, 0, stream, c, cur, oth, want_dot);
+      else
+        hipLaunchKernelGGL((k_sweep<DIM, T, false>), grid, blk, 0, stream, c, cur, oth, 0);
+      T *t = cur; cur = oth; oth = t;
+    }
+    if (pr->nu_post == 1) hipLaunchKernelGGL((k_finalize<T>), grid, blk, 0, stream, c, cur, want_dot);
+    return;
+  }
+  for (int i = 0; i < pr->nu_post; ++i) {
+    const bool fin = (i == pr->nu_post - 1);
+    if (fin)
+      hipLaunchKernelGGL((k_sweep<DIM, T, true>), grid, blk, 0, stream, c, cur, oth, want_dot);
+    else
+      hipLaunchKernelGGL((k_sweep<DIM, T, false>), grid, blk, 0, stream, c, cur, oth, 0);
+    T *t = cur; cur = oth; oth = t;
+  }
+  if (pr->nu_post == 0)
+    hipLaunchKernelGGL((k_finalize<T>), grid, blk, 0, stream, c, have ? (const T *)cur : (const T *)nullptr, want_dot);
+}
+
+template <int DIM>
+static void launch_cycle_any(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, int want_dot) {
+  if (pr->precision == POD2G_MIXED) launch_cycle<DIM, float>(c, pr, stream, want_dot);
+  else launch_cycle<DIM, double>(c, pr, stream, want_dot);
+}
+
+template <int DIM>
+static void launch_first(const Ctx &c, const pod2g_prec *pr, hipStream_t stream) {
+  const int wx = pr->nu_pre >= 1;
+  dim3 grid(c.nb, c.batch);
+  if (pr->precision == POD2G_MIXED) hipLaunchKernelGGL((k_cyc_first<float>), grid, dim3(NT), 0, stream, c, wx);
+  else if (wx) hipLaunchKernelGGL((k_cyc_first<double>), grid, dim3(NT), 0, stream, c, wx);
+}
+
+template <int DIM>
+static void launch_iteration(const Ctx &c, const pod2g_prec *pr, hipStream_t stream) {
+  dim3 grid(c.nb, c.batch), blk(NT);
+  hipLaunchKernelGGL(k_spmv_pq<DIM>, grid, blk, 0, stream, c);
+  if (pr) {
+    const int mode = pr->nu_pre >= 1 ? 1 : 2;
+    if (pr->precision == POD2G_MIXED) hipLaunchKernelGGL(k_update<float>, grid, blk, 0, stream, c, mode);
+    else hipLaunchKernelGGL(k_update<double>, grid, blk, 0, stream, c, mode);
+    launch_cycle_any<DIM>(c, pr, stream, 1);
+    hipLaunchKernelGGL(k_pupdate, grid, blk, 0, stream, c, (const double *)c.s);
+    hipLaunchKernelGGL(k_rescale, dim3(ceil_div(c.batch, 64)), dim3(64), 0, stream, c);
+  } else {
+    hipLaunchKernelGGL(k_update<double>, grid, blk, 0, stream, c, 0);
+    hipLaunchKernelGGL(k_pupdate, grid, blk, 0, stream, c, (const double *)c.r);
+  }
+}
+
+static int read_states(const Ctx &c, std::vector<InstState> &h, hipStream_t stream) {
+  h.resize(c.batch);
+  POD2G_HIP_CHECK(hipMemcpyAsync(h.data(), c.st, sizeof(InstState) * c.batch,
+                                 hipMemcpyDeviceToHost, stream));
+  POD2G_HIP_CHECK(hipStreamSynchronize(stream));
+  return POD2G_OK;
+}
+
+template <int DIM>
+static int pcg_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int beta,
+                   int *iters_h, double *relres_h, int *status_h, hipStream_t stream) {
+  dim3 grid(c.nb, c.batch), blk(NT);
+  hipLaunchKernelGGL(k_state_init, dim3(ceil_div(c.batch, 64)), dim3(64), 0, stream, c.st, c.batch,
+                     rtol, maxit, beta, pr ? (const int *)pr->status : (const int *)nullptr);
+  hipLaunchKernelGGL(k_init<DIM>, grid, blk, 0, stream, c, pr ? 1 : 0);
+  auto start_cycle = [&]() {
+    if (pr) {
+      launch_first<DIM>(c, pr, stream);
+      launch_cycle_any<DIM>(c, pr, stream, 1);
+      hipLaunchKernelGGL(k_pupdate, grid, blk, 0, stream, c, (const double *)c.s);
+    } else {
+      // restart flag: beta = 0 -> p = r
+      hipLaunchKernelGGL(k_pupdate, grid, blk, 0, stream, c, (const double *)c.r);
+    }
+  };
+  // beta of the first direction is 0: k_state_init sets beta = 0, restart = 1
+  start_cycle();
+  POD2G_HIP_CHECK(hipGetLastError());
+  std::vector<InstState> h;
+  std::vector<int> flags(c.batch);
+  int *flags_d = nullptr;
+  {
+    Layout Lo = layout(c.n, c.batch, c.k, pr ? pr->precision : POD2G_FP64);
+    flags_d = (int *)((char *)c.st - Lo.st + Lo.flags);
+  }
+  int chunk = 4;
+  for (int guard = 0; guard < 1000000; ++guard) {
+    for (int i = 0; i < chunk; ++i) launch_iteration<DIM>(c, pr, stream);
+    POD2G_HIP_CHECK(hipGetLastError());
+    int st = read_states(c, h, stream);
+    if (st) return st;
+    bool all_done = true;
+    for (int b = 0; b < c.batch; ++b) all_done = all_done && h[b].done;
+    if (chunk < 16) chunk *= 2;
+    if (!all_done) continue;
+    // exit check on the true residual
+    hipLaunchKernelGGL(k_true_resid<DIM>, grid, blk, 0, stream, c);
+    POD2G_HIP_CHECK(hipGetLastError());
+    st = read_states(c, h, stream);
+    if (st) return st;
+    bool any = false;
+    for (int b = 0; b < c.batch; ++b) {
+      flags[b] = (h[b].status == POD2G_OK && h[b].iter < maxit && h[b].rr_true > h[b].tol2 &&
+                  h[b].iter > 0) ? 1 : 0;
+      any = any || flags[b];
+    }
+    if (!any) break;
+    POD2G_HIP_CHECK(hipMemcpyAsync(flags_d, flags.data(), sizeof(int) * c.batch,
+                                   hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(k_replace, grid, blk, 0, stream, c, (const int *)flags_d, pr ? 1 : 0);
+    start_cycle();
+    chunk = 4;
+  }
+  int ret = POD2G_OK;
+  for (int b = 0; b < c.batch; ++b) {
+    int s = h[b].status;
+    if (s == POD2G_OK && h[b].rr_true > h[b].tol2) s = POD2G_EMAXIT;
+    if (iters_h) iters_h[b] = h[b].iter;
+    if (relres_h) relres_h[b] = h[b].ff > 0 ? sqrt(h[b].rr_true / h[b].ff) : 0.0;
+    if (status_h) status_h[b] = s;
+    if (ret == POD2G_OK && s != POD2G_OK) ret = s;
+  }
+  return ret;
+}
+
+// ---------------------------------------------------------------------------
+// single kernels: y = K x and damped-Jacobi sweeps
+// ---------------------------------------------------------------------------
+template <int DIM>
+__global__ void __launch_bounds__(NT) k_spmv(int n, int nn, int nb, long long vstride,
+                                             const int *__restrict__ colblk,
+                                             const double *__restrict__ vals,
+                                             const double *__restrict__ x, double *__restrict__ y) {
+  const int b = blockIdx.y;
+  const int row = xcd_block(blockIdx.x, nb) * NT + threadIdx.x;
+  if (row >= n) return;
+  const size_t off = (size_t)b * n;
+  y[off + row] = row_dot<DIM>(colblk, vals + (size_t)b * vstride, x + off, row, row / DIM, n, nn);
+}
+
+template <int DIM>
+__global__ void __launch_bounds__(NT) k_jacobi(int n, int nn, int nb, long long vstride,
+                                               const int *__restrict__ colblk,
+                                               const double *__restrict__ vals,
+                                               const double *__restrict__ dinv, double omega,
+                                               const double *__restrict__ rhs,
+                                               const double *__restrict__ x, double *__restrict__ y) {
+  const int b = blockIdx.y;
+  const int row = xcd_block(blockIdx.x, nb) * NT + threadIdx.x;
+  if (row >= n) return;
+  const size_t off = (size_t)b * n;
+  const double kx = row_dot<DIM>(colblk, vals + (size_t)b * vstride, x + off, row, row / DIM, n, nn);
+  y[off + row] = x[off + row] + omega * dinv[off + row] * (rhs[off + row] - kx);
+}
+
+}  // namespace pod2g
+
+using namespace pod2g;
+
+extern "C" {
+
+const char *pod2g_strerror(int s) {
+  switch (s) {
+    case POD2G_OK: return "ok";
+    case POD2G_EINVAL: return "invalid argument";
+    case POD2G_ESIZE: return "workspace too small";
+    case POD2G_EHIP: return "HIP runtime error";
+    case POD2G_ENOTSPD: return "coarse matrix P^T K P is not positive definite";
+    case POD2G_ESMOOTHER: return "damped-Jacobi smoother diverges: omega * lambda_max(D^-1 K) >= 2";
+    case POD2G_EMAXIT: return "iteration limit reached";
+    case POD2G_EBREAKDOWN: return "CG breakdown: p^T K p <= 0 or r^T s <= 0";
+    case POD2G_ENAN: return "non-finite value";
+    default: return "unknown status";
+  }
+}
+
+size_t pcg_solve_bytes(const pod2g_pattern *pat, int batch, int k, int precision) {
+  if (!pat || batch < 1 || k < 0 || k > MAXK) return 0;
+  return layout(pat->n, batch, k, precision).total;
+}
+
+size_t pod2g_apply_bytes(const pod2g_prec *prec) {
+  if (!prec) return 0;
+  return layout(prec->pat.n, prec->batch, prec->k, prec->precision).total;
+}
+
+static int check_prec(const pod2g_prec *pr) {
+  if (pr->k < 0 || pr->k > MAXK || pr->batch < 1 || pr->batch > 65535) return POD2G_EINVAL;
+  if (pr->nu_pre < 0 || pr->nu_post < 0 || pr->nu_pre > 64 || pr->nu_post > 64) return POD2G_EINVAL;
+  if (pr->precision == POD2G_MIXED && (!pr->vals32 || !pr->dinv32 || (pr->k > 0 && !pr->P32)))
+    return POD2G_EINVAL;
+  if (pr->k > 0 && (!pr->P || !pr->L)) return POD2G_EINVAL;
+  return POD2G_OK;
+}
+
+int pcg_solve(const pod2g_pattern *pat, const double *vals, int batch, const pod2g_prec *prec,
+              const double *f, double *u, double rtol, int maxit, int beta, int *iters_h,
+              double *relres_h, int *status_h, void *work, size_t bytes, hipStream_t stream) {
+  if (!pat || !vals || !f || !u || !work || batch < 1 || batch > 65535) return POD2G_EINVAL;
+  if (!(rtol >= 0.0) || maxit < 0 || (beta != POD2G_BETA_FR && beta != POD2G_BETA_PR)) return POD2G_EINVAL;
+  if (prec) {
+    if (check_prec(prec)) return POD2G_EINVAL;
+    if (prec->batch != batch || prec->pat.n != pat->n || prec->vals != vals) return POD2G_EINVAL;
+  }
+  const int k = prec ? prec->k : 0;
+  if (bytes < pcg_solve_bytes(pat, batch, k, prec ? prec->precision : POD2G_FP64)) return POD2G_ESIZE;
+  Ctx c;
+  fill_ctx(c, pat, vals, batch, prec, f, u, work);
+  if (pat->mesh.dim == 2) return pcg_run<2>(c, prec, rtol, maxit, beta, iters_h, relres_h, status_h, stream);
+  return pcg_run<3>(c, prec, rtol, maxit, beta, iters_h, relres_h, status_h, stream);
+}
+
+// s = B r: the same kernels as inside PCG, on a scratch state.
+__global__ void k_apply_init(InstState *st, int batch, const double *sc) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  InstState s;
+  memset(&s, 0, sizeof(s));
+  s.scale = sc ? sc[b] : 1.0;
+  s.restart = 1;
+  st[b] = s;
+}
+
+int pod2g_apply(const pod2g_prec *prec, const double *r, double *s, void *work, size_t bytes,
+                hipStream_t stream) {
+  if (!prec || !r || !s || !work) return POD2G_EINVAL;
+  if (check_prec(prec)) return POD2G_EINVAL;
+  if (bytes < pod2g_apply_bytes(prec)) return POD2G_ESIZE;
+  Ctx c;
+  fill_ctx(c, &prec->pat, prec->vals, prec->batch, prec, nullptr, nullptr, work);
+  // the cycle reads r from c.r and writes c.s; run it on the caller's arrays
+  c.r = const_cast<double *>(r);
+  c.s = s;
+  hipLaunchKernelGGL(k_apply_init, dim3(ceil_div(c.batch, 64)), dim3(64), 0, stream, c.st, c.batch,
+                     (const double *)nullptr);
+  if (prec->pat.mesh.dim == 2) {
+    launch_first<2>(c, prec, stream);
+    launch_cycle_any<2>(c, prec, stream, 0);
+  } else {
+    launch_first<3>(c, prec, stream);
+    launch_cycle_any<3>(c, prec, stream, 0);
+  }
+  POD2G_HIP_CHECK(hipGetLastError());
+  return POD2G_OK;
+}
+
+int pod2g_spmv(const pod2g_pattern *pat, const double *vals, int batch, const double *x, double *y,
+               hipStream_t stream) {
+  if (!pat || !vals || !x || !y || batch < 1 || batch > 65535) return POD2G_EINVAL;
+  const int nb = ceil_div(pat->n, NT);
+  dim3 grid(nb, batch);
+  if (pat->mesh.dim == 2)
+    hipLaunchKernelGGL(k_spmv<2>, grid, dim3(NT), 0, stream, pat->n, pat->n_nodes, nb, pat->nvals,
+                       pat->colblk, vals, x, y);
+  else
+    hipLaunchKernelGGL(k_spmv<3>, grid, dim3(NT), 0, stream, pat->n, pat->n_nodes, nb, pat->nvals,
+                       pat->colblk, vals, x, y);
+  POD2G_HIP_CHECK(hipGetLastError());
+  return POD2G_OK;
+}
+
+int pod2g_jacobi(const pod2g_pattern *pat, const double *vals, const double *dinv, int batch,
+                 double omega, int nsweeps, const double *b, double *x, double *tmp,
+                 hipStream_t stream) {
+  if (!pat || !vals || !dinv || !b || !x || !tmp || batch < 1 || batch > 65535 || nsweeps < 0)
+    return POD2G_EINVAL;
+  const int nb = ceil_div(pat->n, NT);
+  dim3 grid(nb, batch);
+  double *cur = x, *oth = tmp;
+  for (int i = 0; i < nsweeps; ++i) {
+    if (pat->mesh.dim == 2)
+      hipLaunchKernelGGL(k_jacobi<2>, grid, dim3(NT), 0, stream, pat->n, pat->n_nodes, nb,
+                         pat->nvals, pat->colblk, vals, dinv, omega, b, cur, oth);
+    else
+      hipLaunchKernelGGL(k_jacobi<3>, grid, dim3(NT), 0, stream, pat->n, pat->n_nodes, nb,
+                         pat->nvals, pat->colblk, vals, dinv, omega, b, cur, oth);
+    double *t = cur; cur = oth; oth = t;
+  }
+  if (cur != x)
+    POD2G_HIP_CHECK(hipMemcpyAsync(x, cur, sizeof(double) * (size_t)pat->n * batch,
+                                   hipMemcpyDeviceToDevice, stream));
+  POD2G_HIP_CHECK(hipGetLastError());
+  return POD2G_OK;
+}
+
+}  // extern "C"

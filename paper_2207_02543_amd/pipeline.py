@@ -1,0 +1,187 @@
+"""Host-side orchestration of the POD-2G path on one GPU.
+
+Every numerical step runs in the HIP library through ``capi``; this module
+only allocates device memory with torch, orders the calls and moves the
+small host-side results (iteration counts, statuses).
+
+* ``Problem``      -- one problem class (mesh size, field terms, Poisson ratio):
+                      the pattern plus helpers to assemble, set up and solve.
+* ``offline_basis``-- the offline phase (Sec. 3.4): training solves at the
+                      training parameters, then POD by the method of
+                      snapshots (Sec. 3.3) -> P.
+* ``exact_solutions`` -- tight solves used to build warm starts
+                      (surrogate stand-in) for the queries.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import capi as L
+from . import inputs as I
+
+
+def _bytes(n, device):
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
+
+
+def device_view(base: torch.Tensor, ptr: int, count: int, dtype) -> torch.Tensor:
+    """A typed view of `count` elements at device address `ptr` inside the
+    byte tensor `base` (e.g. a field of a handle living in a workspace)."""
+    off = int(ptr) - base.data_ptr()
+    nbytes = count * torch.empty(0, dtype=dtype).element_size()
+    if off < 0 or off + nbytes > base.numel():
+        raise ValueError("pointer outside the buffer")
+    return base[off:off + nbytes].view(dtype)
+
+
+@dataclass
+class System:
+    """Assembled instances of one problem class (device tensors)."""
+    batch: int
+    xi: torch.Tensor          # [batch, n_terms] f64
+    vals: torch.Tensor        # [batch, nvals] f64
+    vals32: torch.Tensor | None
+    dinv: torch.Tensor        # [batch, n] f64
+    f: torch.Tensor           # [n] f64
+
+
+class Problem:
+    def __init__(self, w: I.Workload, device="cuda"):
+        self.w = w
+        self.device = torch.device(device)
+        self.mesh = L.make_mesh(w.dim, w.N, w.n_terms, w.nu, w.kl_scale)
+        nb = L.pod2g_pattern_bytes(self.mesh)
+        if nb == 0:
+            raise L.Pod2gError(L.EINVAL, "pod2g_pattern_bytes")
+        self.pat_buf = _bytes(nb, self.device)
+        self.pat = L.Pattern()
+        L.check(L.pod2g_pattern_build(self.mesh, self.pat_buf, nb, self.pat), "pod2g_pattern_build")
+        self.n = self.pat.n
+        self.nvals = self.pat.nvals
+        self._work = {}
+
+    # -- scratch buffers, reused between calls of the same kind ----------------
+    def work(self, key, nbytes):
+        t = self._work.get(key)
+        if t is None or t.numel() < nbytes:
+            t = _bytes(nbytes, self.device)
+            self._work[key] = t
+        return t
+
+    # -- assembly -----------------------------------------------------------------
+    def alloc_system(self, batch, fp32=False) -> System:
+        d = self.device
+        return System(batch,
+                      torch.empty(batch, self.w.n_terms, dtype=torch.float64, device=d),
+                      torch.empty(batch, self.nvals, dtype=torch.float64, device=d),
+                      torch.empty(batch, self.nvals, dtype=torch.float32, device=d) if fp32 else None,
+                      torch.empty(batch, self.n, dtype=torch.float64, device=d),
+                      torch.empty(self.n, dtype=torch.float64, device=d))
+
+    def assemble(self, sysm: System, xi=None, stream=None):
+        if xi is not None:
+            sysm.xi.copy_(torch.as_tensor(np.asarray(xi), dtype=torch.float64).reshape(sysm.batch, -1))
+        nb = L.pod2g_assemble_bytes(self.pat, sysm.batch)
+        wk = self.work("assemble", nb)
+        L.check(L.pod2g_assemble(self.pat, sysm.xi, sysm.batch, sysm.vals, sysm.vals32, sysm.dinv,
+                                 sysm.f, wk, nb, stream), "pod2g_assemble")
+        return sysm
+
+    # -- preconditioner -----------------------------------------------------------
+    def setup(self, sysm: System, P, k=None, precision=L.FP64, omega=None, nu_pre=None,
+              nu_post=None, power_iters=0, key="setup", stream=None) -> L.Prec:
+        w = self.w
+        k = (P.shape[0] if P is not None else 0) if k is None else k
+        nb = L.pod2g_setup_bytes(self.pat, k, sysm.batch, precision)
+        wk = self.work(key, nb)
+        prec = L.Prec()
+        L.check(L.pod2g_setup(self.pat, sysm.vals, sysm.vals32, sysm.dinv, P, k,
+                              w.omega if omega is None else omega,
+                              w.nu_pre if nu_pre is None else nu_pre,
+                              w.nu_post if nu_post is None else nu_post,
+                              precision, sysm.batch, power_iters, wk, nb, prec, stream),
+                "pod2g_setup")
+        prec._keepalive = (wk, P, sysm)
+        return prec
+
+    # -- solve --------------------------------------------------------------------
+    def solve(self, sysm: System, prec, u, rtol=None, maxit=5000, beta=None, key="pcg",
+              stream=None):
+        k = prec.k if prec is not None else 0
+        precision = prec.precision if prec is not None else L.FP64
+        if beta is None:
+            beta = L.BETA_PR if precision == L.MIXED else L.BETA_FR
+        nb = L.pcg_solve_bytes(self.pat, sysm.batch, k, precision)
+        wk = self.work(key, nb)
+        return L.pcg_solve(self.pat, sysm.vals, sysm.batch, prec, sysm.f, u,
+                           self.w.tol if rtol is None else rtol, maxit, beta, wk, nb, stream)
+
+    def apply(self, prec, r, s, stream=None):
+        nb = L.pod2g_apply_bytes(prec)
+        wk = self.work("apply", nb)
+        L.check(L.pod2g_apply(prec, r, s, wk, nb, stream), "pod2g_apply")
+        return s
+
+
+def solve_batched(prob: Problem, xis: np.ndarray, P=None, k=0, rtol=1e-12, maxit=20000,
+                  chunk=32, u0=None):
+    """Tight solves at the given parameters (FP64 two-grid PCG with the
+    basis P, or the smoother-only cycle for k = 0).  Returns [len(xis), n]."""
+    m = len(xis)
+    out = torch.empty(m, prob.n, dtype=torch.float64, device=prob.device)
+    iters = []
+    for a in range(0, m, chunk):
+        b = min(m, a + chunk)
+        sysm = prob.alloc_system(b - a)
+        prob.assemble(sysm, xis[a:b])
+        prec = prob.setup(sysm, P, k=k if P is None else P.shape[0], key="setup_train")
+        u = out[a:b]
+        if u0 is None:
+            u.zero_()
+        else:
+            u.copy_(u0[a:b])
+        ret, it, rr, st = prob.solve(sysm, prec, u, rtol=rtol, maxit=maxit, key="pcg_train")
+        if ret != L.OK:
+            raise L.Pod2gError(ret, f"training solve {a}..{b}: statuses {st}")
+        iters += it
+        del sysm, prec
+    return out, iters
+
+
+def pod_basis(U: torch.Tensor, k: int):
+    """P ([k, n]) and all eigenvalues of U^T U (descending) from snapshots U ([N, n])."""
+    N, n = U.shape
+    P = torch.empty(k, n, dtype=torch.float64, device=U.device)
+    lam = torch.empty(N, dtype=torch.float64, device=U.device)
+    nb = L.pod2g_pod_basis_bytes(n, N, k)
+    wk = _bytes(nb, U.device)
+    L.check(L.pod2g_pod_basis(U, n, N, k, P, lam, wk, nb), "pod2g_pod_basis")
+    return P, lam
+
+
+def offline_basis(prob: Problem, n_train=None, k=None, rtol=1e-12, chunk=32, bootstrap=8):
+    """Training solves + POD.  The first `bootstrap` training solves use the
+    smoother-only cycle; their POD basis then preconditions the rest."""
+    w = prob.w
+    n_train = w.n_train if n_train is None else n_train
+    k = w.k if k is None else k
+    xis = np.stack([I.train_xi(w, i) for i in range(n_train)])
+    nb0 = min(bootstrap, n_train)
+    U0, it0 = solve_batched(prob, xis[:nb0], None, 0, rtol, chunk=chunk)
+    k0 = min(nb0 - 1, k) if nb0 > 1 else 1
+    P0, _ = pod_basis(U0, k0)
+    if n_train > nb0:
+        U1, it1 = solve_batched(prob, xis[nb0:], P0, rtol=rtol, chunk=chunk)
+        U = torch.cat([U0, U1], 0)
+    else:
+        U, it1 = U0, []
+    P, lam = pod_basis(U, k)
+    return P, lam, U, it0 + it1
+
+
+def exact_solutions(prob: Problem, xis, P, rtol=1e-12, chunk=32):
+    u, it = solve_batched(prob, xis, P, rtol=rtol, chunk=chunk)
+    return u
