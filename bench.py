@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Throughput of the POD-2G preconditioned CG path on one MI355X.
+
+A step is one pass of the online hot path over one batch of query
+parameters: assembly of K(theta), f and D^-1; the preconditioner setup
+(K P, P^T K P, Cholesky); and the warm-started PCG solve to
+||f - K u|| <= tol ||f||.  The offline phase (training solves, POD basis)
+and the exact solutions behind the warm starts run before timing; all
+inputs are resident on the GPU when the timed region starts.
+
+Prints one JSON line (stdout); progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("POD-2G-PCG solves/sec at rel-residual 1e-8 (batched/mixed vs plain); "
+          "SpMV HBM GB/s")
+HBM_PEAK_GBS = 8000.0
+KERNELS = {"spmv_pq": 1, "sweep": 2, "sweep_final": 3, "restrict": 4, "prolong": 5, "update": 6}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(w, kernel, mixed):
+    """Algorithmic HBM bytes of one launch of `kernel` over the batch: each
+    stored matrix value, index and vector entry moved once."""
+    S = 3 ** w.dim
+    n, nn = w.n, w.n_nodes_free
+    nvals = n * S * w.dim
+    B = w.batch
+    vb = 4 if (mixed and kernel in ("sweep", "sweep_final", "restrict")) else 8
+    idx = 4 * S * nn                       # shared block-column indices
+    if kernel == "sweep":                  # vals, x_in, b, D^-1 read; x_out written
+        per = vb * nvals + 4 * vb * n
+    elif kernel == "sweep_final":          # + r (FP64) read, s (FP64) written
+        per = vb * nvals + 3 * vb * n + 16 * n
+    elif kernel == "spmv_pq":              # vals, p read; q written
+        per = 8 * nvals + 16 * n
+    elif kernel == "restrict":             # vals, x, b read; P (shared) read once
+        per = vb * nvals + 2 * vb * n
+        idx += vb * w.k * n
+    else:
+        raise ValueError(kernel)
+    return idx + B * per
+
+
+def cpu_baseline(w, xis, x0s, P, seconds):
+    """Time the oracle's online phase (assembly, two-grid setup, PCG) on the
+    host for a bounded sample of the same queries."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle import fem, problem as oprob, pcg as opcg, twogrid
+
+    done, t_total, iters = 0, 0.0, []
+    with threadpool_limits(limits=1):
+        while done < len(xis) and (t_total < seconds or done == 0):
+            t = time.perf_counter()
+            K = oprob.stiffness(w, xis[done])
+            f = fem.traction_load(w.dim, w.N)
+            M = twogrid.TwoGrid(K, P, w.omega, w.nu_pre, w.nu_post,
+                                precision="fp32" if w.precision == "mixed" else "fp64")
+            r = opcg.pcg(K, f, x0s[done], M, tol=w.tol, maxit=5000,
+                         beta="pr" if w.precision == "mixed" else "fr")
+            t_total += time.perf_counter() - t
+            iters.append(r.iters)
+            done += 1
+    return {"value": done / t_total, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} query solve(s) of workload {w.name} (assembly + two-grid setup + "
+                      f"PCG, oracle iterations {iters}) in {t_total:.1f} s on 1 host thread"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2", help="c1, c2, c3, c4a, c4b, c4c, c5")
+    ap.add_argument("--queries", type=int, default=8, help="distinct query parameters cycled")
+    ap.add_argument("--kernel", default="sweep", choices=sorted(KERNELS),
+                    help="kernel timed live for the roofline entry")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver "
+              "shards over independent queries with no collectives; run one process per GPU.",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    from paper_2207_02543_amd import capi as L, inputs as I, pipeline
+
+    w = I.WORKLOADS[args.workload]
+    mixed = w.precision == "mixed"
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    log(f"[bench] workload {w.name}: dim {w.dim} N {w.N} n {w.n} k {w.k} batch {w.batch} "
+        f"{w.precision}")
+
+    # ---- offline phase and query inputs (untimed) -----------------------------
+    prob = pipeline.Problem(w, dev)
+    t0 = time.perf_counter()
+    P, lam, U, train_iters = pipeline.offline_basis(prob)
+    torch.cuda.synchronize()
+    log(f"[bench] offline: {w.n_train} training solves ({sum(train_iters)} iterations) + POD "
+        f"in {time.perf_counter() - t0:.1f} s; lambda_k/lambda_1 = "
+        f"{float(lam[w.k - 1] / lam[0]):.2e}")
+    del U
+    Q = max(args.queries, w.batch)
+    xis = I.query_xis(w, Q)
+    t0 = time.perf_counter()
+    ustar = pipeline.exact_solutions(prob, xis, P, rtol=1e-12)
+    g = torch.tensor(np.stack([I.noise(w, j) for j in range(Q)]), device=dev)
+    x0 = torch.stack([I.warm_start(ustar[j], g[j], w.noise) for j in range(Q)])
+    xi_d = torch.tensor(xis, device=dev)
+    torch.cuda.synchronize()
+    log(f"[bench] {Q} query warm starts in {time.perf_counter() - t0:.1f} s")
+
+    # ---- timed steps ------------------------------------------------------------
+    sysm = prob.alloc_system(w.batch, fp32=mixed)
+    u = torch.empty(w.batch, w.n, dtype=torch.float64, device=dev)
+    precision = L.MIXED if mixed else L.FP64
+    per_call = 6
+    timer = L.pod2g_timer_create(KERNELS[args.kernel], per_call * args.steps, per_call)
+    stats = {"iters": [], "relres": [], "err": []}
+
+    def step(i, timed):
+        idx = [(i * w.batch + b) % Q for b in range(w.batch)]
+        sysm.xi.copy_(xi_d[idx])
+        prob.assemble(sysm)
+        prec = prob.setup(sysm, P, precision=precision)
+        u.copy_(x0[idx])
+        ret, its, rr, st = prob.solve(sysm, prec, u, timer=timer if timed else None)
+        if ret != L.OK:
+            raise L.Pod2gError(ret, f"step {i}: statuses {st}")
+        return idx, its, rr
+
+    for i in range(args.warmup):
+        step(i, False)
+    torch.cuda.synchronize()
+    L.pod2g_timer_reset(timer)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        idx, its, rr = step(args.warmup + i, True)
+        stats["iters"] += its
+        stats["relres"] += rr
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    # accuracy of the last step against the tight FP64 solutions
+    for b, j in enumerate(idx):
+        stats["err"].append(float(torch.linalg.norm(u[b] - ustar[j]) / torch.linalg.norm(ustar[j])))
+    ms_k, cnt = L.pod2g_timer_elapsed(timer)
+    L.pod2g_timer_destroy(timer)
+
+    solves = args.steps * w.batch
+    value = solves / dt
+    avg_s = (ms_k / cnt) / 1e3 if cnt else float("nan")
+    nbytes = kernel_bytes(w, args.kernel, mixed)
+    achieved = nbytes / avg_s / 1e9 if cnt else None
+    log(f"[bench] {solves} solves in {dt:.3f} s; mean iterations "
+        f"{np.mean(stats['iters']):.1f}; {args.kernel}: {cnt} timed launches, "
+        f"{avg_s * 1e6:.1f} us avg, {nbytes / 1e6:.2f} MB -> {achieved:.0f} GB/s")
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64+f32" if mixed else "f64", "data": "synthetic",
+        "config": {"workload": w.name,
+                   "problem": f"{w.dim}D {'Q4 plane stress' if w.dim == 2 else 'Hex8'} "
+                              f"{'x'.join([str(w.N)] * w.dim)}, {w.n_terms} field terms",
+                   "n": w.n, "k": w.k, "n_train": w.n_train, "batch": w.batch,
+                   "precision": w.precision, "tol": w.tol, "omega": w.omega,
+                   "sweeps": [w.nu_pre, w.nu_post], "queries": Q,
+                   "iters_mean": float(np.mean(stats["iters"])),
+                   "relres_max": float(np.max(stats["relres"])),
+                   "err_vs_fp64_max": float(np.max(stats["err"]))},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                     "kernel": args.kernel, "bytes_per_launch": nbytes,
+                     "avg_launch_us": avg_s * 1e6, "launches_timed": cnt},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the oracle on the host ...")
+        x0h = x0.cpu().numpy()
+        Ph = np.ascontiguousarray(P.cpu().numpy().T)
+        result["cpu_baseline"] = cpu_baseline(w, xis, x0h, Ph, args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -183,13 +183,47 @@ int pcg_solve(const pod2g_pattern *pat, const double *vals, int batch,
               int *iters_h, double *relres_h, int *status_h,
               void *work, size_t bytes, hipStream_t stream);
 
+/* ---- live kernel timing ----------------------------------------------------
+ * A timer holds `capacity` pairs of HIP events (created by
+ * pod2g_timer_create, released by pod2g_timer_destroy).  pcg_solve_timed
+ * records one pair around each launch of the selected kernel until the
+ * pairs run out; pod2g_timer_elapsed (synchronous) returns the summed
+ * duration in ms and the number of timed launches.  Kernel ids:           */
+#define POD2G_TK_SPMV_PQ     1   /* q = K p with p^T q (outer SpMV)            */
+#define POD2G_TK_SWEEP       2   /* damped-Jacobi sweep inside the cycle       */
+#define POD2G_TK_SWEEP_FINAL 3   /* last post-sweep with r^T s                 */
+#define POD2G_TK_RESTRICT    4   /* residual + restriction + coarse solve      */
+#define POD2G_TK_PROLONG     5   /* prolongation and correction                */
+#define POD2G_TK_UPDATE      6   /* u, r updates with ||r||^2                  */
+
+typedef struct pod2g_timer {
+  int kernel;        /* POD2G_TK_* */
+  int capacity;      /* event pairs */
+  int count;         /* pairs recorded */
+  int per_call;      /* at most this many pairs per pcg_solve_timed call
+                        (the first launches of a solve, before any instance
+                        can have converged) */
+  hipEvent_t *start, *stop;   /* host arrays of events, owned by the timer */
+} pod2g_timer;
+
+int pod2g_timer_create(int kernel, int capacity, int per_call, pod2g_timer *out);
+int pod2g_timer_reset(pod2g_timer *t);
+int pod2g_timer_elapsed(const pod2g_timer *t, double *ms_total_h, int *count_h);
+int pod2g_timer_destroy(pod2g_timer *t);
+/* pcg_solve with a timer (NULL: identical to pcg_solve).                    */
+int pcg_solve_timed(const pod2g_pattern *pat, const double *vals, int batch,
+                    const pod2g_prec *prec, const double *f, double *u,
+                    double rtol, int maxit, int beta,
+                    int *iters_h, double *relres_h, int *status_h,
+                    void *work, size_t bytes, pod2g_timer *timer, hipStream_t stream);
+
 /* ---- single kernels (measurement and parity checks) ---------------------
  * y_b = K_b x_b (FP64).  Asynchronous.                                      */
 int pod2g_spmv(const pod2g_pattern *pat, const double *vals, int batch,
                const double *x, double *y, hipStream_t stream);
 /* nsweeps damped-Jacobi sweeps x <- x + omega D^-1 (b - K x) (the relaxation
- * of Alg. 2) in place on x, using tmp ([batch][n]) as the second buffer.
- * Asynchronous.                                                              */
+ * of Alg. 2) in place on x, using tmp ([batch][n]) as the second buffer;
+ * the same kernel as the cycle's sweeps.  Asynchronous.                     */
 int pod2g_jacobi(const pod2g_pattern *pat, const double *vals, const double *dinv,
                  int batch, double omega, int nsweeps, const double *b, double *x,
                  double *tmp, hipStream_t stream);

@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpod2g.so")
 
 OK, EINVAL, ESIZE, EHIP, ENOTSPD, ESMOOTHER, EMAXIT, EBREAKDOWN, ENAN = 0, -1, -2, -3, -4, -5, -6, -7, -8
+TK_SPMV_PQ, TK_SWEEP, TK_SWEEP_FINAL, TK_RESTRICT, TK_PROLONG, TK_UPDATE = 1, 2, 3, 4, 5, 6
 FP64, MIXED = 0, 1
 BETA_FR, BETA_PR = 0, 1
 MAX_K = 64
@@ -44,6 +45,11 @@ class Prec(C.Structure):
                 ("P", C.c_void_p), ("P32", C.c_void_p), ("dinv32", C.c_void_p),
                 ("KP", C.c_void_p), ("L", C.c_void_p), ("lam", C.c_void_p),
                 ("status", C.c_void_p)]
+
+
+class Timer(C.Structure):
+    _fields_ = [("kernel", C.c_int), ("capacity", C.c_int), ("count", C.c_int),
+                ("per_call", C.c_int), ("start", C.c_void_p), ("stop", C.c_void_p)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -77,6 +83,14 @@ _f = {
     "pcg_solve_bytes": _sig("pcg_solve_bytes", _sz, [_PP, _i, _i, _i]),
     "pcg_solve": _sig("pcg_solve", _i, [_PP, _vp, _i, _PR, _vp, _vp, _d, _i, _i, C.POINTER(_i),
                                         C.POINTER(_d), C.POINTER(_i), _vp, _sz, _vp]),
+    "pcg_solve_timed": _sig("pcg_solve_timed", _i, [_PP, _vp, _i, _PR, _vp, _vp, _d, _i, _i,
+                                                    C.POINTER(_i), C.POINTER(_d), C.POINTER(_i),
+                                                    _vp, _sz, C.POINTER(Timer), _vp]),
+    "pod2g_timer_create": _sig("pod2g_timer_create", _i, [_i, _i, _i, C.POINTER(Timer)]),
+    "pod2g_timer_reset": _sig("pod2g_timer_reset", _i, [C.POINTER(Timer)]),
+    "pod2g_timer_elapsed": _sig("pod2g_timer_elapsed", _i, [C.POINTER(Timer), C.POINTER(_d),
+                                                            C.POINTER(_i)]),
+    "pod2g_timer_destroy": _sig("pod2g_timer_destroy", _i, [C.POINTER(Timer)]),
     "pod2g_spmv": _sig("pod2g_spmv", _i, [_PP, _vp, _i, _vp, _vp, _vp]),
     "pod2g_jacobi": _sig("pod2g_jacobi", _i, [_PP, _vp, _vp, _i, _d, _i, _vp, _vp, _vp, _vp]),
     "pod2g_pod_basis_bytes": _sig("pod2g_pod_basis_bytes", _sz, [_i, _i, _i]),
@@ -179,6 +193,40 @@ def pcg_solve(pat, vals, batch, prec, f, u, rtol, maxit, beta, work, nbytes, str
                           _ptr(f), _ptr(u), float(rtol), int(maxit), int(beta), it, rr, st,
                           _ptr(work), nbytes, _stream(stream))
     return ret, list(it), list(rr), list(st)
+
+
+def pcg_solve_timed(pat, vals, batch, prec, f, u, rtol, maxit, beta, work, nbytes, timer,
+                    stream=None):
+    it = (C.c_int * batch)()
+    rr = (C.c_double * batch)()
+    st = (C.c_int * batch)()
+    ret = _f["pcg_solve_timed"](C.byref(pat), _ptr(vals), batch,
+                                C.byref(prec) if prec is not None else None, _ptr(f), _ptr(u),
+                                float(rtol), int(maxit), int(beta), it, rr, st, _ptr(work), nbytes,
+                                C.byref(timer) if timer is not None else None, _stream(stream))
+    return ret, list(it), list(rr), list(st)
+
+
+def pod2g_timer_create(kernel: int, capacity: int, per_call: int) -> Timer:
+    t = Timer()
+    check(_f["pod2g_timer_create"](kernel, capacity, per_call, C.byref(t)), "pod2g_timer_create")
+    return t
+
+
+def pod2g_timer_reset(t: Timer) -> int:
+    return _f["pod2g_timer_reset"](C.byref(t))
+
+
+def pod2g_timer_elapsed(t: Timer):
+    """(total ms, timed launches); synchronous."""
+    ms = C.c_double()
+    cnt = C.c_int()
+    check(_f["pod2g_timer_elapsed"](C.byref(t), C.byref(ms), C.byref(cnt)), "pod2g_timer_elapsed")
+    return ms.value, cnt.value
+
+
+def pod2g_timer_destroy(t: Timer) -> int:
+    return _f["pod2g_timer_destroy"](C.byref(t))
 
 
 def pod2g_spmv(pat, vals, batch, x, y, stream=None) -> int:

@@ -135,8 +135,8 @@ __global__ void __launch_bounds__(NT) k_sweep(Ctx c, const T *__restrict__ xin, 
   __shared__ double lds[2 * NWAVE];
   __shared__ int flag;
   const int b = inst_id();
-  InstState *st = c.st + b;
-  if (st->done) return;
+  InstState *st = c.st ? c.st + b : nullptr;   // null: standalone sweeps
+  if (st && st->done) return;
   const int blk = xcd_block(blockIdx.x, c.nb);
   const int row = blk * NT + threadIdx.x;
   const size_t off = (size_t)b * c.n;
@@ -444,6 +444,24 @@ __global__ void __launch_bounds__(NT) k_replace(Ctx c, const int *__restrict__ f
 // ---------------------------------------------------------------------------
 static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Records an event pair around the launches of the timer's kernel.
+struct TimeScope {
+  pod2g_timer *tm;
+  hipStream_t s;
+  bool on;
+  TimeScope(pod2g_timer *t, int id, hipStream_t st) : tm(t), s(st) {
+    on = tm && tm->kernel == id && tm->count < tm->capacity && tm->per_call > 0;
+    if (on) tm->per_call--;
+    if (on) (void)hipEventRecord(tm->start[tm->count], s);
+  }
+  ~TimeScope() {
+    if (on) {
+      (void)hipEventRecord(tm->stop[tm->count], s);
+      tm->count++;
+    }
+  }
+};
+
 struct Layout {
   size_t st, ec, part, vec, vec32, flags, total;
 };
@@ -514,22 +532,32 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
 // the first pre-relaxation sweep when nu_pre >= 1 (made by the producer of
 // r).  With want_dot the last kernel also forms rho and beta.
 template <int DIM, typename T>
-static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, int want_dot) {
+static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, int want_dot,
+                         pod2g_timer *tm) {
   dim3 grid(c.nb, c.batch), blk(NT);
   T *xa = (T *)c.xa, *xb = (T *)c.xb;
   T *cur = xa, *oth = xb;
   const bool have_x = pr->nu_pre >= 1;
   for (int i = 1; i < pr->nu_pre; ++i) {
-    hipLaunchKernelGGL((k_sweep<DIM, T, false>), grid, blk, 0, stream, c, cur, oth, 0);
+    {
+      TimeScope ts(tm, POD2G_TK_SWEEP, stream);
+      hipLaunchKernelGGL((k_sweep<DIM, T, false>), grid, blk, 0, stream, c, cur, oth, 0);
+    }
     T *t = cur; cur = oth; oth = t;
   }
   bool have = have_x;
   if (c.k > 0) {
-    if (have)
-      hipLaunchKernelGGL((k_restrict<DIM, T, false>), grid, blk, 0, stream, c, cur);
-    else
-      hipLaunchKernelGGL((k_restrict<DIM, T, true>), grid, blk, 0, stream, c, (const T *)nullptr);
-    hipLaunchKernelGGL((k_prolong<T>), grid, blk, 0, stream, c, have ? (const T *)cur : (const T *)nullptr, oth);
+    {
+      TimeScope ts(tm, POD2G_TK_RESTRICT, stream);
+      if (have)
+        hipLaunchKernelGGL((k_restrict<DIM, T, false>), grid, blk, 0, stream, c, cur);
+      else
+        hipLaunchKernelGGL((k_restrict<DIM, T, true>), grid, blk, 0, stream, c, (const T *)nullptr);
+    }
+    {
+      TimeScope ts(tm, POD2G_TK_PROLONG, stream);
+      hipLaunchKernelGGL((k_prolong<T>), grid, blk, 0, stream, c, have ? (const T *)cur : (const T *)nullptr, oth);
+    }
     T *t = cur; cur = oth; oth = t;
     have = true;
   }
@@ -551,10 +579,13 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
   }
   for (int i = 0; i < pr->nu_post; ++i) {
     const bool fin = (i == pr->nu_post - 1);
-    if (fin)
+    if (fin) {
+      TimeScope ts(tm, POD2G_TK_SWEEP_FINAL, stream);
       hipLaunchKernelGGL((k_sweep<DIM, T, true>), grid, blk, 0, stream, c, cur, oth, want_dot);
-    else
+    } else {
+      TimeScope ts(tm, POD2G_TK_SWEEP, stream);
       hipLaunchKernelGGL((k_sweep<DIM, T, false>), grid, blk, 0, stream, c, cur, oth, 0);
+    }
     T *t = cur; cur = oth; oth = t;
   }
   if (pr->nu_post == 0)
@@ -562,9 +593,10 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
 }
 
 template <int DIM>
-static void launch_cycle_any(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, int want_dot) {
-  if (pr->precision == POD2G_MIXED) launch_cycle<DIM, float>(c, pr, stream, want_dot);
-  else launch_cycle<DIM, double>(c, pr, stream, want_dot);
+static void launch_cycle_any(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, int want_dot,
+                             pod2g_timer *tm) {
+  if (pr->precision == POD2G_MIXED) launch_cycle<DIM, float>(c, pr, stream, want_dot, tm);
+  else launch_cycle<DIM, double>(c, pr, stream, want_dot, tm);
 }
 
 template <int DIM>
@@ -576,18 +608,27 @@ static void launch_first(const Ctx &c, const pod2g_prec *pr, hipStream_t stream)
 }
 
 template <int DIM>
-static void launch_iteration(const Ctx &c, const pod2g_prec *pr, hipStream_t stream) {
+static void launch_iteration(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, pod2g_timer *tm) {
   dim3 grid(c.nb, c.batch), blk(NT);
-  hipLaunchKernelGGL(k_spmv_pq<DIM>, grid, blk, 0, stream, c);
+  {
+    TimeScope ts(tm, POD2G_TK_SPMV_PQ, stream);
+    hipLaunchKernelGGL(k_spmv_pq<DIM>, grid, blk, 0, stream, c);
+  }
   if (pr) {
     const int mode = pr->nu_pre >= 1 ? 1 : 2;
-    if (pr->precision == POD2G_MIXED) hipLaunchKernelGGL(k_update<float>, grid, blk, 0, stream, c, mode);
-    else hipLaunchKernelGGL(k_update<double>, grid, blk, 0, stream, c, mode);
-    launch_cycle_any<DIM>(c, pr, stream, 1);
+    {
+      TimeScope ts(tm, POD2G_TK_UPDATE, stream);
+      if (pr->precision == POD2G_MIXED) hipLaunchKernelGGL(k_update<float>, grid, blk, 0, stream, c, mode);
+      else hipLaunchKernelGGL(k_update<double>, grid, blk, 0, stream, c, mode);
+    }
+    launch_cycle_any<DIM>(c, pr, stream, 1, tm);
     hipLaunchKernelGGL(k_pupdate, grid, blk, 0, stream, c, (const double *)c.s);
     hipLaunchKernelGGL(k_rescale, dim3(ceil_div(c.batch, 64)), dim3(64), 0, stream, c);
   } else {
-    hipLaunchKernelGGL(k_update<double>, grid, blk, 0, stream, c, 0);
+    {
+      TimeScope ts(tm, POD2G_TK_UPDATE, stream);
+      hipLaunchKernelGGL(k_update<double>, grid, blk, 0, stream, c, 0);
+    }
     hipLaunchKernelGGL(k_pupdate, grid, blk, 0, stream, c, (const double *)c.r);
   }
 }
@@ -602,7 +643,8 @@ static int read_states(const Ctx &c, std::vector<InstState> &h, hipStream_t stre
 
 template <int DIM>
 static int pcg_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int beta,
-                   int *iters_h, double *relres_h, int *status_h, hipStream_t stream) {
+                   int *iters_h, double *relres_h, int *status_h, pod2g_timer *tm,
+                   hipStream_t stream) {
   dim3 grid(c.nb, c.batch), blk(NT);
   hipLaunchKernelGGL(k_state_init, dim3(ceil_div(c.batch, 64)), dim3(64), 0, stream, c.st, c.batch,
                      rtol, maxit, beta, pr ? (const int *)pr->status : (const int *)nullptr);
@@ -610,7 +652,7 @@ static int pcg_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int bet
   auto start_cycle = [&]() {
     if (pr) {
       launch_first<DIM>(c, pr, stream);
-      launch_cycle_any<DIM>(c, pr, stream, 1);
+      launch_cycle_any<DIM>(c, pr, stream, 1, tm);
       hipLaunchKernelGGL(k_pupdate, grid, blk, 0, stream, c, (const double *)c.s);
     } else {
       // restart flag: beta = 0 -> p = r
@@ -629,7 +671,7 @@ static int pcg_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int bet
   }
   int chunk = 4;
   for (int guard = 0; guard < 1000000; ++guard) {
-    for (int i = 0; i < chunk; ++i) launch_iteration<DIM>(c, pr, stream);
+    for (int i = 0; i < chunk; ++i) launch_iteration<DIM>(c, pr, stream, tm);
     POD2G_HIP_CHECK(hipGetLastError());
     int st = read_states(c, h, stream);
     if (st) return st;
@@ -682,21 +724,6 @@ __global__ void __launch_bounds__(NT) k_spmv(int n, int nn, int nb, long long vs
   y[off + row] = row_dot<DIM>(colblk, vals + (size_t)b * vstride, x + off, row, row / DIM, n, nn);
 }
 
-template <int DIM>
-__global__ void __launch_bounds__(NT) k_jacobi(int n, int nn, int nb, long long vstride,
-                                               const int *__restrict__ colblk,
-                                               const double *__restrict__ vals,
-                                               const double *__restrict__ dinv, double omega,
-                                               const double *__restrict__ rhs,
-                                               const double *__restrict__ x, double *__restrict__ y) {
-  const int b = blockIdx.y;
-  const int row = xcd_block(blockIdx.x, nb) * NT + threadIdx.x;
-  if (row >= n) return;
-  const size_t off = (size_t)b * n;
-  const double kx = row_dot<DIM>(colblk, vals + (size_t)b * vstride, x + off, row, row / DIM, n, nn);
-  y[off + row] = x[off + row] + omega * dinv[off + row] * (rhs[off + row] - kx);
-}
-
 }  // namespace pod2g
 
 using namespace pod2g;
@@ -737,9 +764,10 @@ static int check_prec(const pod2g_prec *pr) {
   return POD2G_OK;
 }
 
-int pcg_solve(const pod2g_pattern *pat, const double *vals, int batch, const pod2g_prec *prec,
-              const double *f, double *u, double rtol, int maxit, int beta, int *iters_h,
-              double *relres_h, int *status_h, void *work, size_t bytes, hipStream_t stream) {
+int pcg_solve_timed(const pod2g_pattern *pat, const double *vals, int batch,
+                    const pod2g_prec *prec, const double *f, double *u, double rtol, int maxit,
+                    int beta, int *iters_h, double *relres_h, int *status_h, void *work,
+                    size_t bytes, pod2g_timer *timer, hipStream_t stream) {
   if (!pat || !vals || !f || !u || !work || batch < 1 || batch > 65535) return POD2G_EINVAL;
   if (!(rtol >= 0.0) || maxit < 0 || (beta != POD2G_BETA_FR && beta != POD2G_BETA_PR)) return POD2G_EINVAL;
   if (prec) {
@@ -750,8 +778,78 @@ int pcg_solve(const pod2g_pattern *pat, const double *vals, int batch, const pod
   if (bytes < pcg_solve_bytes(pat, batch, k, prec ? prec->precision : POD2G_FP64)) return POD2G_ESIZE;
   Ctx c;
   fill_ctx(c, pat, vals, batch, prec, f, u, work);
-  if (pat->mesh.dim == 2) return pcg_run<2>(c, prec, rtol, maxit, beta, iters_h, relres_h, status_h, stream);
-  return pcg_run<3>(c, prec, rtol, maxit, beta, iters_h, relres_h, status_h, stream);
+  // per_call counts down inside this call only
+  pod2g_timer tcopy;
+  pod2g_timer *tm = nullptr;
+  if (timer) { tcopy = *timer; tm = &tcopy; }
+  int ret;
+  if (pat->mesh.dim == 2)
+    ret = pcg_run<2>(c, prec, rtol, maxit, beta, iters_h, relres_h, status_h, tm, stream);
+  else
+    ret = pcg_run<3>(c, prec, rtol, maxit, beta, iters_h, relres_h, status_h, tm, stream);
+  if (timer) timer->count = tcopy.count;
+  return ret;
+}
+
+int pcg_solve(const pod2g_pattern *pat, const double *vals, int batch, const pod2g_prec *prec,
+              const double *f, double *u, double rtol, int maxit, int beta, int *iters_h,
+              double *relres_h, int *status_h, void *work, size_t bytes, hipStream_t stream) {
+  return pcg_solve_timed(pat, vals, batch, prec, f, u, rtol, maxit, beta, iters_h, relres_h,
+                         status_h, work, bytes, nullptr, stream);
+}
+
+int pod2g_timer_create(int kernel, int capacity, int per_call, pod2g_timer *out) {
+  if (!out || capacity < 1 || per_call < 1 || kernel < POD2G_TK_SPMV_PQ || kernel > POD2G_TK_UPDATE)
+    return POD2G_EINVAL;
+  pod2g_timer t;
+  t.kernel = kernel;
+  t.capacity = capacity;
+  t.count = 0;
+  t.per_call = per_call;
+  t.start = new hipEvent_t[capacity];
+  t.stop = new hipEvent_t[capacity];
+  for (int i = 0; i < capacity; ++i) {
+    if (hipEventCreate(&t.start[i]) != hipSuccess || hipEventCreate(&t.stop[i]) != hipSuccess) {
+      delete[] t.start;
+      delete[] t.stop;
+      return POD2G_EHIP;
+    }
+  }
+  *out = t;
+  return POD2G_OK;
+}
+
+int pod2g_timer_reset(pod2g_timer *t) {
+  if (!t) return POD2G_EINVAL;
+  t->count = 0;
+  return POD2G_OK;
+}
+
+int pod2g_timer_elapsed(const pod2g_timer *t, double *ms_total_h, int *count_h) {
+  if (!t || !ms_total_h) return POD2G_EINVAL;
+  double tot = 0.0;
+  for (int i = 0; i < t->count; ++i) {
+    POD2G_HIP_CHECK(hipEventSynchronize(t->stop[i]));
+    float ms = 0.f;
+    POD2G_HIP_CHECK(hipEventElapsedTime(&ms, t->start[i], t->stop[i]));
+    tot += ms;
+  }
+  *ms_total_h = tot;
+  if (count_h) *count_h = t->count;
+  return POD2G_OK;
+}
+
+int pod2g_timer_destroy(pod2g_timer *t) {
+  if (!t || !t->start) return POD2G_EINVAL;
+  for (int i = 0; i < t->capacity; ++i) {
+    (void)hipEventDestroy(t->start[i]);
+    (void)hipEventDestroy(t->stop[i]);
+  }
+  delete[] t->start;
+  delete[] t->stop;
+  t->start = t->stop = nullptr;
+  t->capacity = t->count = 0;
+  return POD2G_OK;
 }
 
 // s = B r: the same kernels as inside PCG, on a scratch state.
@@ -779,10 +877,10 @@ int pod2g_apply(const pod2g_prec *prec, const double *r, double *s, void *work, 
                      (const double *)nullptr);
   if (prec->pat.mesh.dim == 2) {
     launch_first<2>(c, prec, stream);
-    launch_cycle_any<2>(c, prec, stream, 0);
+    launch_cycle_any<2>(c, prec, stream, 0, nullptr);
   } else {
     launch_first<3>(c, prec, stream);
-    launch_cycle_any<3>(c, prec, stream, 0);
+    launch_cycle_any<3>(c, prec, stream, 0, nullptr);
   }
   POD2G_HIP_CHECK(hipGetLastError());
   return POD2G_OK;
@@ -808,16 +906,25 @@ int pod2g_jacobi(const pod2g_pattern *pat, const double *vals, const double *din
                  hipStream_t stream) {
   if (!pat || !vals || !dinv || !b || !x || !tmp || batch < 1 || batch > 65535 || nsweeps < 0)
     return POD2G_EINVAL;
-  const int nb = ceil_div(pat->n, NT);
-  dim3 grid(nb, batch);
+  Ctx c;
+  memset(&c, 0, sizeof(c));
+  c.n = pat->n;
+  c.nn = pat->n_nodes;
+  c.batch = batch;
+  c.nb = ceil_div(pat->n, NT);
+  c.vstride = pat->nvals;
+  c.colblk = pat->colblk;
+  c.svals = vals;
+  c.sdinv = dinv;
+  c.omega = omega;
+  c.r = const_cast<double *>(b);   // the sweep's right-hand side
+  dim3 grid(c.nb, batch);
   double *cur = x, *oth = tmp;
   for (int i = 0; i < nsweeps; ++i) {
     if (pat->mesh.dim == 2)
-      hipLaunchKernelGGL(k_jacobi<2>, grid, dim3(NT), 0, stream, pat->n, pat->n_nodes, nb,
-                         pat->nvals, pat->colblk, vals, dinv, omega, b, cur, oth);
+      hipLaunchKernelGGL((k_sweep<2, double, false>), grid, dim3(NT), 0, stream, c, cur, oth, 0);
     else
-      hipLaunchKernelGGL(k_jacobi<3>, grid, dim3(NT), 0, stream, pat->n, pat->n_nodes, nb,
-                         pat->nvals, pat->colblk, vals, dinv, omega, b, cur, oth);
+      hipLaunchKernelGGL((k_sweep<3, double, false>), grid, dim3(NT), 0, stream, c, cur, oth, 0);
     double *t = cur; cur = oth; oth = t;
   }
   if (cur != x)

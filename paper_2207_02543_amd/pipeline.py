@@ -109,15 +109,19 @@ class Problem:
 
     # -- solve --------------------------------------------------------------------
     def solve(self, sysm: System, prec, u, rtol=None, maxit=5000, beta=None, key="pcg",
-              stream=None):
+              timer=None, stream=None):
         k = prec.k if prec is not None else 0
         precision = prec.precision if prec is not None else L.FP64
         if beta is None:
             beta = L.BETA_PR if precision == L.MIXED else L.BETA_FR
         nb = L.pcg_solve_bytes(self.pat, sysm.batch, k, precision)
         wk = self.work(key, nb)
-        return L.pcg_solve(self.pat, sysm.vals, sysm.batch, prec, sysm.f, u,
-                           self.w.tol if rtol is None else rtol, maxit, beta, wk, nb, stream)
+        rtol = self.w.tol if rtol is None else rtol
+        if timer is not None:
+            return L.pcg_solve_timed(self.pat, sysm.vals, sysm.batch, prec, sysm.f, u, rtol, maxit,
+                                     beta, wk, nb, timer, stream)
+        return L.pcg_solve(self.pat, sysm.vals, sysm.batch, prec, sysm.f, u, rtol, maxit, beta,
+                           wk, nb, stream)
 
     def apply(self, prec, r, s, stream=None):
         nb = L.pod2g_apply_bytes(prec)

@@ -277,9 +277,10 @@ def test_pod_basis_matches_oracle(env):
     np.testing.assert_allclose(Pg @ Pg.T, P @ P.T, atol=1e-8)
     # odd snapshot count and rank-deficient input
     Pg2, _ = pipeline.pod_basis(Ud[:7].contiguous(), 5)
+    P2 = Pg2.cpu().numpy().T
     Q = np.linalg.svd(U[:, :7], full_matrices=False)[0][:, :5]
-    np.testing.assert_allclose(Pg2.cpu().numpy().T @ Pg2.cpu().numpy(), np.eye(5), atol=1e-6)
-    np.testing.assert_allclose(Pg2.cpu().numpy().T @ (Q @ Q.T), Pg2.cpu().numpy().T, atol=1e-6)
+    np.testing.assert_allclose(P2.T @ P2, np.eye(5), atol=1e-6)
+    np.testing.assert_allclose(P2 @ P2.T, Q @ Q.T, atol=1e-6)
     Ur = torch.ones(4, w.n, dtype=torch.float64, device="cuda")
     with pytest.raises(capi.Pod2gError):
         pipeline.pod_basis(Ur, 2)
