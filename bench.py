@@ -91,6 +91,11 @@ def main(argv=None):
                     help="kernel timed live for the roofline entry")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--chunk", type=int, default=8,
+                    help="PCG iterations per captured graph launch (0: no graph, eager launches)")
+    ap.add_argument("--roi", action="store_true",
+                    help="bracket the timed steps with roctxProfilerResume/Pause (for "
+                         "rocprofv3 --selected-regions)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver "
@@ -132,9 +137,15 @@ def main(argv=None):
     sysm = prob.alloc_system(w.batch, fp32=mixed)
     u = torch.empty(w.batch, w.n, dtype=torch.float64, device=dev)
     precision = L.MIXED if mixed else L.FP64
-    per_call = 6
-    timer = L.pod2g_timer_create(KERNELS[args.kernel], per_call * args.steps, per_call)
+    timer = L.pod2g_timer_create(KERNELS[args.kernel], 6)
     stats = {"iters": [], "relres": [], "err": []}
+    plan = None
+    if args.chunk > 0:
+        # capture the PCG iterations once: every step reuses these buffers
+        sysm.xi.copy_(xi_d[:w.batch])
+        prob.assemble(sysm)
+        prec0 = prob.setup(sysm, P, precision=precision)
+        plan = prob.plan(sysm, prec0, u, chunk=args.chunk, timer=timer)
 
     def step(i, timed):
         idx = [(i * w.batch + b) % Q for b in range(w.batch)]
@@ -142,15 +153,24 @@ def main(argv=None):
         prob.assemble(sysm)
         prec = prob.setup(sysm, P, precision=precision)
         u.copy_(x0[idx])
-        ret, its, rr, st = prob.solve(sysm, prec, u, timer=timer if timed else None)
+        if plan is not None:
+            ret, its, rr, st = plan.solve(w.tol)
+        else:
+            ret, its, rr, st = prob.solve(sysm, prec, u, timer=timer if timed else None)
         if ret != L.OK:
             raise L.Pod2gError(ret, f"step {i}: statuses {st}")
         return idx, its, rr
 
+    roctx = None
+    if args.roi:
+        import ctypes
+        roctx = ctypes.CDLL("/opt/rocm/lib/librocprofiler-sdk-roctx.so")
     for i in range(args.warmup):
         step(i, False)
     torch.cuda.synchronize()
     L.pod2g_timer_reset(timer)
+    if roctx is not None:
+        roctx.roctxProfilerResume(0)
     t0 = time.perf_counter()
     for i in range(args.steps):
         idx, its, rr = step(args.warmup + i, True)
@@ -158,10 +178,14 @@ def main(argv=None):
         stats["relres"] += rr
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    if roctx is not None:
+        roctx.roctxProfilerPause(0)
     # accuracy of the last step against the tight FP64 solutions
     for b, j in enumerate(idx):
         stats["err"].append(float(torch.linalg.norm(u[b] - ustar[j]) / torch.linalg.norm(ustar[j])))
-    ms_k, cnt = L.pod2g_timer_elapsed(timer)
+    ms_k, cnt = timer.total_ms, timer.launches
+    if plan is not None:
+        plan.close()
     L.pod2g_timer_destroy(timer)
 
     solves = args.steps * w.batch
@@ -184,6 +208,7 @@ def main(argv=None):
                    "n": w.n, "k": w.k, "n_train": w.n_train, "batch": w.batch,
                    "precision": w.precision, "tol": w.tol, "omega": w.omega,
                    "sweeps": [w.nu_pre, w.nu_post], "queries": Q,
+                   "graph_chunk": args.chunk,
                    "iters_mean": float(np.mean(stats["iters"])),
                    "relres_max": float(np.max(stats["relres"])),
                    "err_vs_fp64_max": float(np.max(stats["err"]))},

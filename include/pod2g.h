@@ -184,11 +184,11 @@ int pcg_solve(const pod2g_pattern *pat, const double *vals, int batch,
               void *work, size_t bytes, hipStream_t stream);
 
 /* ---- live kernel timing ----------------------------------------------------
- * A timer holds `capacity` pairs of HIP events (created by
- * pod2g_timer_create, released by pod2g_timer_destroy).  pcg_solve_timed
- * records one pair around each launch of the selected kernel until the
- * pairs run out; pod2g_timer_elapsed (synchronous) returns the summed
- * duration in ms and the number of timed launches.  Kernel ids:           */
+ * A timer holds per_call pairs of HIP events (created by pod2g_timer_create,
+ * released by pod2g_timer_destroy).  A timed solve records one pair around
+ * each of the first per_call launches of the selected kernel and, if every
+ * instance was still iterating through the first chunk of iterations,
+ * adds their durations to total_ms / launches.  Kernel ids:                */
 #define POD2G_TK_SPMV_PQ     1   /* q = K p with p^T q (outer SpMV)            */
 #define POD2G_TK_SWEEP       2   /* damped-Jacobi sweep inside the cycle       */
 #define POD2G_TK_SWEEP_FINAL 3   /* last post-sweep with r^T s                 */
@@ -198,17 +198,14 @@ int pcg_solve(const pod2g_pattern *pat, const double *vals, int batch,
 
 typedef struct pod2g_timer {
   int kernel;        /* POD2G_TK_* */
-  int capacity;      /* event pairs */
-  int count;         /* pairs recorded */
-  int per_call;      /* at most this many pairs per pcg_solve_timed call
-                        (the first launches of a solve, before any instance
-                        can have converged) */
+  int per_call;      /* event pairs = launches timed per solve */
   hipEvent_t *start, *stop;   /* host arrays of events, owned by the timer */
+  double total_ms;   /* accumulated kernel time */
+  long long launches;/* accumulated timed launches */
 } pod2g_timer;
 
-int pod2g_timer_create(int kernel, int capacity, int per_call, pod2g_timer *out);
-int pod2g_timer_reset(pod2g_timer *t);
-int pod2g_timer_elapsed(const pod2g_timer *t, double *ms_total_h, int *count_h);
+int pod2g_timer_create(int kernel, int per_call, pod2g_timer *out);
+int pod2g_timer_reset(pod2g_timer *t);      /* zeroes total_ms and launches */
 int pod2g_timer_destroy(pod2g_timer *t);
 /* pcg_solve with a timer (NULL: identical to pcg_solve).                    */
 int pcg_solve_timed(const pod2g_pattern *pat, const double *vals, int batch,
@@ -216,6 +213,26 @@ int pcg_solve_timed(const pod2g_pattern *pat, const double *vals, int batch,
                     double rtol, int maxit, int beta,
                     int *iters_h, double *relres_h, int *status_h,
                     void *work, size_t bytes, pod2g_timer *timer, hipStream_t stream);
+
+/* ---- captured solve plans ---------------------------------------------------
+ * A plan captures `chunk` PCG iterations on fixed buffers (the arguments of
+ * pcg_solve: pattern, values, preconditioner workspace, f, u, solve
+ * workspace) into one HIP graph; pcg_plan_solve then runs the solve like
+ * pcg_solve but launches that graph once per chunk instead of the
+ * individual kernels, and checks convergence between chunks.  The plan
+ * stays valid while those buffers live and keep their sizes; their contents
+ * may change between solves (new theta, new warm start, new setup in the
+ * same setup workspace).  With a timer, the graph records the timer's
+ * events (the timer must outlive the plan).  pcg_plan_solve is synchronous
+ * and has pcg_solve's outputs and statuses.  Plans are host objects: create,
+ * solve and destroy them from one thread.                                   */
+typedef struct pod2g_plan pod2g_plan;
+int pcg_plan_create(const pod2g_pattern *pat, const double *vals, int batch,
+                    const pod2g_prec *prec, const double *f, double *u, int chunk,
+                    void *work, size_t bytes, pod2g_timer *timer, pod2g_plan **out);
+int pcg_plan_solve(pod2g_plan *plan, double rtol, int maxit, int beta,
+                   int *iters_h, double *relres_h, int *status_h, hipStream_t stream);
+int pcg_plan_destroy(pod2g_plan *plan);
 
 /* ---- single kernels (measurement and parity checks) ---------------------
  * y_b = K_b x_b (FP64).  Asynchronous.                                      */

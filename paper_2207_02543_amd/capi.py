@@ -48,8 +48,8 @@ class Prec(C.Structure):
 
 
 class Timer(C.Structure):
-    _fields_ = [("kernel", C.c_int), ("capacity", C.c_int), ("count", C.c_int),
-                ("per_call", C.c_int), ("start", C.c_void_p), ("stop", C.c_void_p)]
+    _fields_ = [("kernel", C.c_int), ("per_call", C.c_int), ("start", C.c_void_p),
+                ("stop", C.c_void_p), ("total_ms", C.c_double), ("launches", C.c_longlong)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -86,11 +86,14 @@ _f = {
     "pcg_solve_timed": _sig("pcg_solve_timed", _i, [_PP, _vp, _i, _PR, _vp, _vp, _d, _i, _i,
                                                     C.POINTER(_i), C.POINTER(_d), C.POINTER(_i),
                                                     _vp, _sz, C.POINTER(Timer), _vp]),
-    "pod2g_timer_create": _sig("pod2g_timer_create", _i, [_i, _i, _i, C.POINTER(Timer)]),
+    "pod2g_timer_create": _sig("pod2g_timer_create", _i, [_i, _i, C.POINTER(Timer)]),
     "pod2g_timer_reset": _sig("pod2g_timer_reset", _i, [C.POINTER(Timer)]),
-    "pod2g_timer_elapsed": _sig("pod2g_timer_elapsed", _i, [C.POINTER(Timer), C.POINTER(_d),
-                                                            C.POINTER(_i)]),
     "pod2g_timer_destroy": _sig("pod2g_timer_destroy", _i, [C.POINTER(Timer)]),
+    "pcg_plan_create": _sig("pcg_plan_create", _i, [_PP, _vp, _i, _PR, _vp, _vp, _i, _vp, _sz,
+                                                    C.POINTER(Timer), C.POINTER(_vp)]),
+    "pcg_plan_solve": _sig("pcg_plan_solve", _i, [_vp, _d, _i, _i, C.POINTER(_i), C.POINTER(_d),
+                                                  C.POINTER(_i), _vp]),
+    "pcg_plan_destroy": _sig("pcg_plan_destroy", _i, [_vp]),
     "pod2g_spmv": _sig("pod2g_spmv", _i, [_PP, _vp, _i, _vp, _vp, _vp]),
     "pod2g_jacobi": _sig("pod2g_jacobi", _i, [_PP, _vp, _vp, _i, _d, _i, _vp, _vp, _vp, _vp]),
     "pod2g_pod_basis_bytes": _sig("pod2g_pod_basis_bytes", _sz, [_i, _i, _i]),
@@ -207,9 +210,9 @@ def pcg_solve_timed(pat, vals, batch, prec, f, u, rtol, maxit, beta, work, nbyte
     return ret, list(it), list(rr), list(st)
 
 
-def pod2g_timer_create(kernel: int, capacity: int, per_call: int) -> Timer:
+def pod2g_timer_create(kernel: int, per_call: int) -> Timer:
     t = Timer()
-    check(_f["pod2g_timer_create"](kernel, capacity, per_call, C.byref(t)), "pod2g_timer_create")
+    check(_f["pod2g_timer_create"](kernel, per_call, C.byref(t)), "pod2g_timer_create")
     return t
 
 
@@ -217,16 +220,31 @@ def pod2g_timer_reset(t: Timer) -> int:
     return _f["pod2g_timer_reset"](C.byref(t))
 
 
-def pod2g_timer_elapsed(t: Timer):
-    """(total ms, timed launches); synchronous."""
-    ms = C.c_double()
-    cnt = C.c_int()
-    check(_f["pod2g_timer_elapsed"](C.byref(t), C.byref(ms), C.byref(cnt)), "pod2g_timer_elapsed")
-    return ms.value, cnt.value
-
-
 def pod2g_timer_destroy(t: Timer) -> int:
     return _f["pod2g_timer_destroy"](C.byref(t))
+
+
+def pcg_plan_create(pat, vals, batch, prec, f, u, chunk, work, nbytes, timer=None):
+    """Returns an opaque plan handle (int) or raises Pod2gError."""
+    h = C.c_void_p()
+    check(_f["pcg_plan_create"](C.byref(pat), _ptr(vals), batch,
+                                C.byref(prec) if prec is not None else None, _ptr(f), _ptr(u),
+                                chunk, _ptr(work), nbytes,
+                                C.byref(timer) if timer is not None else None, C.byref(h)),
+          "pcg_plan_create")
+    return h.value
+
+
+def pcg_plan_solve(plan, rtol, maxit, beta, batch, stream=None):
+    it = (C.c_int * batch)()
+    rr = (C.c_double * batch)()
+    st = (C.c_int * batch)()
+    ret = _f["pcg_plan_solve"](plan, float(rtol), int(maxit), int(beta), it, rr, st, _stream(stream))
+    return ret, list(it), list(rr), list(st)
+
+
+def pcg_plan_destroy(plan) -> int:
+    return _f["pcg_plan_destroy"](plan)
 
 
 def pod2g_spmv(pat, vals, batch, x, y, stream=None) -> int:

@@ -81,22 +81,32 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *lds /*[
   __syncthreads();
 }
 
-// Release this workgroup's partial results and report whether it is the
-// last of `total` workgroups to arrive at `counter`; the last one resets
-// the counter and may then read every partial (acquire).
+// Cross-workgroup partial results are written and read with agent-scope
+// relaxed atomics: the stores write through to the point of coherence
+// shared by all XCDs and the loads read from it, so no L2 writeback or
+// invalidation of unrelated data is needed.
+__device__ __forceinline__ void put_partial(double *p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double get_partial(const double *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Report whether this workgroup is the last of `total` to arrive at
+// `counter`.  Every wave first waits for its outstanding stores (so its
+// put_partial writes are complete before the counter moves); the last
+// workgroup resets the counter and may then get_partial every partial.
 __device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned total, int *lds_flag) {
-  __threadfence();
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(counter, 1u);
+    const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const int last = (prev == total - 1u);
-    if (last) *counter = 0u;
+    if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     *lds_flag = last;
   }
   __syncthreads();
-  const bool last = *lds_flag != 0;
-  if (last) __threadfence();
-  return last;
+  return *lds_flag != 0;
 }
 
 // Deterministic sum of m partials (strided by `stride` doubles) by one
@@ -104,7 +114,7 @@ __device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned total, i
 __device__ __forceinline__ double reduce_partials(const double *part, int m, int stride,
                                                   double *lds) {
   double v = 0.0;
-  for (int i = threadIdx.x; i < m; i += NT) v += part[(size_t)i * stride];
+  for (int i = threadIdx.x; i < m; i += NT) v += get_partial(part + (size_t)i * stride);
   return block_sum(v, lds);
 }
 

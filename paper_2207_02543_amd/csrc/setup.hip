@@ -143,14 +143,14 @@ __global__ void __launch_bounds__(NT) k_kc(int n, int k, int rows_per_wg, int nb
 #pragma unroll
   for (int m = 0; m < MAXE; ++m) {
     const int e = threadIdx.x + m * NT;
-    if (e < ntri) pb[(size_t)wg * ntri + e] = acc[m];
+    if (e < ntri) put_partial(pb + (size_t)wg * ntri + e, acc[m]);
   }
   if (!arrive_last(&pst[b].cnt[CNT_A], nbk, &flag)) return;
   // K_c into LDS (full symmetric), then Cholesky
   double *A = sp;  // k x k, row-major
   for (int e = threadIdx.x; e < ntri; e += NT) {
     double s = 0.0;
-    for (int w = 0; w < nbk; ++w) s += pb[(size_t)w * ntri + e];
+    for (int w = 0; w < nbk; ++w) s += get_partial(pb + (size_t)w * ntri + e);
     int j, l;
     tri_index(e, j, l);
     A[j * k + l] = s;
@@ -218,10 +218,10 @@ __global__ void __launch_bounds__(NT) k_power(int n, int nn, int nb, long long v
     yy = v * v;
   }
   yy = block_sum(yy, lds);
-  if (threadIdx.x == 0) part[(size_t)b * nb + blk] = yy;
+  if (threadIdx.x == 0) put_partial(part + (size_t)b * nb + blk, yy);
   if (!arrive_last(&pst[b].cnt[CNT_B], nb, &flag)) return;
   double s = 0.0;
-  for (int i = threadIdx.x; i < nb; i += NT) s += part[(size_t)b * nb + i];
+  for (int i = threadIdx.x; i < nb; i += NT) s += get_partial(part + (size_t)b * nb + i);
   s = block_sum(s, lds);
   if (threadIdx.x == 0) {
     pst[b].xnorm2 = s;

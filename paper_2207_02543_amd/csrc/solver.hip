@@ -90,7 +90,7 @@ __global__ void __launch_bounds__(NT) k_init(Ctx c, int have_prec) {
   }
   block_sum2(rr, ff, lds);
   double *part = c.part + ((size_t)b * c.nb + blk) * c.ps;
-  if (threadIdx.x == 0) { part[0] = rr; part[1] = ff; }
+  if (threadIdx.x == 0) { put_partial(part, rr); put_partial(part + 1, ff); }
   if (!arrive_last(&st->cnt[CNT_A], c.nb, &flag)) return;
   const double *p0 = c.part + (size_t)b * c.nb * c.ps;
   double trr = reduce_partials(p0, c.nb, c.ps, lds);
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(NT) k_sweep(Ctx c, const T *__restrict__ xin, 
   double dummy = 0.0;
   block_sum2(rs, dummy, lds);
   double *part = c.part + ((size_t)b * c.nb + blk) * c.ps;
-  if (threadIdx.x == 0) part[0] = rs;
+  if (threadIdx.x == 0) put_partial(part, rs);
   if (!arrive_last(&st->cnt[CNT_B], c.nb, &flag)) return;
   const double trs = reduce_partials(c.part + (size_t)b * c.nb * c.ps, c.nb, c.ps, lds);
   if (threadIdx.x == 0) {
@@ -212,13 +212,13 @@ __global__ void __launch_bounds__(NT) k_restrict(Ctx c, const T *__restrict__ x)
       if (rr < c.n) acc += (double)P[(size_t)j * c.n + rr] * rsh[lane + m * WAVE];
     }
     acc = wave_sum(acc);
-    if (lane == 0) part[j] = acc;
+    if (lane == 0) put_partial(part + j, acc);
   }
   if (!arrive_last(&st->cnt[CNT_C], c.nb, &flag)) return;
   const double *p0 = c.part + (size_t)b * c.nb * c.ps;
   for (int j = w; j < c.k; j += NWAVE) {
     double acc = 0.0;
-    for (int i = lane; i < c.nb; i += WAVE) acc += p0[(size_t)i * c.ps + j];
+    for (int i = lane; i < c.nb; i += WAVE) acc += get_partial(p0 + (size_t)i * c.ps + j);
     acc = wave_sum(acc);
     if (lane == 0) rc[j] = acc;
   }
@@ -279,7 +279,7 @@ __global__ void __launch_bounds__(NT) k_finalize(Ctx c, const T *__restrict__ x,
   if (!want_dot) return;
   double dummy = 0.0;
   block_sum2(rs, dummy, lds);
-  if (threadIdx.x == 0) c.part[((size_t)b * c.nb + blk) * c.ps] = rs;
+  if (threadIdx.x == 0) put_partial(c.part + ((size_t)b * c.nb + blk) * c.ps, rs);
   if (!arrive_last(&st->cnt[CNT_B], c.nb, &flag)) return;
   const double trs = reduce_partials(c.part + (size_t)b * c.nb * c.ps, c.nb, c.ps, lds);
   if (threadIdx.x == 0) {
@@ -313,7 +313,7 @@ __global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c) {
   }
   double dummy = 0.0;
   block_sum2(pq, dummy, lds);
-  if (threadIdx.x == 0) c.part[((size_t)b * c.nb + blk) * c.ps] = pq;
+  if (threadIdx.x == 0) put_partial(c.part + ((size_t)b * c.nb + blk) * c.ps, pq);
   if (!arrive_last(&st->cnt[CNT_D], c.nb, &flag)) return;
   const double g = reduce_partials(c.part + (size_t)b * c.nb * c.ps, c.nb, c.ps, lds);
   if (threadIdx.x == 0) {
@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode) {
   }
   block_sum2(rr, rs, lds);
   double *part = c.part + ((size_t)b * c.nb + blk) * c.ps;
-  if (threadIdx.x == 0) { part[0] = rr; part[1] = rs; }
+  if (threadIdx.x == 0) { put_partial(part, rr); put_partial(part + 1, rs); }
   if (!arrive_last(&st->cnt[CNT_E], c.nb, &flag)) return;
   const double *p0 = c.part + (size_t)b * c.nb * c.ps;
   const double trr = reduce_partials(p0, c.nb, c.ps, lds);
@@ -375,23 +375,18 @@ __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode) {
   }
 }
 
-// p = s + beta p; the next cycle's input scale takes effect.
+// p = s + beta p; the next cycle's input scale (from the current ||r||)
+// is set by one thread: no other workgroup reads it in this kernel.
 __global__ void __launch_bounds__(NT) k_pupdate(Ctx c, const double *__restrict__ s) {
   const int b = inst_id();
   InstState *st = c.st + b;
   if (st->done) return;
+  const double beta = st->beta;
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->scale = cycle_scale(c, st->rr);
   const int row = blockIdx.x * NT + threadIdx.x;
   if (row >= c.n) return;
   const size_t off = (size_t)b * c.n;
-  c.p[off + row] = s[off + row] + st->beta * c.p[off + row];
-}
-
-__global__ void k_rescale(Ctx c) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= c.batch) return;
-  InstState *st = c.st + b;
-  if (st->done) return;
-  st->scale = cycle_scale(c, st->rr);
+  c.p[off + row] = s[off + row] + beta * c.p[off + row];
 }
 
 // q = f - K u with ||q||^2 for every instance (done or not).
@@ -414,7 +409,7 @@ __global__ void __launch_bounds__(NT) k_true_resid(Ctx c) {
   }
   double dummy = 0.0;
   block_sum2(rr, dummy, lds);
-  if (threadIdx.x == 0) c.part[((size_t)b * c.nb + blk) * c.ps] = rr;
+  if (threadIdx.x == 0) put_partial(c.part + ((size_t)b * c.nb + blk) * c.ps, rr);
   if (!arrive_last(&st->cnt[CNT_A], c.nb, &flag)) return;
   const double t = reduce_partials(c.part + (size_t)b * c.nb * c.ps, c.nb, c.ps, lds);
   if (threadIdx.x == 0) st->rr_true = t;
@@ -444,23 +439,39 @@ __global__ void __launch_bounds__(NT) k_replace(Ctx c, const int *__restrict__ f
 // ---------------------------------------------------------------------------
 static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Records an event pair around the launches of the timer's kernel.
+// Per-call timing: records an event pair around the first per_call
+// launches of the timer's kernel.
+struct Tm {
+  pod2g_timer *t;
+  int used;
+};
+
 struct TimeScope {
-  pod2g_timer *tm;
+  Tm *tm;
   hipStream_t s;
   bool on;
-  TimeScope(pod2g_timer *t, int id, hipStream_t st) : tm(t), s(st) {
-    on = tm && tm->kernel == id && tm->count < tm->capacity && tm->per_call > 0;
-    if (on) tm->per_call--;
-    if (on) (void)hipEventRecord(tm->start[tm->count], s);
+  TimeScope(Tm *m, int id, hipStream_t st) : tm(m), s(st) {
+    on = tm && tm->t && tm->t->kernel == id && tm->used < tm->t->per_call;
+    if (on) (void)hipEventRecord(tm->t->start[tm->used], s);
   }
   ~TimeScope() {
     if (on) {
-      (void)hipEventRecord(tm->stop[tm->count], s);
-      tm->count++;
+      (void)hipEventRecord(tm->t->stop[tm->used], s);
+      tm->used++;
     }
   }
 };
+
+static int accumulate(pod2g_timer *t, int used) {
+  for (int i = 0; i < used; ++i) {
+    POD2G_HIP_CHECK(hipEventSynchronize(t->stop[i]));
+    float ms = 0.f;
+    POD2G_HIP_CHECK(hipEventElapsedTime(&ms, t->start[i], t->stop[i]));
+    t->total_ms += ms;
+    t->launches += 1;
+  }
+  return POD2G_OK;
+}
 
 struct Layout {
   size_t st, ec, part, vec, vec32, flags, total;
@@ -533,7 +544,7 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
 // r).  With want_dot the last kernel also forms rho and beta.
 template <int DIM, typename T>
 static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, int want_dot,
-                         pod2g_timer *tm) {
+                         Tm *tm) {
   dim3 grid(c.nb, c.batch), blk(NT);
   T *xa = (T *)c.xa, *xb = (T *)c.xb;
   T *cur = xa, *oth = xb;
@@ -594,7 +605,7 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
 
 template <int DIM>
 static void launch_cycle_any(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, int want_dot,
-                             pod2g_timer *tm) {
+                             Tm *tm) {
   if (pr->precision == POD2G_MIXED) launch_cycle<DIM, float>(c, pr, stream, want_dot, tm);
   else launch_cycle<DIM, double>(c, pr, stream, want_dot, tm);
 }
@@ -608,7 +619,7 @@ static void launch_first(const Ctx &c, const pod2g_prec *pr, hipStream_t stream)
 }
 
 template <int DIM>
-static void launch_iteration(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, pod2g_timer *tm) {
+static void launch_iteration(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, Tm *tm) {
   dim3 grid(c.nb, c.batch), blk(NT);
   {
     TimeScope ts(tm, POD2G_TK_SPMV_PQ, stream);
@@ -623,7 +634,6 @@ static void launch_iteration(const Ctx &c, const pod2g_prec *pr, hipStream_t str
     }
     launch_cycle_any<DIM>(c, pr, stream, 1, tm);
     hipLaunchKernelGGL(k_pupdate, grid, blk, 0, stream, c, (const double *)c.s);
-    hipLaunchKernelGGL(k_rescale, dim3(ceil_div(c.batch, 64)), dim3(64), 0, stream, c);
   } else {
     {
       TimeScope ts(tm, POD2G_TK_UPDATE, stream);
@@ -641,10 +651,27 @@ static int read_states(const Ctx &c, std::vector<InstState> &h, hipStream_t stre
   return POD2G_OK;
 }
 
+}  // namespace pod2g
+
+// A captured chunk of PCG iterations on fixed buffers (see pcg_plan_create).
+struct pod2g_plan {
+  pod2g::Ctx c;
+  pod2g_pattern pat;
+  pod2g_prec prec;
+  bool has_prec;
+  int chunk;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  pod2g_timer *timer;
+  int timed;   // event pairs captured in the chunk
+};
+
+namespace pod2g {
+
 template <int DIM>
 static int pcg_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int beta,
-                   int *iters_h, double *relres_h, int *status_h, pod2g_timer *tm,
-                   hipStream_t stream) {
+                   int *iters_h, double *relres_h, int *status_h, pod2g_timer *timer,
+                   pod2g_plan *plan, hipStream_t stream) {
   dim3 grid(c.nb, c.batch), blk(NT);
   hipLaunchKernelGGL(k_state_init, dim3(ceil_div(c.batch, 64)), dim3(64), 0, stream, c.st, c.batch,
                      rtol, maxit, beta, pr ? (const int *)pr->status : (const int *)nullptr);
@@ -652,32 +679,40 @@ static int pcg_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int bet
   auto start_cycle = [&]() {
     if (pr) {
       launch_first<DIM>(c, pr, stream);
-      launch_cycle_any<DIM>(c, pr, stream, 1, tm);
-      hipLaunchKernelGGL(k_pupdate, grid, blk, 0, stream, c, (const double *)c.s);
-    } else {
-      // restart flag: beta = 0 -> p = r
-      hipLaunchKernelGGL(k_pupdate, grid, blk, 0, stream, c, (const double *)c.r);
+      launch_cycle_any<DIM>(c, pr, stream, 1, nullptr);
     }
+    // beta = 0 (restart): p = s, or p = r without a preconditioner
+    hipLaunchKernelGGL(k_pupdate, grid, blk, 0, stream, c, pr ? (const double *)c.s : (const double *)c.r);
   };
-  // beta of the first direction is 0: k_state_init sets beta = 0, restart = 1
   start_cycle();
   POD2G_HIP_CHECK(hipGetLastError());
   std::vector<InstState> h;
   std::vector<int> flags(c.batch);
-  int *flags_d = nullptr;
-  {
-    Layout Lo = layout(c.n, c.batch, c.k, pr ? pr->precision : POD2G_FP64);
-    flags_d = (int *)((char *)c.st - Lo.st + Lo.flags);
-  }
-  int chunk = 4;
-  for (int guard = 0; guard < 1000000; ++guard) {
-    for (int i = 0; i < chunk; ++i) launch_iteration<DIM>(c, pr, stream, tm);
-    POD2G_HIP_CHECK(hipGetLastError());
+  Layout Lo = layout(c.n, c.batch, c.k, pr ? pr->precision : POD2G_FP64);
+  int *flags_d = (int *)((char *)c.st - Lo.st + Lo.flags);
+  int chunk = plan ? plan->chunk : 4;
+  bool first = true;
+  for (int guard = 0; guard < 10000000; ++guard) {
+    Tm tm = {timer, 0};
+    if (plan) {
+      POD2G_HIP_CHECK(hipGraphLaunch(plan->exec, stream));
+    } else {
+      for (int i = 0; i < chunk; ++i) launch_iteration<DIM>(c, pr, stream, first ? &tm : nullptr);
+      POD2G_HIP_CHECK(hipGetLastError());
+    }
     int st = read_states(c, h, stream);
     if (st) return st;
+    if (first && timer) {
+      // count the timed launches only if every instance was live through the chunk
+      bool live = true;
+      for (int b = 0; b < c.batch; ++b) live = live && h[b].iter >= chunk;
+      const int used = plan ? plan->timed : tm.used;
+      if (live && (st = accumulate(timer, used))) return st;
+    }
+    first = false;
     bool all_done = true;
     for (int b = 0; b < c.batch; ++b) all_done = all_done && h[b].done;
-    if (chunk < 16) chunk *= 2;
+    if (!plan && chunk < 16) chunk *= 2;
     if (!all_done) continue;
     // exit check on the true residual
     hipLaunchKernelGGL(k_true_resid<DIM>, grid, blk, 0, stream, c);
@@ -695,7 +730,7 @@ static int pcg_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int bet
                                    hipMemcpyHostToDevice, stream));
     hipLaunchKernelGGL(k_replace, grid, blk, 0, stream, c, (const int *)flags_d, pr ? 1 : 0);
     start_cycle();
-    chunk = 4;
+    if (!plan) chunk = 4;
   }
   int ret = POD2G_OK;
   for (int b = 0; b < c.batch; ++b) {
@@ -764,31 +799,32 @@ static int check_prec(const pod2g_prec *pr) {
   return POD2G_OK;
 }
 
-int pcg_solve_timed(const pod2g_pattern *pat, const double *vals, int batch,
-                    const pod2g_prec *prec, const double *f, double *u, double rtol, int maxit,
-                    int beta, int *iters_h, double *relres_h, int *status_h, void *work,
-                    size_t bytes, pod2g_timer *timer, hipStream_t stream) {
+static int check_solve_args(const pod2g_pattern *pat, const double *vals, int batch,
+                            const pod2g_prec *prec, const double *f, double *u, int beta,
+                            void *work, size_t bytes) {
   if (!pat || !vals || !f || !u || !work || batch < 1 || batch > 65535) return POD2G_EINVAL;
-  if (!(rtol >= 0.0) || maxit < 0 || (beta != POD2G_BETA_FR && beta != POD2G_BETA_PR)) return POD2G_EINVAL;
+  if (beta != POD2G_BETA_FR && beta != POD2G_BETA_PR) return POD2G_EINVAL;
   if (prec) {
     if (check_prec(prec)) return POD2G_EINVAL;
     if (prec->batch != batch || prec->pat.n != pat->n || prec->vals != vals) return POD2G_EINVAL;
   }
   const int k = prec ? prec->k : 0;
   if (bytes < pcg_solve_bytes(pat, batch, k, prec ? prec->precision : POD2G_FP64)) return POD2G_ESIZE;
+  return POD2G_OK;
+}
+
+int pcg_solve_timed(const pod2g_pattern *pat, const double *vals, int batch,
+                    const pod2g_prec *prec, const double *f, double *u, double rtol, int maxit,
+                    int beta, int *iters_h, double *relres_h, int *status_h, void *work,
+                    size_t bytes, pod2g_timer *timer, hipStream_t stream) {
+  int st = check_solve_args(pat, vals, batch, prec, f, u, beta, work, bytes);
+  if (st) return st;
+  if (!(rtol >= 0.0) || maxit < 0) return POD2G_EINVAL;
   Ctx c;
   fill_ctx(c, pat, vals, batch, prec, f, u, work);
-  // per_call counts down inside this call only
-  pod2g_timer tcopy;
-  pod2g_timer *tm = nullptr;
-  if (timer) { tcopy = *timer; tm = &tcopy; }
-  int ret;
   if (pat->mesh.dim == 2)
-    ret = pcg_run<2>(c, prec, rtol, maxit, beta, iters_h, relres_h, status_h, tm, stream);
-  else
-    ret = pcg_run<3>(c, prec, rtol, maxit, beta, iters_h, relres_h, status_h, tm, stream);
-  if (timer) timer->count = tcopy.count;
-  return ret;
+    return pcg_run<2>(c, prec, rtol, maxit, beta, iters_h, relres_h, status_h, timer, nullptr, stream);
+  return pcg_run<3>(c, prec, rtol, maxit, beta, iters_h, relres_h, status_h, timer, nullptr, stream);
 }
 
 int pcg_solve(const pod2g_pattern *pat, const double *vals, int batch, const pod2g_prec *prec,
@@ -798,17 +834,73 @@ int pcg_solve(const pod2g_pattern *pat, const double *vals, int batch, const pod
                          status_h, work, bytes, nullptr, stream);
 }
 
-int pod2g_timer_create(int kernel, int capacity, int per_call, pod2g_timer *out) {
-  if (!out || capacity < 1 || per_call < 1 || kernel < POD2G_TK_SPMV_PQ || kernel > POD2G_TK_UPDATE)
+int pcg_plan_create(const pod2g_pattern *pat, const double *vals, int batch, const pod2g_prec *prec,
+                    const double *f, double *u, int chunk, void *work, size_t bytes,
+                    pod2g_timer *timer, pod2g_plan **out) {
+  if (!out) return POD2G_EINVAL;
+  int st = check_solve_args(pat, vals, batch, prec, f, u, POD2G_BETA_FR, work, bytes);
+  if (st) return st;
+  if (chunk < 1 || chunk > 256) return POD2G_EINVAL;
+  pod2g_plan *pl = new pod2g_plan;
+  memset(pl, 0, sizeof(*pl));
+  pl->pat = *pat;
+  pl->has_prec = prec != nullptr;
+  if (prec) pl->prec = *prec;
+  pl->chunk = chunk;
+  pl->timer = timer;
+  fill_ctx(pl->c, pat, vals, batch, prec, f, u, work);
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { delete pl; return POD2G_EHIP; }
+  const pod2g_prec *pr = prec ? &pl->prec : nullptr;
+  Tm tm = {timer, 0};
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    for (int i = 0; i < chunk; ++i) {
+      if (pat->mesh.dim == 2) launch_iteration<2>(pl->c, pr, cs, &tm);
+      else launch_iteration<3>(pl->c, pr, cs, &tm);
+    }
+    ok = hipStreamEndCapture(cs, &pl->graph) == hipSuccess;
+  }
+  if (ok) ok = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) == hipSuccess;
+  (void)hipStreamDestroy(cs);
+  if (!ok) {
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    delete pl;
+    return POD2G_EHIP;
+  }
+  pl->timed = tm.used;
+  *out = pl;
+  return POD2G_OK;
+}
+
+int pcg_plan_solve(pod2g_plan *pl, double rtol, int maxit, int beta, int *iters_h,
+                   double *relres_h, int *status_h, hipStream_t stream) {
+  if (!pl || !(rtol >= 0.0) || maxit < 0) return POD2G_EINVAL;
+  if (beta != POD2G_BETA_FR && beta != POD2G_BETA_PR) return POD2G_EINVAL;
+  const pod2g_prec *pr = pl->has_prec ? &pl->prec : nullptr;
+  if (pl->pat.mesh.dim == 2)
+    return pcg_run<2>(pl->c, pr, rtol, maxit, beta, iters_h, relres_h, status_h, pl->timer, pl, stream);
+  return pcg_run<3>(pl->c, pr, rtol, maxit, beta, iters_h, relres_h, status_h, pl->timer, pl, stream);
+}
+
+int pcg_plan_destroy(pod2g_plan *pl) {
+  if (!pl) return POD2G_EINVAL;
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  delete pl;
+  return POD2G_OK;
+}
+
+int pod2g_timer_create(int kernel, int per_call, pod2g_timer *out) {
+  if (!out || per_call < 1 || per_call > 4096 || kernel < POD2G_TK_SPMV_PQ || kernel > POD2G_TK_UPDATE)
     return POD2G_EINVAL;
   pod2g_timer t;
+  memset(&t, 0, sizeof(t));
   t.kernel = kernel;
-  t.capacity = capacity;
-  t.count = 0;
   t.per_call = per_call;
-  t.start = new hipEvent_t[capacity];
-  t.stop = new hipEvent_t[capacity];
-  for (int i = 0; i < capacity; ++i) {
+  t.start = new hipEvent_t[per_call];
+  t.stop = new hipEvent_t[per_call];
+  for (int i = 0; i < per_call; ++i) {
     if (hipEventCreate(&t.start[i]) != hipSuccess || hipEventCreate(&t.stop[i]) != hipSuccess) {
       delete[] t.start;
       delete[] t.stop;
@@ -821,34 +913,21 @@ int pod2g_timer_create(int kernel, int capacity, int per_call, pod2g_timer *out)
 
 int pod2g_timer_reset(pod2g_timer *t) {
   if (!t) return POD2G_EINVAL;
-  t->count = 0;
-  return POD2G_OK;
-}
-
-int pod2g_timer_elapsed(const pod2g_timer *t, double *ms_total_h, int *count_h) {
-  if (!t || !ms_total_h) return POD2G_EINVAL;
-  double tot = 0.0;
-  for (int i = 0; i < t->count; ++i) {
-    POD2G_HIP_CHECK(hipEventSynchronize(t->stop[i]));
-    float ms = 0.f;
-    POD2G_HIP_CHECK(hipEventElapsedTime(&ms, t->start[i], t->stop[i]));
-    tot += ms;
-  }
-  *ms_total_h = tot;
-  if (count_h) *count_h = t->count;
+  t->total_ms = 0.0;
+  t->launches = 0;
   return POD2G_OK;
 }
 
 int pod2g_timer_destroy(pod2g_timer *t) {
   if (!t || !t->start) return POD2G_EINVAL;
-  for (int i = 0; i < t->capacity; ++i) {
+  for (int i = 0; i < t->per_call; ++i) {
     (void)hipEventDestroy(t->start[i]);
     (void)hipEventDestroy(t->stop[i]);
   }
   delete[] t->start;
   delete[] t->stop;
   t->start = t->stop = nullptr;
-  t->capacity = t->count = 0;
+  t->per_call = 0;
   return POD2G_OK;
 }
 

@@ -123,11 +123,43 @@ class Problem:
         return L.pcg_solve(self.pat, sysm.vals, sysm.batch, prec, sysm.f, u, rtol, maxit, beta,
                            wk, nb, stream)
 
+    def plan(self, sysm: System, prec, u, chunk=8, timer=None, key="pcg"):
+        """Capture `chunk` PCG iterations on these buffers (see pcg_plan_create)."""
+        k = prec.k if prec is not None else 0
+        precision = prec.precision if prec is not None else L.FP64
+        nb = L.pcg_solve_bytes(self.pat, sysm.batch, k, precision)
+        wk = self.work(key, nb)
+        h = L.pcg_plan_create(self.pat, sysm.vals, sysm.batch, prec, sysm.f, u, chunk, wk, nb, timer)
+        return Plan(h, sysm.batch, precision, (wk, prec, sysm, u, timer))
+
     def apply(self, prec, r, s, stream=None):
         nb = L.pod2g_apply_bytes(prec)
         wk = self.work("apply", nb)
         L.check(L.pod2g_apply(prec, r, s, wk, nb, stream), "pod2g_apply")
         return s
+
+
+class Plan:
+    """Owner of a captured solve plan; keeps its buffers alive."""
+
+    def __init__(self, handle, batch, precision, keep):
+        self.handle, self.batch, self.precision, self._keep = handle, batch, precision, keep
+
+    def solve(self, rtol, maxit=5000, beta=None, stream=None):
+        if beta is None:
+            beta = L.BETA_PR if self.precision == L.MIXED else L.BETA_FR
+        return L.pcg_plan_solve(self.handle, rtol, maxit, beta, self.batch, stream)
+
+    def close(self):
+        if self.handle:
+            L.pcg_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def solve_batched(prob: Problem, xis: np.ndarray, P=None, k=0, rtol=1e-12, maxit=20000,
