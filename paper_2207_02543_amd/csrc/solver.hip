@@ -444,33 +444,60 @@ static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 struct Tm {
   pod2g_timer *t;
   int used;
+  int capturing;   // inside stream capture: record as graph event nodes
+  int failed;      // a record failed: no further timing in this call / plan
 };
+
+// Inside stream capture an event record must become an explicit graph node
+// (a captured hipEventRecord only marks a dependency): add the node after
+// the stream's current capture dependencies and make it the new one.
+static bool record_node(hipEvent_t e, hipStream_t s) {
+  hipStreamCaptureStatus cst;
+  unsigned long long id = 0;
+  hipGraph_t g = nullptr;
+  const hipGraphNode_t *deps = nullptr;
+  size_t ndeps = 0;
+  if (hipStreamGetCaptureInfo_v2(s, &cst, &id, &g, &deps, &ndeps) != hipSuccess ||
+      cst != hipStreamCaptureStatusActive || !g)
+    return false;
+  hipGraphNode_t node;
+  if (hipGraphAddEventRecordNode(&node, g, deps, ndeps, e) != hipSuccess) return false;
+  return hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies) == hipSuccess;
+}
+
+static inline bool record(hipEvent_t e, hipStream_t s, int capturing) {
+  if (capturing) return record_node(e, s);
+  return hipEventRecord(e, s) == hipSuccess;
+}
 
 struct TimeScope {
   Tm *tm;
   hipStream_t s;
   bool on;
   TimeScope(Tm *m, int id, hipStream_t st) : tm(m), s(st) {
-    on = tm && tm->t && tm->t->kernel == id && tm->used < tm->t->per_call;
-    if (on) (void)hipEventRecord(tm->t->start[tm->used], s);
+    on = tm && tm->t && !tm->failed && tm->t->kernel == id && tm->used < tm->t->per_call;
+    if (on && !record(tm->t->start[tm->used], s, tm->capturing)) { tm->failed = 1; on = false; }
   }
   ~TimeScope() {
     if (on) {
-      (void)hipEventRecord(tm->t->stop[tm->used], s);
-      tm->used++;
+      if (record(tm->t->stop[tm->used], s, tm->capturing)) tm->used++;
+      else tm->failed = 1;
     }
   }
 };
 
-static int accumulate(pod2g_timer *t, int used) {
+// Timing never fails a solve: a pair whose duration cannot be read is skipped.
+static void accumulate(pod2g_timer *t, int used) {
   for (int i = 0; i < used; ++i) {
-    POD2G_HIP_CHECK(hipEventSynchronize(t->stop[i]));
     float ms = 0.f;
-    POD2G_HIP_CHECK(hipEventElapsedTime(&ms, t->start[i], t->stop[i]));
+    if (hipEventSynchronize(t->stop[i]) != hipSuccess ||
+        hipEventElapsedTime(&ms, t->start[i], t->stop[i]) != hipSuccess) {
+      (void)hipGetLastError();   // clear the sticky error
+      continue;
+    }
     t->total_ms += ms;
     t->launches += 1;
   }
-  return POD2G_OK;
 }
 
 struct Layout {
@@ -693,7 +720,7 @@ static int pcg_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int bet
   int chunk = plan ? plan->chunk : 4;
   bool first = true;
   for (int guard = 0; guard < 10000000; ++guard) {
-    Tm tm = {timer, 0};
+    Tm tm = {timer, 0, 0, 0};
     if (plan) {
       POD2G_HIP_CHECK(hipGraphLaunch(plan->exec, stream));
     } else {
@@ -706,8 +733,8 @@ static int pcg_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int bet
       // count the timed launches only if every instance was live through the chunk
       bool live = true;
       for (int b = 0; b < c.batch; ++b) live = live && h[b].iter >= chunk;
-      const int used = plan ? plan->timed : tm.used;
-      if (live && (st = accumulate(timer, used))) return st;
+      const int used = plan ? plan->timed : (tm.failed ? 0 : tm.used);
+      if (live) accumulate(timer, used);
     }
     first = false;
     bool all_done = true;
@@ -852,23 +879,35 @@ int pcg_plan_create(const pod2g_pattern *pat, const double *vals, int batch, con
   hipStream_t cs;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { delete pl; return POD2G_EHIP; }
   const pod2g_prec *pr = prec ? &pl->prec : nullptr;
-  Tm tm = {timer, 0};
-  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-  if (ok) {
+  Tm tm = {timer, 0, 1, 0};
+  auto capture = [&](Tm *t) -> bool {
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
     for (int i = 0; i < chunk; ++i) {
-      if (pat->mesh.dim == 2) launch_iteration<2>(pl->c, pr, cs, &tm);
-      else launch_iteration<3>(pl->c, pr, cs, &tm);
+      if (pat->mesh.dim == 2) launch_iteration<2>(pl->c, pr, cs, t);
+      else launch_iteration<3>(pl->c, pr, cs, t);
     }
-    ok = hipStreamEndCapture(cs, &pl->graph) == hipSuccess;
+    if (hipStreamEndCapture(cs, &pl->graph) != hipSuccess) return false;
+    if (hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) != hipSuccess) {
+      (void)hipGraphDestroy(pl->graph);
+      pl->graph = nullptr;
+      return false;
+    }
+    return true;
+  };
+  bool ok = capture(timer ? &tm : nullptr);
+  if (!ok && timer) {
+    // the timing nodes are optional: capture again without them
+    (void)hipGetLastError();
+    tm.failed = 1;
+    ok = capture(nullptr);
   }
-  if (ok) ok = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) == hipSuccess;
   (void)hipStreamDestroy(cs);
   if (!ok) {
-    if (pl->graph) (void)hipGraphDestroy(pl->graph);
     delete pl;
     return POD2G_EHIP;
   }
-  pl->timed = tm.used;
+  pl->timed = tm.failed ? 0 : tm.used;
+  if (tm.failed) (void)hipGetLastError();   // timing unavailable: clear its error, keep the plan
   *out = pl;
   return POD2G_OK;
 }

@@ -47,7 +47,7 @@ def test_plan_replays_match_eager(dim, N, prec, chunk, batch):
         for m, j0 in enumerate(range(0, nq, batch)):
             load(j0)
             ret, it, rr, st = plan.solve(w.tol)
-            assert ret == capi.OK, st
+            assert ret == capi.OK, (ret, st)
             assert it == eager[m][0]
             np.testing.assert_array_equal(u.cpu().numpy(), eager[m][1])
             # eager work on the same stream between replays
