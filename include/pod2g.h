@@ -111,6 +111,8 @@ typedef struct pod2g_prec {
   float *dinv32;        /* [batch][n] (MIXED), in the setup workspace */
   double *KP;           /* [batch][k][n] K P, in the setup workspace */
   double *L;            /* [batch][k][k] row-major lower Cholesky factor of P^T K P */
+  double *Linv;         /* [batch][k][k] row-major inverse of L (lower triangular):
+                           the cycle's coarse solve is e_c = Linv^T (Linv r_c) */
   double *lam;          /* [batch] power-iteration estimate of lambda_max(D^-1 K) */
   int *status;          /* [batch] per-instance setup status (device) */
 } pod2g_prec;
@@ -224,8 +226,9 @@ int pcg_solve_timed(const pod2g_pattern *pat, const double *vals, int batch,
  * may change between solves (new theta, new warm start, new setup in the
  * same setup workspace).  With a timer, the graph records the timer's
  * events (the timer must outlive the plan).  pcg_plan_solve is synchronous
- * and has pcg_solve's outputs and statuses.  Plans are host objects: create,
- * solve and destroy them from one thread.                                   */
+ * and has pcg_solve's outputs and statuses.  An odd chunk is rounded up to
+ * the next even number.  Plans are host objects: create, solve and destroy
+ * them from one thread.                                                     */
 typedef struct pod2g_plan pod2g_plan;
 int pcg_plan_create(const pod2g_pattern *pat, const double *vals, int batch,
                     const pod2g_prec *prec, const double *f, double *u, int chunk,

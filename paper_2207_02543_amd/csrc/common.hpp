@@ -81,21 +81,19 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *lds /*[
   __syncthreads();
 }
 
-// Cross-workgroup partial results are written and read with agent-scope
-// relaxed atomics: the stores write through to the point of coherence
-// shared by all XCDs and the loads read from it, so no L2 writeback or
-// invalidation of unrelated data is needed.
+// Cross-workgroup partial results: each workgroup writes its partials with
+// agent-scope relaxed atomic stores, which write through to the point of
+// coherence shared by all XCDs (no L2 writeback of unrelated data).  The
+// last workgroup to arrive invalidates its caches once (agent-scope acquire
+// fence) and then reads the partials with ordinary, pipelined loads.
 __device__ __forceinline__ void put_partial(double *p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double get_partial(const double *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Report whether this workgroup is the last of `total` to arrive at
 // `counter`.  Every wave first waits for its outstanding stores (so its
 // put_partial writes are complete before the counter moves); the last
-// workgroup resets the counter and may then get_partial every partial.
+// workgroup resets the counter, acquires, and may then read every partial.
 __device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned total, int *lds_flag) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
@@ -106,16 +104,32 @@ __device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned total, i
     *lds_flag = last;
   }
   __syncthreads();
-  return *lds_flag != 0;
+  const bool last = *lds_flag != 0;
+  if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return last;
 }
 
 // Deterministic sum of m partials (strided by `stride` doubles) by one
 // workgroup: fixed per-thread order, then the fixed block tree.
+// Sum of part[i * stride] for i = first, first + step, ... < m with four
+// independent accumulators (loads in flight together; order fixed by m).
+__device__ __forceinline__ double strided_sum(const double *part, int first, int m, int step,
+                                              int stride) {
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int i = first;
+  for (; i + 3 * step < m; i += 4 * step) {
+    a0 += part[(size_t)i * stride];
+    a1 += part[(size_t)(i + step) * stride];
+    a2 += part[(size_t)(i + 2 * step) * stride];
+    a3 += part[(size_t)(i + 3 * step) * stride];
+  }
+  for (; i < m; i += step) a0 += part[(size_t)i * stride];
+  return (a0 + a1) + (a2 + a3);
+}
+
 __device__ __forceinline__ double reduce_partials(const double *part, int m, int stride,
                                                   double *lds) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < m; i += NT) v += get_partial(part + (size_t)i * stride);
-  return block_sum(v, lds);
+  return block_sum(strided_sum(part, threadIdx.x, m, NT, stride), lds);
 }
 
 __device__ __forceinline__ bool finite(double x) { return x - x == 0.0; }

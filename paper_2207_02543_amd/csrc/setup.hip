@@ -13,7 +13,7 @@ constexpr int KP_CH = 8;   // columns of K P per pass over K
 constexpr int KC_TR = 64;  // rows per LDS tile of the coarse-matrix kernel
 
 struct SetupLayout {
-  size_t status, lam, pst, kp, L, kcpart, ppart, p32, d32, pw, total;
+  size_t status, lam, pst, kp, L, Linv, kcpart, ppart, p32, d32, pw, total;
   int nbk, rows_per_wg;
 };
 
@@ -32,6 +32,7 @@ static SetupLayout setup_layout(int n, int k, int batch, int precision) {
   S.pst = o;    o += align256(sizeof(InstState) * batch);
   S.kp = o;     o += align256(sizeof(double) * (size_t)batch * k * n);
   S.L = o;      o += align256(sizeof(double) * (size_t)batch * k * k);
+  S.Linv = o;   o += align256(sizeof(double) * (size_t)batch * k * k);
   S.kcpart = o; o += align256(sizeof(double) * (size_t)batch * S.nbk * (ntri > 0 ? ntri : 1));
   S.ppart = o;  o += align256(sizeof(double) * (size_t)batch * ceil_div(n, NT));
   S.p32 = o;    if (precision == POD2G_MIXED) o += align256(sizeof(float) * (size_t)k * n);
@@ -100,8 +101,8 @@ __device__ __forceinline__ void tri_index(int e, int &j, int &l) {
 __global__ void __launch_bounds__(NT) k_kc(int n, int k, int rows_per_wg, int nbk,
                                            const double *__restrict__ P,
                                            const double *__restrict__ KP, double *__restrict__ part,
-                                           double *__restrict__ Lout, int *__restrict__ status,
-                                           InstState *pst) {
+                                           double *__restrict__ Lout, double *__restrict__ Linv,
+                                           int *__restrict__ status, InstState *pst) {
   constexpr int MAXE = (MAXK * (MAXK + 1) / 2 + NT - 1) / NT;
   __shared__ double sp[MAXK * KC_TR];
   __shared__ double skp[MAXK * KC_TR];
@@ -150,7 +151,7 @@ __global__ void __launch_bounds__(NT) k_kc(int n, int k, int rows_per_wg, int nb
   double *A = sp;  // k x k, row-major
   for (int e = threadIdx.x; e < ntri; e += NT) {
     double s = 0.0;
-    for (int w = 0; w < nbk; ++w) s += get_partial(pb + (size_t)w * ntri + e);
+    for (int w = 0; w < nbk; ++w) s += pb[(size_t)w * ntri + e];
     int j, l;
     tri_index(e, j, l);
     A[j * k + l] = s;
@@ -180,6 +181,23 @@ __global__ void __launch_bounds__(NT) k_kc(int n, int k, int rows_per_wg, int nb
     const int i = t / k, l = t % k;
     Lb[t] = l <= i ? A[t] : 0.0;
   }
+  // X = L^-1 by forward substitution, one column per thread
+  double *X = skp;   // k x k, row-major
+  if (threadIdx.x < k) {
+    const int j = threadIdx.x;
+    for (int i = 0; i < k; ++i) {
+      double v = 0.0;
+      if (i >= j) {
+        v = i == j ? 1.0 : 0.0;
+        for (int m = j; m < i; ++m) v -= A[i * k + m] * X[m * k + j];
+        v /= A[i * k + i];
+      }
+      X[i * k + j] = v;
+    }
+  }
+  __syncthreads();
+  double *Xb = Linv + (size_t)b * k * k;
+  for (int t = threadIdx.x; t < k * k; t += NT) Xb[t] = X[t];
   if (threadIdx.x == 0 && fail) status[b] = POD2G_ENOTSPD;
 }
 
@@ -221,7 +239,7 @@ __global__ void __launch_bounds__(NT) k_power(int n, int nn, int nb, long long v
   if (threadIdx.x == 0) put_partial(part + (size_t)b * nb + blk, yy);
   if (!arrive_last(&pst[b].cnt[CNT_B], nb, &flag)) return;
   double s = 0.0;
-  for (int i = threadIdx.x; i < nb; i += NT) s += get_partial(part + (size_t)b * nb + i);
+  for (int i = threadIdx.x; i < nb; i += NT) s += part[(size_t)b * nb + i];
   s = block_sum(s, lds);
   if (threadIdx.x == 0) {
     pst[b].xnorm2 = s;
@@ -278,6 +296,7 @@ int pod2g_setup(const pod2g_pattern *pat, const double *vals, const float *vals3
   InstState *pst = (InstState *)(w + S.pst);
   pr.KP = k > 0 ? (double *)(w + S.kp) : nullptr;
   pr.L = k > 0 ? (double *)(w + S.L) : nullptr;
+  pr.Linv = k > 0 ? (double *)(w + S.Linv) : nullptr;
   double *kcpart = (double *)(w + S.kcpart);
   double *ppart = (double *)(w + S.ppart);
   pr.P32 = (precision == POD2G_MIXED && k > 0) ? (float *)(w + S.p32) : nullptr;
@@ -297,7 +316,7 @@ int pod2g_setup(const pod2g_pattern *pat, const double *vals, const float *vals3
       hipLaunchKernelGGL(k_kp<3>, gk, dim3(NT), 0, stream, n, pat->n_nodes, k, pat->nvals,
                          pat->colblk, vals, P, pr.KP);
     hipLaunchKernelGGL(k_kc, dim3(S.nbk, batch), dim3(NT), 0, stream, n, k, S.rows_per_wg, S.nbk,
-                       P, (const double *)pr.KP, kcpart, pr.L, pr.status, pst);
+                       P, (const double *)pr.KP, kcpart, pr.L, pr.Linv, pr.status, pst);
     if (precision == POD2G_MIXED)
       hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(NT), 0, stream, (size_t)k * n, P, pr.P32);
   }

@@ -24,10 +24,11 @@ struct Ctx {
   const void *svals;             // smoother K (FP64 or FP32)
   const void *sdinv;             // smoother D^-1
   const void *sP;                // cycle P (FP64 or FP32)
-  const double *L;               // [batch][k][k]
+  const double *Linv;            // [batch][k][k] inverse Cholesky factor
   double omega;
   const double *f;               // [n]
-  double *u, *r, *p, *q, *s;     // [batch][n] FP64
+  double *u, *r, *q, *s;         // [batch][n] FP64
+  double *p0, *p1;               // [batch][n] search directions (ping-pong)
   void *xa, *xb;                 // [batch][n] cycle vectors (smoother type)
   void *b32;                     // [batch][n] FP32 scaled residual (mixed only)
   double *part;                  // [batch][nb][ps]
@@ -36,6 +37,18 @@ struct Ctx {
 };
 
 __device__ __forceinline__ int inst_id() { return blockIdx.y; }
+
+// Partial sums: slot j of instance b holds one value per workgroup,
+// contiguous over workgroups.
+__device__ __forceinline__ double *slot(const Ctx &c, int b, int j) {
+  return c.part + ((size_t)b * c.ps + j) * c.nb;
+}
+
+// The search direction p = s + beta p_old (beta = 0 on a restart: p = s,
+// p_old not read).  One expression for the owned and the gathered entries.
+__device__ __forceinline__ double pdir(double s, const double *pold, size_t i, double beta) {
+  return beta == 0.0 ? s : s + beta * pold[i];
+}
 
 __device__ __forceinline__ double pow2_scale(double rr);
 __device__ __forceinline__ double cycle_scale(const Ctx &c, double rr) {
@@ -89,12 +102,10 @@ __global__ void __launch_bounds__(NT) k_init(Ctx c, int have_prec) {
     ff = fv * fv;
   }
   block_sum2(rr, ff, lds);
-  double *part = c.part + ((size_t)b * c.nb + blk) * c.ps;
-  if (threadIdx.x == 0) { put_partial(part, rr); put_partial(part + 1, ff); }
+  if (threadIdx.x == 0) { put_partial(slot(c, b, 0) + blk, rr); put_partial(slot(c, b, 1) + blk, ff); }
   if (!arrive_last(&st->cnt[CNT_A], c.nb, &flag)) return;
-  const double *p0 = c.part + (size_t)b * c.nb * c.ps;
-  double trr = reduce_partials(p0, c.nb, c.ps, lds);
-  double tff = reduce_partials(p0 + 1, c.nb, c.ps, lds);
+  double trr = reduce_partials(slot(c, b, 0), c.nb, 1, lds);
+  double tff = reduce_partials(slot(c, b, 1), c.nb, 1, lds);
   if (threadIdx.x == 0) {
     st->rr = trr;
     st->ff = tff;
@@ -157,10 +168,9 @@ __global__ void __launch_bounds__(NT) k_sweep(Ctx c, const T *__restrict__ xin, 
   if (!FINAL || !want_dot) return;
   double dummy = 0.0;
   block_sum2(rs, dummy, lds);
-  double *part = c.part + ((size_t)b * c.nb + blk) * c.ps;
-  if (threadIdx.x == 0) put_partial(part, rs);
+  if (threadIdx.x == 0) put_partial(slot(c, b, 0) + blk, rs);
   if (!arrive_last(&st->cnt[CNT_B], c.nb, &flag)) return;
-  const double trs = reduce_partials(c.part + (size_t)b * c.nb * c.ps, c.nb, c.ps, lds);
+  const double trs = reduce_partials(slot(c, b, 0), c.nb, 1, lds);
   if (threadIdx.x == 0) {
     double beta = 0.0;
     if (!st->restart) {
@@ -203,42 +213,61 @@ __global__ void __launch_bounds__(NT) k_restrict(Ctx c, const T *__restrict__ x)
   const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
   const T *P = (const T *)c.sP;
   const int row0 = blk * NT;
-  double *part = c.part + ((size_t)b * c.nb + blk) * c.ps;
-  for (int j = w; j < c.k; j += NWAVE) {
-    double acc = 0.0;
+  // this wave's columns j = w + NWAVE q, four at a time so that their P
+  // loads are in flight together
+  const int ncol = (c.k - w + NWAVE - 1) / NWAVE;
+  for (int q0 = 0; q0 < ncol; q0 += 4) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int m = 0; m < NT / WAVE; ++m) {
-      const int rr = row0 + lane + m * WAVE;
-      if (rr < c.n) acc += (double)P[(size_t)j * c.n + rr] * rsh[lane + m * WAVE];
+    for (int cc = 0; cc < 4; ++cc) {
+      if (q0 + cc < ncol) {
+        const T *Pj = P + (size_t)(w + (q0 + cc) * NWAVE) * c.n;
+#pragma unroll
+        for (int m = 0; m < NT / WAVE; ++m) {
+          const int rr = row0 + lane + m * WAVE;
+          if (rr < c.n) acc[cc] += (double)Pj[rr] * rsh[lane + m * WAVE];
+        }
+      }
     }
-    acc = wave_sum(acc);
-    if (lane == 0) put_partial(part + j, acc);
-  }
-  if (!arrive_last(&st->cnt[CNT_C], c.nb, &flag)) return;
-  const double *p0 = c.part + (size_t)b * c.nb * c.ps;
-  for (int j = w; j < c.k; j += NWAVE) {
-    double acc = 0.0;
-    for (int i = lane; i < c.nb; i += WAVE) acc += get_partial(p0 + (size_t)i * c.ps + j);
-    acc = wave_sum(acc);
-    if (lane == 0) rc[j] = acc;
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) acc[cc] = wave_sum(acc[cc]);
+    if (lane == 0) {
+#pragma unroll
+      for (int cc = 0; cc < 4; ++cc)
+        if (q0 + cc < ncol) rc[w + (q0 + cc) * NWAVE] = acc[cc];
+    }
   }
   __syncthreads();
-  if (w == 0) {
-    // L L^T e = rc with lane t owning unknown t
-    const double *L = c.L + (size_t)b * c.k * c.k;
-    const int k = c.k;
-    double y = lane < k ? rc[lane] : 0.0;
-    for (int j = 0; j < k; ++j) {
-      const double yj = __shfl(y, j, WAVE) / L[j * k + j];
-      if (lane == j) y = yj;
-      if (lane > j && lane < k) y -= L[lane * k + j] * yj;
-    }
-    for (int j = k - 1; j >= 0; --j) {
-      const double ej = __shfl(y, j, WAVE) / L[j * k + j];
-      if (lane == j) y = ej;
-      if (lane < j) y -= L[j * k + lane] * ej;
-    }
-    if (lane < k) c.ec[(size_t)b * MAXK + lane] = y;
+  if (threadIdx.x < c.k) put_partial(slot(c, b, threadIdx.x) + blk, rc[threadIdx.x]);
+  if (!arrive_last(&st->cnt[CNT_C], c.nb, &flag)) return;
+  // r_c: tpc threads per column, each summing a strided share of the
+  // column's partials, then the shares in order
+  const int k = c.k;
+  const int tpc = NT / k;
+  if (threadIdx.x < k * tpc)
+    rsh[threadIdx.x] = strided_sum(slot(c, b, threadIdx.x / tpc), threadIdx.x % tpc, c.nb, tpc, 1);
+  __syncthreads();
+  if (threadIdx.x < k) {
+    double v = 0.0;
+    for (int q = 0; q < tpc; ++q) v += rsh[threadIdx.x * tpc + q];
+    rc[threadIdx.x] = v;
+  }
+  __syncthreads();
+  // coarse solve L L^T e_c = r_c as e_c = Linv^T (Linv r_c)
+  const double *Li = c.Linv + (size_t)b * k * k;
+  double y = 0.0;
+  if (threadIdx.x < k) {
+    const int i = threadIdx.x;
+    for (int j = 0; j <= i; ++j) y += Li[i * k + j] * rc[j];
+  }
+  __syncthreads();
+  if (threadIdx.x < k) rsh[threadIdx.x] = y;
+  __syncthreads();
+  if (threadIdx.x < k) {
+    const int i = threadIdx.x;
+    double e = 0.0;
+    for (int j = i; j < k; ++j) e += Li[j * k + i] * rsh[j];
+    c.ec[(size_t)b * MAXK + i] = e;
   }
 }
 
@@ -279,9 +308,9 @@ __global__ void __launch_bounds__(NT) k_finalize(Ctx c, const T *__restrict__ x,
   if (!want_dot) return;
   double dummy = 0.0;
   block_sum2(rs, dummy, lds);
-  if (threadIdx.x == 0) put_partial(c.part + ((size_t)b * c.nb + blk) * c.ps, rs);
+  if (threadIdx.x == 0) put_partial(slot(c, b, 0) + blk, rs);
   if (!arrive_last(&st->cnt[CNT_B], c.nb, &flag)) return;
-  const double trs = reduce_partials(c.part + (size_t)b * c.nb * c.ps, c.nb, c.ps, lds);
+  const double trs = reduce_partials(slot(c, b, 0), c.nb, 1, lds);
   if (threadIdx.x == 0) {
     double beta = 0.0;
     if (!st->restart)
@@ -293,29 +322,49 @@ __global__ void __launch_bounds__(NT) k_finalize(Ctx c, const T *__restrict__ x,
   }
 }
 
-// q = K p and p^T q; the last block forms alpha = rho / p^T q.
+// p = s + beta p_old (gathered where K needs it), q = K p, p^T q; the
+// last block forms alpha = rho / p^T q.  Workgroup 0 also sets the input
+// scale of the next cycle from the current ||r||.
 template <int DIM>
-__global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c) {
+__global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c, const double *__restrict__ s,
+                                                const double *__restrict__ pold,
+                                                double *__restrict__ pnew) {
   __shared__ double lds[2 * NWAVE];
   __shared__ int flag;
   const int b = inst_id();
   InstState *st = c.st + b;
   if (st->done) return;
+  const double beta = st->beta;
+  if (blockIdx.x == 0 && threadIdx.x == 0) st->scale = cycle_scale(c, st->rr);
   const int blk = xcd_block(blockIdx.x, c.nb);
   const int row = blk * NT + threadIdx.x;
   const size_t off = (size_t)b * c.n;
   double pq = 0.0;
   if (row < c.n) {
-    const double kp = row_dot<DIM>(c.colblk, c.vals + (size_t)b * c.vstride, c.p + off, row,
-                                   row / DIM, c.n, c.nn);
+    constexpr int S = Stencil<DIM>::S;
+    const double *vals = c.vals + (size_t)b * c.vstride;
+    const double *sb = s + off, *pb = pold + off;
+    const int node = row / DIM;
+    double kp = 0.0;
+#pragma unroll 9
+    for (int sl = 0; sl < S; ++sl) {
+      const int col = c.colblk[sl * c.nn + node];
+#pragma unroll
+      for (int bc = 0; bc < DIM; ++bc) {
+        const size_t i = (size_t)col * DIM + bc;
+        kp += vals[(size_t)(sl * DIM + bc) * c.n + row] * pdir(sb[i], pb, i, beta);
+      }
+    }
+    const double pv = pdir(sb[row], pb, row, beta);
+    pnew[off + row] = pv;
     c.q[off + row] = kp;
-    pq = c.p[off + row] * kp;
+    pq = pv * kp;
   }
   double dummy = 0.0;
   block_sum2(pq, dummy, lds);
-  if (threadIdx.x == 0) put_partial(c.part + ((size_t)b * c.nb + blk) * c.ps, pq);
+  if (threadIdx.x == 0) put_partial(slot(c, b, 0) + blk, pq);
   if (!arrive_last(&st->cnt[CNT_D], c.nb, &flag)) return;
-  const double g = reduce_partials(c.part + (size_t)b * c.nb * c.ps, c.nb, c.ps, lds);
+  const double g = reduce_partials(slot(c, b, 0), c.nb, 1, lds);
   if (threadIdx.x == 0) {
     st->gamma = g;
     if (!(g > 0.0)) { st->done = 1; st->status = finite(g) ? POD2G_EBREAKDOWN : POD2G_ENAN; }
@@ -329,7 +378,7 @@ __global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c) {
 // iteration limit, non-finite checks; without a preconditioner (mode 0)
 // s = r, so rho and beta are formed here.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_update(Ctx c, int mode) {
+__global__ void __launch_bounds__(NT) k_update(Ctx c, int mode, const double *__restrict__ p) {
   const int have_prec = mode != 0;
   __shared__ double lds[2 * NWAVE];
   __shared__ int flag;
@@ -343,7 +392,7 @@ __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode) {
   const bool pr = have_prec && st->beta_kind == POD2G_BETA_PR;
   double rr = 0.0, rs = 0.0;
   if (row < c.n) {
-    c.u[off + row] += alpha * c.p[off + row];
+    c.u[off + row] += alpha * p[off + row];
     const double rv = c.r[off + row] - alpha * c.q[off + row];
     c.r[off + row] = rv;
     rr = rv * rv;
@@ -355,12 +404,10 @@ __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode) {
     }
   }
   block_sum2(rr, rs, lds);
-  double *part = c.part + ((size_t)b * c.nb + blk) * c.ps;
-  if (threadIdx.x == 0) { put_partial(part, rr); put_partial(part + 1, rs); }
+  if (threadIdx.x == 0) { put_partial(slot(c, b, 0) + blk, rr); put_partial(slot(c, b, 1) + blk, rs); }
   if (!arrive_last(&st->cnt[CNT_E], c.nb, &flag)) return;
-  const double *p0 = c.part + (size_t)b * c.nb * c.ps;
-  const double trr = reduce_partials(p0, c.nb, c.ps, lds);
-  const double trs = pr ? reduce_partials(p0 + 1, c.nb, c.ps, lds) : 0.0;
+  const double trr = reduce_partials(slot(c, b, 0), c.nb, 1, lds);
+  const double trs = pr ? reduce_partials(slot(c, b, 1), c.nb, 1, lds) : 0.0;
   if (threadIdx.x == 0) {
     st->iter += 1;
     st->rr = trr;
@@ -373,20 +420,6 @@ __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode) {
       st->rho = trr;
     }
   }
-}
-
-// p = s + beta p; the next cycle's input scale (from the current ||r||)
-// is set by one thread: no other workgroup reads it in this kernel.
-__global__ void __launch_bounds__(NT) k_pupdate(Ctx c, const double *__restrict__ s) {
-  const int b = inst_id();
-  InstState *st = c.st + b;
-  if (st->done) return;
-  const double beta = st->beta;
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->scale = cycle_scale(c, st->rr);
-  const int row = blockIdx.x * NT + threadIdx.x;
-  if (row >= c.n) return;
-  const size_t off = (size_t)b * c.n;
-  c.p[off + row] = s[off + row] + beta * c.p[off + row];
 }
 
 // q = f - K u with ||q||^2 for every instance (done or not).
@@ -409,9 +442,9 @@ __global__ void __launch_bounds__(NT) k_true_resid(Ctx c) {
   }
   double dummy = 0.0;
   block_sum2(rr, dummy, lds);
-  if (threadIdx.x == 0) put_partial(c.part + ((size_t)b * c.nb + blk) * c.ps, rr);
+  if (threadIdx.x == 0) put_partial(slot(c, b, 0) + blk, rr);
   if (!arrive_last(&st->cnt[CNT_A], c.nb, &flag)) return;
-  const double t = reduce_partials(c.part + (size_t)b * c.nb * c.ps, c.nb, c.ps, lds);
+  const double t = reduce_partials(slot(c, b, 0), c.nb, 1, lds);
   if (threadIdx.x == 0) st->rr_true = t;
 }
 
@@ -513,7 +546,7 @@ static Layout layout(int n, int batch, int k, int precision) {
   L.ec = o;    o += align256(sizeof(double) * MAXK * (size_t)batch);
   L.part = o;  o += align256(sizeof(double) * (size_t)ps * nb * batch);
   L.flags = o; o += align256(sizeof(int) * (size_t)batch);
-  L.vec = o;   o += 6 * align256(sizeof(double) * (size_t)n * batch);   // r p q s xa xb
+  L.vec = o;   o += 7 * align256(sizeof(double) * (size_t)n * batch);   // r p0 p1 q s xa xb
   L.vec32 = o;
   if (precision == POD2G_MIXED) o += align256(sizeof(float) * (size_t)n * batch);  // b32
   L.total = o;
@@ -544,16 +577,17 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
   c.part = (double *)(w + Lo.part);
   const size_t vb = align256(sizeof(double) * (size_t)n * batch);
   c.r = (double *)(w + Lo.vec);
-  c.p = (double *)(w + Lo.vec + vb);
-  c.q = (double *)(w + Lo.vec + 2 * vb);
-  c.s = (double *)(w + Lo.vec + 3 * vb);
-  c.xa = (void *)(w + Lo.vec + 4 * vb);
-  c.xb = (void *)(w + Lo.vec + 5 * vb);
+  c.p0 = (double *)(w + Lo.vec + vb);
+  c.p1 = (double *)(w + Lo.vec + 2 * vb);
+  c.q = (double *)(w + Lo.vec + 3 * vb);
+  c.s = (double *)(w + Lo.vec + 4 * vb);
+  c.xa = (void *)(w + Lo.vec + 5 * vb);
+  c.xb = (void *)(w + Lo.vec + 6 * vb);
   c.b32 = precision == POD2G_MIXED ? (void *)(w + Lo.vec32) : nullptr;
   c.mixed = precision == POD2G_MIXED;
   if (prec) {
     c.omega = prec->omega;
-    c.L = prec->L;
+    c.Linv = prec->Linv;
     if (precision == POD2G_MIXED) {
       c.svals = prec->vals32;
       c.sdinv = prec->dinv32;
@@ -645,28 +679,32 @@ static void launch_first(const Ctx &c, const pod2g_prec *pr, hipStream_t stream)
   else if (wx) hipLaunchKernelGGL((k_cyc_first<double>), grid, dim3(NT), 0, stream, c, wx);
 }
 
+// One PCG iteration.  Iterations alternate the two direction buffers
+// (parity 0 reads p0 and writes p1), so chunks have an even length.
 template <int DIM>
-static void launch_iteration(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, Tm *tm) {
+static void launch_iteration(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, Tm *tm,
+                             int parity) {
   dim3 grid(c.nb, c.batch), blk(NT);
+  const double *pold = parity ? c.p1 : c.p0;
+  double *pnew = parity ? c.p0 : c.p1;
   {
     TimeScope ts(tm, POD2G_TK_SPMV_PQ, stream);
-    hipLaunchKernelGGL(k_spmv_pq<DIM>, grid, blk, 0, stream, c);
+    hipLaunchKernelGGL(k_spmv_pq<DIM>, grid, blk, 0, stream, c, pr ? (const double *)c.s : (const double *)c.r,
+                       pold, pnew);
   }
   if (pr) {
     const int mode = pr->nu_pre >= 1 ? 1 : 2;
     {
       TimeScope ts(tm, POD2G_TK_UPDATE, stream);
-      if (pr->precision == POD2G_MIXED) hipLaunchKernelGGL(k_update<float>, grid, blk, 0, stream, c, mode);
-      else hipLaunchKernelGGL(k_update<double>, grid, blk, 0, stream, c, mode);
+      if (pr->precision == POD2G_MIXED)
+        hipLaunchKernelGGL(k_update<float>, grid, blk, 0, stream, c, mode, (const double *)pnew);
+      else
+        hipLaunchKernelGGL(k_update<double>, grid, blk, 0, stream, c, mode, (const double *)pnew);
     }
     launch_cycle_any<DIM>(c, pr, stream, 1, tm);
-    hipLaunchKernelGGL(k_pupdate, grid, blk, 0, stream, c, (const double *)c.s);
   } else {
-    {
-      TimeScope ts(tm, POD2G_TK_UPDATE, stream);
-      hipLaunchKernelGGL(k_update<double>, grid, blk, 0, stream, c, 0);
-    }
-    hipLaunchKernelGGL(k_pupdate, grid, blk, 0, stream, c, (const double *)c.r);
+    TimeScope ts(tm, POD2G_TK_UPDATE, stream);
+    hipLaunchKernelGGL(k_update<double>, grid, blk, 0, stream, c, 0, (const double *)pnew);
   }
 }
 
@@ -703,13 +741,13 @@ static int pcg_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int bet
   hipLaunchKernelGGL(k_state_init, dim3(ceil_div(c.batch, 64)), dim3(64), 0, stream, c.st, c.batch,
                      rtol, maxit, beta, pr ? (const int *)pr->status : (const int *)nullptr);
   hipLaunchKernelGGL(k_init<DIM>, grid, blk, 0, stream, c, pr ? 1 : 0);
+  // s = B r and rho; the restart flag makes beta = 0, so the next
+  // iteration's direction is p = s (p = r without a preconditioner)
   auto start_cycle = [&]() {
     if (pr) {
       launch_first<DIM>(c, pr, stream);
       launch_cycle_any<DIM>(c, pr, stream, 1, nullptr);
     }
-    // beta = 0 (restart): p = s, or p = r without a preconditioner
-    hipLaunchKernelGGL(k_pupdate, grid, blk, 0, stream, c, pr ? (const double *)c.s : (const double *)c.r);
   };
   start_cycle();
   POD2G_HIP_CHECK(hipGetLastError());
@@ -724,7 +762,7 @@ static int pcg_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int bet
     if (plan) {
       POD2G_HIP_CHECK(hipGraphLaunch(plan->exec, stream));
     } else {
-      for (int i = 0; i < chunk; ++i) launch_iteration<DIM>(c, pr, stream, first ? &tm : nullptr);
+      for (int i = 0; i < chunk; ++i) launch_iteration<DIM>(c, pr, stream, first ? &tm : nullptr, i & 1);
       POD2G_HIP_CHECK(hipGetLastError());
     }
     int st = read_states(c, h, stream);
@@ -822,7 +860,7 @@ static int check_prec(const pod2g_prec *pr) {
   if (pr->nu_pre < 0 || pr->nu_post < 0 || pr->nu_pre > 64 || pr->nu_post > 64) return POD2G_EINVAL;
   if (pr->precision == POD2G_MIXED && (!pr->vals32 || !pr->dinv32 || (pr->k > 0 && !pr->P32)))
     return POD2G_EINVAL;
-  if (pr->k > 0 && (!pr->P || !pr->L)) return POD2G_EINVAL;
+  if (pr->k > 0 && (!pr->P || !pr->L || !pr->Linv)) return POD2G_EINVAL;
   return POD2G_OK;
 }
 
@@ -868,6 +906,7 @@ int pcg_plan_create(const pod2g_pattern *pat, const double *vals, int batch, con
   int st = check_solve_args(pat, vals, batch, prec, f, u, POD2G_BETA_FR, work, bytes);
   if (st) return st;
   if (chunk < 1 || chunk > 256) return POD2G_EINVAL;
+  chunk += chunk & 1;   // even: every replay starts on the same direction buffer
   pod2g_plan *pl = new pod2g_plan;
   memset(pl, 0, sizeof(*pl));
   pl->pat = *pat;
@@ -883,8 +922,8 @@ int pcg_plan_create(const pod2g_pattern *pat, const double *vals, int batch, con
   auto capture = [&](Tm *t) -> bool {
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
     for (int i = 0; i < chunk; ++i) {
-      if (pat->mesh.dim == 2) launch_iteration<2>(pl->c, pr, cs, t);
-      else launch_iteration<3>(pl->c, pr, cs, t);
+      if (pat->mesh.dim == 2) launch_iteration<2>(pl->c, pr, cs, t, i & 1);
+      else launch_iteration<3>(pl->c, pr, cs, t, i & 1);
     }
     if (hipStreamEndCapture(cs, &pl->graph) != hipSuccess) return false;
     if (hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) != hipSuccess) {

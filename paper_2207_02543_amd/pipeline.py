@@ -198,24 +198,36 @@ def pod_basis(U: torch.Tensor, k: int):
     return P, lam
 
 
-def offline_basis(prob: Problem, n_train=None, k=None, rtol=1e-12, chunk=32, bootstrap=8):
-    """Training solves + POD.  The first `bootstrap` training solves use the
-    smoother-only cycle; their POD basis then preconditions the rest."""
+def offline_basis(prob: Problem, n_train=None, k=None, rtol=1e-12, chunk=32):
+    """Offline phase (Sec. 3.4): training solves, then POD of the snapshots
+    (Sec. 3.3).  The training solves are incremental: the first one uses
+    the smoother-only cycle; every later group (doubling in size up to
+    `chunk`) is preconditioned by the POD basis of all snapshots so far."""
     w = prob.w
     n_train = w.n_train if n_train is None else n_train
     k = w.k if k is None else k
     xis = np.stack([I.train_xi(w, i) for i in range(n_train)])
-    nb0 = min(bootstrap, n_train)
-    U0, it0 = solve_batched(prob, xis[:nb0], None, 0, rtol, chunk=chunk)
-    k0 = min(nb0 - 1, k) if nb0 > 1 else 1
-    P0, _ = pod_basis(U0, k0)
-    if n_train > nb0:
-        U1, it1 = solve_batched(prob, xis[nb0:], P0, rtol=rtol, chunk=chunk)
-        U = torch.cat([U0, U1], 0)
-    else:
-        U, it1 = U0, []
+    U = torch.empty(n_train, prob.n, dtype=torch.float64, device=prob.device)
+    iters = []
+    done, size = 0, 1
+    while done < n_train:
+        b = min(n_train, done + size)
+        P_cur = None
+        if done > 0:
+            kk = min(done, k)
+            while P_cur is None:
+                try:
+                    P_cur, _ = pod_basis(U[:done], kk)
+                except L.Pod2gError:
+                    if kk == 1:
+                        raise
+                    kk -= 1
+        Ub, its = solve_batched(prob, xis[done:b], P_cur, rtol=rtol, chunk=chunk)
+        U[done:b] = Ub
+        iters += its
+        done, size = b, min(chunk, 2 * size)
     P, lam = pod_basis(U, k)
-    return P, lam, U, it0 + it1
+    return P, lam, U, iters
 
 
 def exact_solutions(prob: Problem, xis, P, rtol=1e-12, chunk=32):

@@ -131,6 +131,9 @@ def test_setup_coarse_factor(env, dim, N, k):
     K = oprob.stiffness(w, xis[0])
     Kc = twogrid.coarse_matrix(K, P)
     np.testing.assert_allclose(Ld @ Ld.T, Kc, rtol=0, atol=1e-12 * np.abs(Kc).max())
+    Li = pipeline.device_view(pr._keepalive[0], pr.Linv, k * k, torch.float64).cpu().numpy().reshape(k, k)
+    np.testing.assert_allclose(Li @ Ld, np.eye(k), atol=1e-10)
+    assert np.all(np.triu(Li, 1) == 0.0)
     lmax = twogrid.power_lambda_max(K, 1.0 / K.diagonal(), iters=200)
     assert lamh[0] == pytest.approx(lmax, rel=1e-10)
 
@@ -291,7 +294,7 @@ def test_offline_pipeline_matches_direct_solves(env):
     flush("offline pipeline")
     w = I.small(2, 16, k=5, n_train=12)
     prob = pipeline.Problem(w)
-    Pg, lamg, Ug, iters = pipeline.offline_basis(prob, rtol=1e-12, bootstrap=4)
+    Pg, lamg, Ug, iters = pipeline.offline_basis(prob, rtol=1e-12)
     U = oprob.snapshots(w, I.train_xis(w))
     assert relerr(Ug.cpu().numpy().T, U) < 1e-9
     P, lam = opod.pod_basis(U, 5)
