@@ -93,9 +93,9 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chunk", type=int, default=8,
                     help="PCG iterations per captured graph launch (0: no graph, eager launches)")
-    ap.add_argument("--roi", action="store_true",
-                    help="bracket the timed steps with roctxProfilerResume/Pause (for "
-                         "rocprofv3 --selected-regions)")
+    ap.add_argument("--markers", action="store_true",
+                    help="launch the k_mark_begin / k_mark_end kernels around the timed steps "
+                         "(for cutting a rocprofv3 trace to them)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver "
@@ -161,16 +161,12 @@ def main(argv=None):
             raise L.Pod2gError(ret, f"step {i}: statuses {st}")
         return idx, its, rr
 
-    roctx = None
-    if args.roi:
-        import ctypes
-        roctx = ctypes.CDLL("/opt/rocm/lib/librocprofiler-sdk-roctx.so")
     for i in range(args.warmup):
         step(i, False)
     torch.cuda.synchronize()
     L.pod2g_timer_reset(timer)
-    if roctx is not None:
-        roctx.roctxProfilerResume(0)
+    if args.markers:
+        L.check(L.pod2g_mark(0), "pod2g_mark")
     t0 = time.perf_counter()
     for i in range(args.steps):
         idx, its, rr = step(args.warmup + i, True)
@@ -178,8 +174,9 @@ def main(argv=None):
         stats["relres"] += rr
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    if roctx is not None:
-        roctx.roctxProfilerPause(0)
+    if args.markers:
+        L.check(L.pod2g_mark(1), "pod2g_mark")
+        torch.cuda.synchronize()
     # accuracy of the last step against the tight FP64 solutions
     for b, j in enumerate(idx):
         stats["err"].append(float(torch.linalg.norm(u[b] - ustar[j]) / torch.linalg.norm(ustar[j])))

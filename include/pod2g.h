@@ -237,6 +237,12 @@ int pcg_plan_solve(pod2g_plan *plan, double rtol, int maxit, int beta,
                    int *iters_h, double *relres_h, int *status_h, hipStream_t stream);
 int pcg_plan_destroy(pod2g_plan *plan);
 
+/* ---- profiling markers -------------------------------------------------------
+ * Launches an empty one-thread kernel named k_mark_begin (which = 0) or
+ * k_mark_end (which = 1) on the stream, so that a kernel trace can be cut
+ * to the dispatches between them.  Asynchronous.                            */
+int pod2g_mark(int which, hipStream_t stream);
+
 /* ---- single kernels (measurement and parity checks) ---------------------
  * y_b = K_b x_b (FP64).  Asynchronous.                                      */
 int pod2g_spmv(const pod2g_pattern *pat, const double *vals, int batch,

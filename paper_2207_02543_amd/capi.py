@@ -94,6 +94,7 @@ _f = {
     "pcg_plan_solve": _sig("pcg_plan_solve", _i, [_vp, _d, _i, _i, C.POINTER(_i), C.POINTER(_d),
                                                   C.POINTER(_i), _vp]),
     "pcg_plan_destroy": _sig("pcg_plan_destroy", _i, [_vp]),
+    "pod2g_mark": _sig("pod2g_mark", _i, [_i, _vp]),
     "pod2g_spmv": _sig("pod2g_spmv", _i, [_PP, _vp, _i, _vp, _vp, _vp]),
     "pod2g_jacobi": _sig("pod2g_jacobi", _i, [_PP, _vp, _vp, _i, _d, _i, _vp, _vp, _vp, _vp]),
     "pod2g_pod_basis_bytes": _sig("pod2g_pod_basis_bytes", _sz, [_i, _i, _i]),
@@ -245,6 +246,10 @@ def pcg_plan_solve(plan, rtol, maxit, beta, batch, stream=None):
 
 def pcg_plan_destroy(plan) -> int:
     return _f["pcg_plan_destroy"](plan)
+
+
+def pod2g_mark(which: int, stream=None) -> int:
+    return _f["pod2g_mark"](which, _stream(stream))
 
 
 def pod2g_spmv(pat, vals, batch, x, y, stream=None) -> int:
