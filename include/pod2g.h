@@ -187,10 +187,13 @@ int pcg_solve(const pod2g_pattern *pat, const double *vals, int batch,
 
 /* ---- live kernel timing ----------------------------------------------------
  * A timer holds per_call pairs of HIP events (created by pod2g_timer_create,
- * released by pod2g_timer_destroy).  A timed solve records one pair around
- * each of the first per_call launches of the selected kernel and, if every
- * instance was still iterating through the first chunk of iterations,
- * adds their durations to total_ms / launches.  Kernel ids:                */
+ * released by pod2g_timer_destroy).  In the second chunk of iterations of a
+ * timed solve, the first per_call launches of the selected kernel go through
+ * hipExtLaunchKernel, whose events receive the dispatch's own start and end
+ * timestamps; if every instance was still iterating through that chunk,
+ * their durations are added to total_ms / launches.  A timed plan solve runs
+ * that chunk as individual launches (same kernels, same results) and the
+ * others as graph replays.  Kernel ids:                                     */
 #define POD2G_TK_SPMV_PQ     1   /* q = K p with p^T q (outer SpMV)            */
 #define POD2G_TK_SWEEP       2   /* damped-Jacobi sweep inside the cycle       */
 #define POD2G_TK_SWEEP_FINAL 3   /* last post-sweep with r^T s                 */
@@ -224,8 +227,8 @@ int pcg_solve_timed(const pod2g_pattern *pat, const double *vals, int batch,
  * individual kernels, and checks convergence between chunks.  The plan
  * stays valid while those buffers live and keep their sizes; their contents
  * may change between solves (new theta, new warm start, new setup in the
- * same setup workspace).  With a timer, the graph records the timer's
- * events (the timer must outlive the plan).  pcg_plan_solve is synchronous
+ * same setup workspace).  With a timer (which must outlive the plan), the
+ * second chunk of every solve is timed as described above.  pcg_plan_solve is synchronous
  * and has pcg_solve's outputs and statuses.  An odd chunk is rounded up to
  * the next even number.  Plans are host objects: create, solve and destroy
  * them from one thread.                                                     */

@@ -33,7 +33,7 @@ struct alignas(128) InstState {
   unsigned cnt[8]; // last-workgroup counters, one per reduction site
 };
 
-enum CounterSlot { CNT_A = 0, CNT_B = 1, CNT_C = 2, CNT_D = 3, CNT_E = 4 };
+enum CounterSlot { CNT_A = 0, CNT_B = 1, CNT_C = 2, CNT_D = 3, CNT_E = 4, CNT_F = 5 };
 
 // Blocks are handed to the 8 XCDs round-robin; map them so that every XCD
 // works on one contiguous range of rows (its L2 then holds that range's

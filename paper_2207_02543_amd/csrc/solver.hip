@@ -9,6 +9,8 @@
 // convergence without changing the result.
 #include "common.hpp"
 
+#include <hip/hip_ext.h>
+
 #include <math.h>
 #include <string.h>
 #include <vector>
@@ -34,7 +36,14 @@ struct Ctx {
   double *part;                  // [batch][nb][ps]
   double *ec;                    // [batch][MAXK]
   InstState *st;
+  double *bpart;                 // [bgrid][k][batch] partials of the batched restriction
+  float *rbuf;                   // [batch][n] FP32 residuals r' of the batched restriction
+  int bgrid;                     // workgroups of the batched restriction
 };
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int MAXB = 32;             // instances of one batched contraction
+constexpr int BATCH_MFMA_MIN = 4;    // batched MFMA products from this batch size
 
 __device__ __forceinline__ int inst_id() { return blockIdx.y; }
 
@@ -271,6 +280,21 @@ __global__ void __launch_bounds__(NT) k_restrict(Ctx c, const T *__restrict__ x)
   }
 }
 
+// Residual after pre-relaxation for the batched restriction:
+// r'_b = b_b - K_b x_b stored in FP32 (one thread per row, one grid row per
+// instance, no reduction).
+template <int DIM>
+__global__ void __launch_bounds__(NT) k_resid32(Ctx c, const float *__restrict__ x) {
+  const int b = inst_id();
+  if (c.st[b].done) return;
+  const int row = xcd_block(blockIdx.x, c.nb) * NT + threadIdx.x;
+  if (row >= c.n) return;
+  const size_t off = (size_t)b * c.n;
+  const float *vals = (const float *)c.svals + (size_t)b * c.vstride;
+  c.rbuf[off + row] = ((const float *)c.b32)[off + row] -
+                      row_dot<DIM>(c.colblk, vals, x + off, row, row / DIM, c.n, c.nn);
+}
+
 // Prolongation and correction: x_out = x_in + P e_c.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_prolong(Ctx c, const T *__restrict__ xin, T *__restrict__ xout) {
@@ -322,10 +346,11 @@ __global__ void __launch_bounds__(NT) k_finalize(Ctx c, const T *__restrict__ x,
   }
 }
 
-// p = s + beta p_old (gathered where K needs it), q = K p, p^T q; the
-// last block forms alpha = rho / p^T q.  Workgroup 0 also sets the input
-// scale of the next cycle from the current ||r||.
-template <int DIM>
+// q = K p and p^T q; the last block forms alpha = rho / p^T q.  With FUSED
+// the direction p = s + beta p_old is formed here (gathered where K needs
+// it, the owned rows written to pnew); otherwise k_pdir formed it already.
+// Workgroup 0 sets the input scale of the next cycle from the current ||r||.
+template <int DIM, bool FUSED>
 __global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c, const double *__restrict__ s,
                                                 const double *__restrict__ pold,
                                                 double *__restrict__ pnew) {
@@ -341,22 +366,28 @@ __global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c, const double *__restrict_
   const size_t off = (size_t)b * c.n;
   double pq = 0.0;
   if (row < c.n) {
-    constexpr int S = Stencil<DIM>::S;
     const double *vals = c.vals + (size_t)b * c.vstride;
-    const double *sb = s + off, *pb = pold + off;
-    const int node = row / DIM;
-    double kp = 0.0;
+    double kp, pv;
+    if (FUSED) {
+      constexpr int S = Stencil<DIM>::S;
+      const double *sb = s + off, *pb = pold + off;
+      const int node = row / DIM;
+      kp = 0.0;
 #pragma unroll 9
-    for (int sl = 0; sl < S; ++sl) {
-      const int col = c.colblk[sl * c.nn + node];
+      for (int sl = 0; sl < S; ++sl) {
+        const int col = c.colblk[sl * c.nn + node];
 #pragma unroll
-      for (int bc = 0; bc < DIM; ++bc) {
-        const size_t i = (size_t)col * DIM + bc;
-        kp += vals[(size_t)(sl * DIM + bc) * c.n + row] * pdir(sb[i], pb, i, beta);
+        for (int bc = 0; bc < DIM; ++bc) {
+          const size_t i = (size_t)col * DIM + bc;
+          kp += vals[(size_t)(sl * DIM + bc) * c.n + row] * pdir(sb[i], pb, i, beta);
+        }
       }
+      pv = pdir(sb[row], pb, row, beta);
+      pnew[off + row] = pv;
+    } else {
+      kp = row_dot<DIM>(c.colblk, vals, pnew + off, row, row / DIM, c.n, c.nn);
+      pv = pnew[off + row];
     }
-    const double pv = pdir(sb[row], pb, row, beta);
-    pnew[off + row] = pv;
     c.q[off + row] = kp;
     pq = pv * kp;
   }
@@ -370,6 +401,19 @@ __global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c, const double *__restrict_
     if (!(g > 0.0)) { st->done = 1; st->status = finite(g) ? POD2G_EBREAKDOWN : POD2G_ENAN; }
     st->alpha = st->rho / g;
   }
+}
+
+// p = s + beta p_old (the unfused form of the direction update).
+__global__ void __launch_bounds__(NT) k_pdir(Ctx c, const double *__restrict__ s,
+                                             const double *__restrict__ pold,
+                                             double *__restrict__ pnew) {
+  const int b = inst_id();
+  const InstState *st = c.st + b;
+  if (st->done) return;
+  const int row = blockIdx.x * NT + threadIdx.x;
+  if (row >= c.n) return;
+  const size_t off = (size_t)b * c.n;
+  pnew[off + row] = pdir(s[off + row], pold + off, row, st->beta);
 }
 
 // u += alpha p, r -= alpha q, ||r||^2 (and r^T s_old for the flexible
@@ -419,6 +463,193 @@ __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode, const double *__
       st->beta = trr / st->rho;
       st->rho = trr;
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched products with the shared basis (mixed cycle, FP32 on MFMA).
+// v_mfma_f32_16x16x4f32 operand layout (one 64-lane wave): A[i][kk] in lane
+// i + 16 kk, B[kk][j] in lane j + 16 kk, D[i][j] in lane j + 16 (i / 4),
+// register i % 4.
+// ---------------------------------------------------------------------------
+
+// Restriction for all instances at once: C[j][b] = sum_rows P[j][row] R[b][row]
+// with R the residuals r'_b (FP32, [batch][n]).  Every wave owns 64
+// consecutive rows of the workgroup's row range, stages them for all live
+// instances in LDS and accumulates all 16 x 16 output tiles on MFMA; the
+// waves' tiles are summed per workgroup; the last workgroup sums the
+// workgroups (FP64, fixed order) and applies each live instance's coarse
+// solve.
+constexpr int PW_LD = NT + 1;     // padded LDS strides: no bank conflicts between
+constexpr int RW_LD = WAVE + 1;   // the 16 columns an MFMA operand reads at once
+
+__global__ void __launch_bounds__(NT) k_ptr_b(Ctx c, const float *__restrict__ R) {
+  __shared__ float Rw[NWAVE][MAXB][RW_LD];  // 33 KB
+  extern __shared__ float Pw[];             // [k][PW_LD] basis rows of the block (dynamic)
+  __shared__ int live[MAXB];
+  __shared__ int nlive;
+  const int B = c.batch, k = c.k, n = c.n;
+  const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+  if (threadIdx.x == 0) {
+    int m = 0;
+    for (int b = 0; b < B; ++b) { live[b] = !c.st[b].done; m += live[b]; }
+    nlive = m;
+  }
+  __syncthreads();
+  if (nlive == 0) return;
+  const int tj = (k + 15) / 16, tb = (B + 15) / 16, ntile = tj * tb;
+  constexpr int MT = 8;   // every wave accumulates all tiles (at most 4 x 2) over its rows
+  f4 acc[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) acc[m] = f4{0.f, 0.f, 0.f, 0.f};
+  const int g = xcd_block(blockIdx.x, c.bgrid);
+  const int per = (c.nb + c.bgrid - 1) / c.bgrid;
+  const int blk_end = min(c.nb, (g + 1) * per);
+  const float *P = (const float *)c.sP;
+  for (int blk = g * per; blk < blk_end; ++blk) {
+    const int row = blk * NT + w * WAVE + lane;
+    for (int b = 0; b < B; ++b)
+      Rw[w][b][lane] = (live[b] && row < n) ? R[(size_t)b * n + row] : 0.f;
+    for (int j = 0; j < k; ++j) Pw[j * PW_LD + threadIdx.x] = row < n ? P[(size_t)j * n + row] : 0.f;
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      const int t = m;
+      if (t < ntile) {
+        const int j = (t / tb) * 16 + (lane & 15), bb = (t % tb) * 16 + (lane & 15);
+        for (int s4 = 0; s4 < WAVE / 4; ++s4) {
+          const int rr = 4 * s4 + (lane >> 4);
+          const float a = j < k ? Pw[j * PW_LD + w * WAVE + rr] : 0.f;
+          const float bvl = bb < B ? Rw[w][bb][rr] : 0.f;
+          acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bvl, acc[m], 0, 0, 0);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // sum the four waves' tiles of this workgroup (LDS reused), then write
+  float *Cs = &Rw[0][0][0];   // [k_pad][B_pad] accumulators, tj*16 x tb*16 <= 64 x 32
+  const int ldc = tb * 16;
+  for (int t = threadIdx.x; t < tj * 16 * ldc; t += NT) Cs[t] = 0.f;
+  __syncthreads();
+  for (int ww = 0; ww < NWAVE; ++ww) {
+    if (w == ww) {
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        const int t = m;
+        if (t < ntile) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int i = (t / tb) * 16 + 4 * (lane >> 4) + v, jj = (t % tb) * 16 + (lane & 15);
+            Cs[i * ldc + jj] += acc[m][v];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double *gp = c.bpart + (size_t)g * k * B;
+  for (int t = threadIdx.x; t < k * B; t += NT) gp[t] = (double)Cs[(t / B) * ldc + t % B];
+}
+
+// r_c of every (j, b): the workgroup partials of k_ptr_b summed by 16 threads
+// per output (strided shares, then a fixed 16-lane tree); the last workgroup
+// applies each live instance's coarse solve e_c = Linv^T (Linv r_c).
+constexpr int PTR_TPO = 16;   // threads per output
+
+__global__ void __launch_bounds__(NT) k_ptr_sum(Ctx c) {
+  __shared__ int live[MAXB];
+  __shared__ int flag;
+  __shared__ double ys[MAXK * MAXB];
+  const int B = c.batch, k = c.k;
+  const int o = (blockIdx.x * NT + threadIdx.x) / PTR_TPO, q = threadIdx.x % PTR_TPO;
+  if (threadIdx.x < B) live[threadIdx.x] = !c.st[threadIdx.x].done;
+  __syncthreads();
+  double v = 0.0;
+  if (o < k * B) v = strided_sum(c.bpart + o, q, c.bgrid, PTR_TPO, k * B);
+#pragma unroll
+  for (int d = PTR_TPO / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, PTR_TPO);
+  double *rc = c.bpart + (size_t)c.bgrid * k * B;   // k * B sums after the partials
+  if (q == 0 && o < k * B) put_partial(rc + o, v);
+  if (!arrive_last(&c.st[0].cnt[CNT_F], gridDim.x, &flag)) return;
+  for (int t = threadIdx.x; t < k * B; t += NT) {
+    const int b = t / k, i = t % k;
+    double y = 0.0;
+    if (live[b]) {
+      const double *Li = c.Linv + (size_t)b * k * k;
+      for (int j = 0; j <= i; ++j) y += Li[i * k + j] * rc[j * B + b];
+    }
+    ys[t] = y;
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < k * B; t += NT) {
+    const int b = t / k, i = t % k;
+    if (!live[b]) continue;
+    const double *Li = c.Linv + (size_t)b * k * k;
+    double e = 0.0;
+    for (int j = i; j < k; ++j) e += Li[j * k + i] * ys[b * k + j];
+    c.ec[(size_t)b * MAXK + i] = e;
+  }
+}
+
+// Prolongation and correction for all instances of a 256-row block:
+// X_out[b][row] = X_in[b][row] + sum_j P[j][row] E[j][b] with the k x B
+// product on MFMA (FP32), staged through LDS so the writes are coalesced.
+__global__ void __launch_bounds__(NT) k_prolong_b(Ctx c, const float *__restrict__ xin,
+                                                  float *__restrict__ xout) {
+  __shared__ float E[MAXK][MAXB];           // 8 KB
+  __shared__ float Out[MAXB][NT];           // 32 KB
+  __shared__ int live[MAXB];
+  __shared__ int nlive;
+  const int B = c.batch, k = c.k, n = c.n;
+  const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+  if (threadIdx.x == 0) {
+    int m = 0;
+    for (int b = 0; b < B; ++b) { live[b] = !c.st[b].done; m += live[b]; }
+    nlive = m;
+  }
+  for (int t = threadIdx.x; t < MAXK * MAXB; t += NT) {
+    const int j = t / MAXB, b = t % MAXB;
+    E[j][b] = (j < k && b < B) ? (float)c.ec[(size_t)b * MAXK + j] : 0.f;
+  }
+  __syncthreads();
+  if (nlive == 0) return;
+  const int blk = xcd_block(blockIdx.x, c.nb);
+  const int rw0 = blk * NT + w * WAVE;
+  const float *P = (const float *)c.sP;
+  const int tb = (B + 15) / 16, ks = (k + 3) / 4;
+  for (int tr = 0; tr < WAVE / 16; ++tr) {
+    // this row tile's basis entries for all k, loads in flight together
+    const int row_a = rw0 + 16 * tr + (lane & 15);
+    float av[MAXK / 4];
+#pragma unroll
+    for (int s4 = 0; s4 < MAXK / 4; ++s4) {
+      const int kk = 4 * s4 + (lane >> 4);
+      av[s4] = (s4 < ks && kk < k && row_a < n) ? P[(size_t)kk * n + row_a] : 0.f;
+    }
+    for (int t2 = 0; t2 < tb; ++t2) {
+      f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s4 = 0; s4 < MAXK / 4; ++s4) {
+        if (s4 < ks) {
+          const int kk = 4 * s4 + (lane >> 4);
+          acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s4], E[kk][t2 * 16 + (lane & 15)], acc, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int bb = t2 * 16 + (lane & 15);
+        if (bb < MAXB) Out[bb][w * WAVE + 16 * tr + 4 * (lane >> 4) + v] = acc[v];
+      }
+    }
+  }
+  __syncthreads();
+  const int row = blk * NT + threadIdx.x;
+  if (row >= n) return;
+  for (int b = 0; b < B; ++b) {
+    if (!live[b]) continue;
+    const size_t off = (size_t)b * n;
+    xout[off + row] = (xin ? xin[off + row] : 0.f) + Out[b][threadIdx.x];
   }
 }
 
@@ -472,52 +703,25 @@ __global__ void __launch_bounds__(NT) k_replace(Ctx c, const int *__restrict__ f
 // ---------------------------------------------------------------------------
 static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// Per-call timing: records an event pair around the first per_call
-// launches of the timer's kernel.
+// Per-call timing: the first per_call launches of the timer's kernel in a
+// solve go through hipExtLaunchKernel, whose start/stop events receive the
+// dispatch's own begin/end timestamps (the clock a kernel trace reads).
 struct Tm {
   pod2g_timer *t;
   int used;
-  int capturing;   // inside stream capture: record as graph event nodes
-  int failed;      // a record failed: no further timing in this call / plan
 };
 
-// Inside stream capture an event record must become an explicit graph node
-// (a captured hipEventRecord only marks a dependency): add the node after
-// the stream's current capture dependencies and make it the new one.
-static bool record_node(hipEvent_t e, hipStream_t s) {
-  hipStreamCaptureStatus cst;
-  unsigned long long id = 0;
-  hipGraph_t g = nullptr;
-  const hipGraphNode_t *deps = nullptr;
-  size_t ndeps = 0;
-  if (hipStreamGetCaptureInfo_v2(s, &cst, &id, &g, &deps, &ndeps) != hipSuccess ||
-      cst != hipStreamCaptureStatusActive || !g)
-    return false;
-  hipGraphNode_t node;
-  if (hipGraphAddEventRecordNode(&node, g, deps, ndeps, e) != hipSuccess) return false;
-  return hipStreamUpdateCaptureDependencies(s, &node, 1, hipStreamSetCaptureDependencies) == hipSuccess;
-}
-
-static inline bool record(hipEvent_t e, hipStream_t s, int capturing) {
-  if (capturing) return record_node(e, s);
-  return hipEventRecord(e, s) == hipSuccess;
-}
-
-struct TimeScope {
-  Tm *tm;
-  hipStream_t s;
-  bool on;
-  TimeScope(Tm *m, int id, hipStream_t st) : tm(m), s(st) {
-    on = tm && tm->t && !tm->failed && tm->t->kernel == id && tm->used < tm->t->per_call;
-    if (on && !record(tm->t->start[tm->used], s, tm->capturing)) { tm->failed = 1; on = false; }
+template <typename F, typename... Args>
+static void launch(Tm *tm, int id, F kernel, dim3 grid, dim3 block, unsigned shm,
+                   hipStream_t s, Args... args) {
+  if (tm && tm->t && tm->t->kernel == id && tm->used < tm->t->per_call) {
+    hipExtLaunchKernelGGL(kernel, grid, block, shm, s, tm->t->start[tm->used],
+                          tm->t->stop[tm->used], 0, args...);
+    tm->used++;
+  } else {
+    hipLaunchKernelGGL(kernel, grid, block, shm, s, args...);
   }
-  ~TimeScope() {
-    if (on) {
-      if (record(tm->t->stop[tm->used], s, tm->capturing)) tm->used++;
-      else tm->failed = 1;
-    }
-  }
-};
+}
 
 // Timing never fails a solve: a pair whose duration cannot be read is skipped.
 static void accumulate(pod2g_timer *t, int used) {
@@ -534,8 +738,14 @@ static void accumulate(pod2g_timer *t, int used) {
 }
 
 struct Layout {
-  size_t st, ec, part, vec, vec32, flags, total;
+  size_t st, ec, part, bpart, vec, vec32, flags, total;
+  int bgrid;
 };
+
+static int batched_grid(int n) {
+  const int nb = ceil_div(n, NT);
+  return nb < 512 ? nb : 512;
+}
 
 static Layout layout(int n, int batch, int k, int precision) {
   const int nb = ceil_div(n, NT);
@@ -545,10 +755,14 @@ static Layout layout(int n, int batch, int k, int precision) {
   L.st = o;    o += align256(sizeof(InstState) * (size_t)batch);
   L.ec = o;    o += align256(sizeof(double) * MAXK * (size_t)batch);
   L.part = o;  o += align256(sizeof(double) * (size_t)ps * nb * batch);
+  L.bgrid = batched_grid(n);
+  L.bpart = o;
+  if (precision == POD2G_MIXED && batch >= BATCH_MFMA_MIN && batch <= MAXB && k > 0)
+    o += align256(sizeof(double) * (size_t)(L.bgrid + 1) * k * batch);
   L.flags = o; o += align256(sizeof(int) * (size_t)batch);
   L.vec = o;   o += 7 * align256(sizeof(double) * (size_t)n * batch);   // r p0 p1 q s xa xb
   L.vec32 = o;
-  if (precision == POD2G_MIXED) o += align256(sizeof(float) * (size_t)n * batch);  // b32
+  if (precision == POD2G_MIXED) o += 2 * align256(sizeof(float) * (size_t)n * batch);  // b32, rbuf
   L.total = o;
   return L;
 }
@@ -575,6 +789,8 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
   c.st = (InstState *)(w + Lo.st);
   c.ec = (double *)(w + Lo.ec);
   c.part = (double *)(w + Lo.part);
+  c.bpart = (double *)(w + Lo.bpart);
+  c.bgrid = Lo.bgrid;
   const size_t vb = align256(sizeof(double) * (size_t)n * batch);
   c.r = (double *)(w + Lo.vec);
   c.p0 = (double *)(w + Lo.vec + vb);
@@ -584,6 +800,9 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
   c.xa = (void *)(w + Lo.vec + 5 * vb);
   c.xb = (void *)(w + Lo.vec + 6 * vb);
   c.b32 = precision == POD2G_MIXED ? (void *)(w + Lo.vec32) : nullptr;
+  c.rbuf = precision == POD2G_MIXED
+               ? (float *)(w + Lo.vec32 + align256(sizeof(float) * (size_t)n * batch))
+               : nullptr;
   c.mixed = precision == POD2G_MIXED;
   if (prec) {
     c.omega = prec->omega;
@@ -600,6 +819,11 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
   }
 }
 
+template <typename T>
+static bool batched_products(const Ctx &c) {
+  return sizeof(T) == 4 && c.batch >= BATCH_MFMA_MIN && c.batch <= MAXB;
+}
+
 // The cycle s = B r on the instances that are not done.  Assumes xa holds
 // the first pre-relaxation sweep when nu_pre >= 1 (made by the producer of
 // r).  With want_dot the last kernel also forms rho and beta.
@@ -611,25 +835,34 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
   T *cur = xa, *oth = xb;
   const bool have_x = pr->nu_pre >= 1;
   for (int i = 1; i < pr->nu_pre; ++i) {
-    {
-      TimeScope ts(tm, POD2G_TK_SWEEP, stream);
-      hipLaunchKernelGGL((k_sweep<DIM, T, false>), grid, blk, 0, stream, c, cur, oth, 0);
-    }
+    launch(tm, POD2G_TK_SWEEP, k_sweep<DIM, T, false>, grid, blk, 0, stream, c, (const T *)cur, oth, 0);
     T *t = cur; cur = oth; oth = t;
   }
   bool have = have_x;
-  if (c.k > 0) {
-    {
-      TimeScope ts(tm, POD2G_TK_RESTRICT, stream);
-      if (have)
-        hipLaunchKernelGGL((k_restrict<DIM, T, false>), grid, blk, 0, stream, c, cur);
-      else
-        hipLaunchKernelGGL((k_restrict<DIM, T, true>), grid, blk, 0, stream, c, (const T *)nullptr);
+  if (c.k > 0 && batched_products<T>(c)) {
+    // shared basis, many instances: one MFMA contraction over the batch
+    if (have) {
+      launch(tm, POD2G_TK_RESTRICT, k_resid32<DIM>, grid, blk, 0, stream, c, (const float *)cur);
+      hipLaunchKernelGGL(k_ptr_b, dim3(c.bgrid), blk, sizeof(float) * c.k * PW_LD, stream, c,
+                         (const float *)c.rbuf);
+    } else {
+      // x = 0: the residual is the cycle input itself
+      hipLaunchKernelGGL(k_ptr_b, dim3(c.bgrid), blk, sizeof(float) * c.k * PW_LD, stream, c,
+                         (const float *)c.b32);
     }
-    {
-      TimeScope ts(tm, POD2G_TK_PROLONG, stream);
-      hipLaunchKernelGGL((k_prolong<T>), grid, blk, 0, stream, c, have ? (const T *)cur : (const T *)nullptr, oth);
-    }
+    hipLaunchKernelGGL(k_ptr_sum, dim3(ceil_div((long long)c.k * c.batch * PTR_TPO, NT)), blk, 0,
+                       stream, c);
+    launch(tm, POD2G_TK_PROLONG, k_prolong_b, dim3(c.nb), blk, 0, stream, c,
+           have ? (const float *)cur : (const float *)nullptr, (float *)oth);
+    T *t = cur; cur = oth; oth = t;
+    have = true;
+  } else if (c.k > 0) {
+    if (have)
+      launch(tm, POD2G_TK_RESTRICT, k_restrict<DIM, T, false>, grid, blk, 0, stream, c, (const T *)cur);
+    else
+      launch(tm, POD2G_TK_RESTRICT, k_restrict<DIM, T, true>, grid, blk, 0, stream, c, (const T *)nullptr);
+    launch(tm, POD2G_TK_PROLONG, k_prolong<T>, grid, blk, 0, stream, c,
+           have ? (const T *)cur : (const T *)nullptr, oth);
     T *t = cur; cur = oth; oth = t;
     have = true;
   }
@@ -651,13 +884,11 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
   }
   for (int i = 0; i < pr->nu_post; ++i) {
     const bool fin = (i == pr->nu_post - 1);
-    if (fin) {
-      TimeScope ts(tm, POD2G_TK_SWEEP_FINAL, stream);
-      hipLaunchKernelGGL((k_sweep<DIM, T, true>), grid, blk, 0, stream, c, cur, oth, want_dot);
-    } else {
-      TimeScope ts(tm, POD2G_TK_SWEEP, stream);
-      hipLaunchKernelGGL((k_sweep<DIM, T, false>), grid, blk, 0, stream, c, cur, oth, 0);
-    }
+    if (fin)
+      launch(tm, POD2G_TK_SWEEP_FINAL, k_sweep<DIM, T, true>, grid, blk, 0, stream, c, (const T *)cur, oth,
+             want_dot);
+    else
+      launch(tm, POD2G_TK_SWEEP, k_sweep<DIM, T, false>, grid, blk, 0, stream, c, (const T *)cur, oth, 0);
     T *t = cur; cur = oth; oth = t;
   }
   if (pr->nu_post == 0)
@@ -679,6 +910,8 @@ static void launch_first(const Ctx &c, const pod2g_prec *pr, hipStream_t stream)
   else if (wx) hipLaunchKernelGGL((k_cyc_first<double>), grid, dim3(NT), 0, stream, c, wx);
 }
 
+constexpr long long FUSE_DIR_MAX = 1ll << 20;   // rows x instances
+
 // One PCG iteration.  Iterations alternate the two direction buffers
 // (parity 0 reads p0 and writes p1), so chunks have an even length.
 template <int DIM>
@@ -687,24 +920,25 @@ static void launch_iteration(const Ctx &c, const pod2g_prec *pr, hipStream_t str
   dim3 grid(c.nb, c.batch), blk(NT);
   const double *pold = parity ? c.p1 : c.p0;
   double *pnew = parity ? c.p0 : c.p1;
-  {
-    TimeScope ts(tm, POD2G_TK_SPMV_PQ, stream);
-    hipLaunchKernelGGL(k_spmv_pq<DIM>, grid, blk, 0, stream, c, pr ? (const double *)c.s : (const double *)c.r,
-                       pold, pnew);
+  const double *sdir = pr ? (const double *)c.s : (const double *)c.r;
+  // small problems are launch-bound: fold the direction update into the
+  // SpMV; large ones are bandwidth-bound: a second gathered vector costs
+  // more than one elementwise pass
+  if ((long long)c.n * c.batch <= FUSE_DIR_MAX) {
+    launch(tm, POD2G_TK_SPMV_PQ, k_spmv_pq<DIM, true>, grid, blk, 0, stream, c, sdir, pold, pnew);
+  } else {
+    hipLaunchKernelGGL(k_pdir, grid, blk, 0, stream, c, sdir, pold, pnew);
+    launch(tm, POD2G_TK_SPMV_PQ, k_spmv_pq<DIM, false>, grid, blk, 0, stream, c, sdir, pold, pnew);
   }
   if (pr) {
     const int mode = pr->nu_pre >= 1 ? 1 : 2;
-    {
-      TimeScope ts(tm, POD2G_TK_UPDATE, stream);
-      if (pr->precision == POD2G_MIXED)
-        hipLaunchKernelGGL(k_update<float>, grid, blk, 0, stream, c, mode, (const double *)pnew);
-      else
-        hipLaunchKernelGGL(k_update<double>, grid, blk, 0, stream, c, mode, (const double *)pnew);
-    }
+    if (pr->precision == POD2G_MIXED)
+      launch(tm, POD2G_TK_UPDATE, k_update<float>, grid, blk, 0, stream, c, mode, (const double *)pnew);
+    else
+      launch(tm, POD2G_TK_UPDATE, k_update<double>, grid, blk, 0, stream, c, mode, (const double *)pnew);
     launch_cycle_any<DIM>(c, pr, stream, 1, tm);
   } else {
-    TimeScope ts(tm, POD2G_TK_UPDATE, stream);
-    hipLaunchKernelGGL(k_update<double>, grid, blk, 0, stream, c, 0, (const double *)pnew);
+    launch(tm, POD2G_TK_UPDATE, k_update<double>, grid, blk, 0, stream, c, 0, (const double *)pnew);
   }
 }
 
@@ -728,7 +962,6 @@ struct pod2g_plan {
   hipGraph_t graph;
   hipGraphExec_t exec;
   pod2g_timer *timer;
-  int timed;   // event pairs captured in the chunk
 };
 
 namespace pod2g {
@@ -756,25 +989,29 @@ static int pcg_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int bet
   Layout Lo = layout(c.n, c.batch, c.k, pr ? pr->precision : POD2G_FP64);
   int *flags_d = (int *)((char *)c.st - Lo.st + Lo.flags);
   int chunk = plan ? plan->chunk : 4;
-  bool first = true;
+  int nchunk = 0;       // chunks launched since the last (re)start
+  int launched = 0;     // iterations launched since the last (re)start
   for (int guard = 0; guard < 10000000; ++guard) {
-    Tm tm = {timer, 0, 0, 0};
-    if (plan) {
+    // the second chunk of a solve is the timed one: caches are warm and no
+    // instance can have converged before it unless the solve is very short
+    const bool timed = timer && nchunk == 1;
+    Tm tm = {timer, 0};
+    if (plan && !timed) {
       POD2G_HIP_CHECK(hipGraphLaunch(plan->exec, stream));
     } else {
-      for (int i = 0; i < chunk; ++i) launch_iteration<DIM>(c, pr, stream, first ? &tm : nullptr, i & 1);
+      for (int i = 0; i < chunk; ++i) launch_iteration<DIM>(c, pr, stream, timed ? &tm : nullptr, i & 1);
       POD2G_HIP_CHECK(hipGetLastError());
     }
+    launched += chunk;
+    ++nchunk;
     int st = read_states(c, h, stream);
     if (st) return st;
-    if (first && timer) {
+    if (timed) {
       // count the timed launches only if every instance was live through the chunk
       bool live = true;
-      for (int b = 0; b < c.batch; ++b) live = live && h[b].iter >= chunk;
-      const int used = plan ? plan->timed : (tm.failed ? 0 : tm.used);
-      if (live) accumulate(timer, used);
+      for (int b = 0; b < c.batch; ++b) live = live && h[b].iter >= launched;
+      if (live) accumulate(timer, tm.used);
     }
-    first = false;
     bool all_done = true;
     for (int b = 0; b < c.batch; ++b) all_done = all_done && h[b].done;
     if (!plan && chunk < 16) chunk *= 2;
@@ -796,6 +1033,8 @@ static int pcg_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int bet
     hipLaunchKernelGGL(k_replace, grid, blk, 0, stream, c, (const int *)flags_d, pr ? 1 : 0);
     start_cycle();
     if (!plan) chunk = 4;
+    nchunk = 0;
+    launched = 0;
   }
   int ret = POD2G_OK;
   for (int b = 0; b < c.batch; ++b) {
@@ -929,35 +1168,24 @@ int pcg_plan_create(const pod2g_pattern *pat, const double *vals, int batch, con
   hipStream_t cs;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { delete pl; return POD2G_EHIP; }
   const pod2g_prec *pr = prec ? &pl->prec : nullptr;
-  Tm tm = {timer, 0, 1, 0};
-  auto capture = [&](Tm *t) -> bool {
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
     for (int i = 0; i < chunk; ++i) {
-      if (pat->mesh.dim == 2) launch_iteration<2>(pl->c, pr, cs, t, i & 1);
-      else launch_iteration<3>(pl->c, pr, cs, t, i & 1);
+      if (pat->mesh.dim == 2) launch_iteration<2>(pl->c, pr, cs, nullptr, i & 1);
+      else launch_iteration<3>(pl->c, pr, cs, nullptr, i & 1);
     }
-    if (hipStreamEndCapture(cs, &pl->graph) != hipSuccess) return false;
-    if (hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) != hipSuccess) {
-      (void)hipGraphDestroy(pl->graph);
-      pl->graph = nullptr;
-      return false;
-    }
-    return true;
-  };
-  bool ok = capture(timer ? &tm : nullptr);
-  if (!ok && timer) {
-    // the timing nodes are optional: capture again without them
-    (void)hipGetLastError();
-    tm.failed = 1;
-    ok = capture(nullptr);
+    ok = hipStreamEndCapture(cs, &pl->graph) == hipSuccess;
+  }
+  if (ok && hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(pl->graph);
+    pl->graph = nullptr;
+    ok = false;
   }
   (void)hipStreamDestroy(cs);
   if (!ok) {
     delete pl;
     return POD2G_EHIP;
   }
-  pl->timed = tm.failed ? 0 : tm.used;
-  if (tm.failed) (void)hipGetLastError();   // timing unavailable: clear its error, keep the plan
   *out = pl;
   return POD2G_OK;
 }

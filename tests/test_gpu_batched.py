@@ -1,0 +1,62 @@
+"""Batched mixed-precision path (shared pattern and basis, FP32 cycle with
+the restriction and prolongation as MFMA contractions over the batch)
+against the oracle's FP32-emulated cycle and its FP64 PCG."""
+import numpy as np
+import pytest
+
+from gpu_helpers import flush, relerr
+from oracle import pcg as opcg, problem as oprob, twogrid
+from paper_2207_02543_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(dim, N, k, batch):
+    import torch
+    from paper_2207_02543_amd import capi, pipeline
+    w = I.small(dim, N, k=k, n_train=max(12, k + 2))
+    P, lam, U = oprob.basis(w, I.train_xis(w))
+    prob = pipeline.Problem(w)
+    xis = I.query_xis(w, batch)
+    sysm = prob.alloc_system(batch, fp32=True)
+    prob.assemble(sysm, xis)
+    pr = prob.setup(sysm, torch.tensor(np.ascontiguousarray(P.T), device="cuda"), precision=capi.MIXED)
+    return w, P, prob, xis, sysm, pr
+
+
+@pytest.mark.parametrize("dim,N,k,batch", [(2, 30, 10, 5), (3, 7, 18, 6), (2, 9, 33, 4), (2, 12, 6, 33)])
+def test_batched_mixed_cycle(dim, N, k, batch):
+    import torch
+    flush(f"batched cycle dim={dim} N={N} k={k} batch={batch}")
+    w, P, prob, xis, sysm, pr = _setup(dim, N, k, batch)
+    r = np.random.default_rng(8).standard_normal((batch, w.n)) * 1e-2
+    rd = torch.tensor(r, device="cuda")
+    sd = torch.empty_like(rd)
+    prob.apply(pr, rd, sd)
+    torch.cuda.synchronize()
+    s = sd.cpu().numpy()
+    for b in range(batch):
+        K = oprob.stiffness(w, xis[b])
+        ref = twogrid.TwoGrid(K, P, w.omega, precision="fp32")(r[b])
+        assert relerr(s[b], ref) < 5e-6, b
+
+
+@pytest.mark.parametrize("dim,N,k,batch", [(2, 40, 12, 4), (3, 8, 16, 8)])
+def test_batched_mixed_pcg(dim, N, k, batch):
+    import torch
+    from paper_2207_02543_amd import capi
+    flush(f"batched pcg dim={dim} N={N} k={k} batch={batch}")
+    w, P, prob, xis, sysm, pr = _setup(dim, N, k, batch)
+    queries = [oprob.query(w, xis[j], I.noise(w, j)) for j in range(batch)]
+    u = torch.tensor(np.stack([q.x0 for q in queries]), device="cuda")
+    ret, it, rr, st = prob.solve(sysm, pr, u)
+    assert ret == capi.OK, st
+    u = u.cpu().numpy()
+    for j, q in enumerate(queries):
+        ref64 = oprob.solve_query(w, q, P, precision="fp64", beta="fr")
+        ref32 = oprob.solve_query(w, q, P, precision="fp32", beta="pr")
+        flush(f"  {j}: gpu {it[j]} relres {rr[j]:.2e}; oracle fp32 {ref32.iters} fp64 {ref64.iters}")
+        assert abs(it[j] - ref32.iters) <= 2
+        assert rr[j] <= w.tol
+        assert relerr(u[j], ref64.u) <= 1e-6
+        assert np.linalg.norm(q.f - q.K @ u[j]) / np.linalg.norm(q.f) <= 1.01 * w.tol
