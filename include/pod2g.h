@@ -115,6 +115,7 @@ typedef struct pod2g_prec {
                            the cycle's coarse solve is e_c = Linv^T (Linv r_c) */
   double *lam;          /* [batch] power-iteration estimate of lambda_max(D^-1 K) */
   int *status;          /* [batch] per-instance setup status (device) */
+  void *work;           /* the setup workspace this handle lives in */
 } pod2g_prec;
 
 const char *pod2g_strerror(int status);
@@ -155,6 +156,12 @@ int pod2g_setup(const pod2g_pattern *pat, const double *vals, const float *vals3
                 const double *dinv, const double *P, int k, double omega,
                 int nu_pre, int nu_post, int precision, int batch, int power_iters,
                 void *work, size_t bytes, pod2g_prec *out, hipStream_t stream);
+/* Redoes the setup of instance `slot` of an existing handle, in place, from
+ * that instance's current vals / dinv (after the caller re-assembled it):
+ * K P, K_c, L, Linv, status, lambda estimate and the FP32 D^-1.  The shared
+ * FP32 basis and the other instances are left alone.  Asynchronous.
+ * Errors: EINVAL (slot out of range, handle without workspace), EHIP.      */
+int pod2g_setup_slot(const pod2g_prec *prec, int slot, int power_iters, hipStream_t stream);
 /* Synchronous: copies the per-instance setup status (and, if lam_h is not
  * NULL, the lambda_max estimates) to host arrays of length batch.          */
 int pod2g_setup_status(const pod2g_prec *prec, int *status_h, double *lam_h,
@@ -239,6 +246,61 @@ int pcg_plan_create(const pod2g_pattern *pat, const double *vals, int batch,
 int pcg_plan_solve(pod2g_plan *plan, double rtol, int maxit, int beta,
                    int *iters_h, double *relres_h, int *status_h, hipStream_t stream);
 int pcg_plan_destroy(pod2g_plan *plan);
+
+/* ---- served solves (continuous batching over slot groups) -----------------
+ * Many independent queries theta (Sec. 3, the multi-query setting) arrive
+ * over time.  A server owns n_groups slot groups; group g is one problem
+ * class: one pattern, one basis P and prec->batch slots, each slot holding
+ * one query's K, D^-1, coarse factor (the preconditioner handle's arrays),
+ * u and CG state (the group's solve workspace, pcg_solve_bytes(pat,
+ * prec->batch, prec->k, prec->precision) bytes).  The caller writes a
+ * query into a free slot (pod2g_assemble on the slot's rows with batch 1,
+ * pod2g_setup_slot, u_slot = x0) and calls pod2g_server_admit.
+ * pod2g_serve_step launches one HIP graph that advances every live slot of
+ * every group by `chunk` PCG iterations (Alg. 3, the same kernels and
+ * arithmetic as pcg_solve with batch = prec->batch), forms the true
+ * residual of the admitted and the stopped slots, and either finishes a
+ * slot or restarts it from its true residual (the exit check of pcg_solve).
+ * It then copies one pod2g_slot_info per slot (groups in order, slots in
+ * order) to info_h; done = 1 marks a finished solve whose u is final.
+ * Steps are asynchronous: synchronize the stream before reading info_h
+ * (pinned host memory keeps the copy asynchronous).  A slot's result is
+ * bitwise the one pcg_solve gives for it in a batch of the same size,
+ * whatever the other slots hold.  All calls of one server go to one stream
+ * from one host thread.  Errors: EINVAL, ESIZE, EHIP.                      */
+typedef struct pod2g_slot_info {
+  int done;        /* 1: solve finished (or slot free), 0: running */
+  int iter;        /* completed PCG iterations */
+  int status;      /* POD2G_OK, EMAXIT, EBREAKDOWN, ENAN or the setup error */
+  int pad;
+  double relres;   /* true ||f - K u|| / ||f|| of the final iterate */
+} pod2g_slot_info;
+
+typedef struct pod2g_group {
+  const pod2g_pattern *pat;
+  const double *vals;     /* [batch][nvals], the handle's vals */
+  const pod2g_prec *prec; /* batch = slots of the group (required) */
+  const double *f;        /* [n] */
+  double *u;              /* [batch][n] */
+  void *work;             /* solve workspace of the group */
+  size_t bytes;
+} pod2g_group;
+
+typedef struct pod2g_server pod2g_server;
+/* Captures the step graph; every slot starts free.  chunk >= 2, even
+ * (an odd chunk is rounded up).  The groups' buffers must outlive the
+ * server and keep their addresses.                                        */
+int pod2g_server_create(const pod2g_group *groups, int n_groups, int chunk,
+                        pod2g_server **out, hipStream_t stream);
+/* Starts the solve of slot `slot` of group `group` from u_slot = x0 with
+ * tolerance rtol, iteration limit maxit and beta kind; a slot whose setup
+ * failed finishes at the next step with that setup status.  The slot must
+ * not be running.  Asynchronous.                                           */
+int pod2g_server_admit(pod2g_server *srv, int group, int slot, double rtol, int maxit,
+                       int beta, hipStream_t stream);
+int pod2g_serve_step(pod2g_server *srv, pod2g_slot_info *info_h, hipStream_t stream);
+int pod2g_server_slots(const pod2g_server *srv);   /* total slots, or EINVAL */
+int pod2g_server_destroy(pod2g_server *srv);
 
 /* ---- profiling markers -------------------------------------------------------
  * Launches an empty one-thread kernel named k_mark_begin (which = 0) or

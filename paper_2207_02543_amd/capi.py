@@ -44,7 +44,17 @@ class Prec(C.Structure):
                 ("vals", C.c_void_p), ("vals32", C.c_void_p), ("dinv", C.c_void_p),
                 ("P", C.c_void_p), ("P32", C.c_void_p), ("dinv32", C.c_void_p),
                 ("KP", C.c_void_p), ("L", C.c_void_p), ("Linv", C.c_void_p), ("lam", C.c_void_p),
-                ("status", C.c_void_p)]
+                ("status", C.c_void_p), ("work", C.c_void_p)]
+
+
+class SlotInfo(C.Structure):
+    _fields_ = [("done", C.c_int), ("iter", C.c_int), ("status", C.c_int), ("pad", C.c_int),
+                ("relres", C.c_double)]
+
+
+class Group(C.Structure):
+    _fields_ = [("pat", C.c_void_p), ("vals", C.c_void_p), ("prec", C.c_void_p), ("f", C.c_void_p),
+                ("u", C.c_void_p), ("work", C.c_void_p), ("bytes", C.c_size_t)]
 
 
 class Timer(C.Structure):
@@ -77,6 +87,13 @@ _f = {
     "pod2g_setup_bytes": _sig("pod2g_setup_bytes", _sz, [_PP, _i, _i, _i]),
     "pod2g_setup": _sig("pod2g_setup", _i, [_PP, _vp, _vp, _vp, _vp, _i, _d, _i, _i, _i, _i, _i,
                                             _vp, _sz, _PR, _vp]),
+    "pod2g_setup_slot": _sig("pod2g_setup_slot", _i, [_PR, _i, _i, _vp]),
+    "pod2g_server_create": _sig("pod2g_server_create", _i, [C.POINTER(Group), _i, _i,
+                                                            C.POINTER(_vp), _vp]),
+    "pod2g_server_admit": _sig("pod2g_server_admit", _i, [_vp, _i, _i, _d, _i, _i, _vp]),
+    "pod2g_serve_step": _sig("pod2g_serve_step", _i, [_vp, _vp, _vp]),
+    "pod2g_server_slots": _sig("pod2g_server_slots", _i, [_vp]),
+    "pod2g_server_destroy": _sig("pod2g_server_destroy", _i, [_vp]),
     "pod2g_setup_status": _sig("pod2g_setup_status", _i, [_PR, C.POINTER(_i), C.POINTER(_d), _vp]),
     "pod2g_apply_bytes": _sig("pod2g_apply_bytes", _sz, [_PR]),
     "pod2g_apply": _sig("pod2g_apply", _i, [_PR, _vp, _vp, _vp, _sz, _vp]),
@@ -168,6 +185,10 @@ def pod2g_setup(pat, vals, vals32, dinv, P, k, omega, nu_pre, nu_post, precision
                              _ptr(work), nbytes, C.byref(out), _stream(stream))
 
 
+def pod2g_setup_slot(prec: Prec, slot: int, power_iters: int, stream=None) -> int:
+    return _f["pod2g_setup_slot"](C.byref(prec), slot, power_iters, _stream(stream))
+
+
 def pod2g_setup_status(prec: Prec, stream=None):
     st = (C.c_int * prec.batch)()
     lam = (C.c_double * prec.batch)()
@@ -246,6 +267,39 @@ def pcg_plan_solve(plan, rtol, maxit, beta, batch, stream=None):
 
 def pcg_plan_destroy(plan) -> int:
     return _f["pcg_plan_destroy"](plan)
+
+
+# ---- served solves ----------------------------------------------------------
+def pod2g_server_create(groups, chunk, stream=None):
+    """groups: list of (pattern, vals, prec, f, u, work, nbytes); the Pattern
+    and Prec structures must stay alive while the server does.  Returns the
+    opaque server handle (int) or raises Pod2gError."""
+    arr = (Group * len(groups))()
+    for i, (pat, vals, prec, f, u, work, nbytes) in enumerate(groups):
+        arr[i] = Group(C.addressof(pat), _ptr(vals), C.addressof(prec), _ptr(f), _ptr(u), _ptr(work),
+                       nbytes)
+    h = C.c_void_p()
+    check(_f["pod2g_server_create"](arr, len(groups), chunk, C.byref(h), _stream(stream)),
+          "pod2g_server_create")
+    return h.value
+
+
+def pod2g_server_admit(server, group, slot, rtol, maxit, beta, stream=None) -> int:
+    return _f["pod2g_server_admit"](server, group, slot, float(rtol), int(maxit), int(beta),
+                                    _stream(stream))
+
+
+def pod2g_serve_step(server, info, stream=None) -> int:
+    """info: pinned host tensor (uint8) of pod2g_server_slots * sizeof(SlotInfo) bytes."""
+    return _f["pod2g_serve_step"](server, _ptr(info), _stream(stream))
+
+
+def pod2g_server_slots(server) -> int:
+    return _f["pod2g_server_slots"](server)
+
+
+def pod2g_server_destroy(server) -> int:
+    return _f["pod2g_server_destroy"](server)
 
 
 def pod2g_mark(which: int, stream=None) -> int:

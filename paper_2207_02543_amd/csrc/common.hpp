@@ -29,8 +29,11 @@ struct alignas(128) InstState {
   int iter, maxit, done, status;
   int restart;     // next beta is forced to 0
   int beta_kind;
-  int pad1, pad2;
+  int checked;     // served solve: the true residual of the final iterate is known
+  int pending;     // served solve: r is replaced by the true residual in the next update
   unsigned cnt[8]; // last-workgroup counters, one per reduction site
+  int fresh;       // served solve: admitted, r0 = f - K x0 not formed yet
+  int pad1;
 };
 
 enum CounterSlot { CNT_A = 0, CNT_B = 1, CNT_C = 2, CNT_D = 3, CNT_E = 4, CNT_F = 5 };

@@ -264,6 +264,68 @@ size_t pod2g_setup_bytes(const pod2g_pattern *pat, int k, int batch, int precisi
   return setup_layout(pat->n, k, batch, precision).total;
 }
 
+}  // extern "C"
+
+// Setup kernels for instances b0 .. b0 + cnt - 1 of handle pr, whose
+// buffers sit in the setup workspace w with layout S (for pr.batch).
+static int setup_run(const pod2g_prec &pr, const SetupLayout &S, char *w, int b0, int cnt,
+                     int power_iters, bool convert_p, hipStream_t stream) {
+  const pod2g_pattern *pat = &pr.pat;
+  const int n = pat->n, dim = pat->mesh.dim, k = pr.k;
+  const size_t ntri = (size_t)k * (k + 1) / 2;
+  const int nb = ceil_div(n, NT);
+  const double *vals = pr.vals + (size_t)b0 * pat->nvals;
+  const double *dinv = pr.dinv + (size_t)b0 * n;
+  int *status = pr.status + b0;
+  double *lam = pr.lam + b0;
+  InstState *pst = (InstState *)(w + S.pst) + b0;
+  double *KP = k > 0 ? pr.KP + (size_t)b0 * k * n : nullptr;
+  double *L = k > 0 ? pr.L + (size_t)b0 * k * k : nullptr;
+  double *Linv = k > 0 ? pr.Linv + (size_t)b0 * k * k : nullptr;
+  double *kcpart = (double *)(w + S.kcpart) + (size_t)b0 * S.nbk * (ntri > 0 ? ntri : 1);
+  double *ppart = (double *)(w + S.ppart) + (size_t)b0 * nb;
+  double *pw0 = (double *)(w + S.pw) + (size_t)b0 * n;
+  double *pw1 = (double *)(w + S.pw + align256(sizeof(double) * (size_t)pr.batch * n)) + (size_t)b0 * n;
+
+  hipLaunchKernelGGL(k_setup_init, dim3(ceil_div(cnt, 64)), dim3(64), 0, stream, pst, status, lam,
+                     cnt, n);
+  if (k > 0) {
+    dim3 gk(nb, cnt, ceil_div(k, KP_CH));
+    if (dim == 2)
+      hipLaunchKernelGGL(k_kp<2>, gk, dim3(NT), 0, stream, n, pat->n_nodes, k, pat->nvals,
+                         pat->colblk, vals, pr.P, KP);
+    else
+      hipLaunchKernelGGL(k_kp<3>, gk, dim3(NT), 0, stream, n, pat->n_nodes, k, pat->nvals,
+                         pat->colblk, vals, pr.P, KP);
+    hipLaunchKernelGGL(k_kc, dim3(S.nbk, cnt), dim3(NT), 0, stream, n, k, S.rows_per_wg, S.nbk,
+                       pr.P, (const double *)KP, kcpart, L, Linv, status, pst);
+    if (convert_p && pr.precision == POD2G_MIXED)
+      hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(NT), 0, stream, (size_t)k * n, pr.P, pr.P32);
+  }
+  if (pr.precision == POD2G_MIXED)
+    hipLaunchKernelGGL(k_to_f32, dim3(2048), dim3(NT), 0, stream, (size_t)cnt * n, dinv,
+                       pr.dinv32 + (size_t)b0 * n);
+  if (power_iters > 0) {
+    hipLaunchKernelGGL(k_fill, dim3(1024), dim3(NT), 0, stream, (size_t)cnt * n, 1.0, pw0);
+    double *x = pw0, *y = pw1;
+    for (int it = 0; it < power_iters; ++it) {
+      if (dim == 2)
+        hipLaunchKernelGGL(k_power<2>, dim3(nb, cnt), dim3(NT), 0, stream, n, pat->n_nodes, nb,
+                           pat->nvals, pat->colblk, vals, dinv, (const double *)x, y, ppart, pst, lam);
+      else
+        hipLaunchKernelGGL(k_power<3>, dim3(nb, cnt), dim3(NT), 0, stream, n, pat->n_nodes, nb,
+                           pat->nvals, pat->colblk, vals, dinv, (const double *)x, y, ppart, pst, lam);
+      double *t = x; x = y; y = t;
+    }
+    hipLaunchKernelGGL(k_smoother_guard, dim3(ceil_div(cnt, 64)), dim3(64), 0, stream, cnt,
+                       pr.omega, (const double *)lam, status);
+  }
+  POD2G_HIP_CHECK(hipGetLastError());
+  return POD2G_OK;
+}
+
+extern "C" {
+
 int pod2g_setup(const pod2g_pattern *pat, const double *vals, const float *vals32,
                 const double *dinv, const double *P, int k, double omega, int nu_pre, int nu_post,
                 int precision, int batch, int power_iters, void *work, size_t bytes,
@@ -275,7 +337,7 @@ int pod2g_setup(const pod2g_pattern *pat, const double *vals, const float *vals3
   if (!(omega > 0.0) || nu_pre < 0 || nu_post < 0 || nu_pre > 64 || nu_post > 64 || power_iters < 0)
     return POD2G_EINVAL;
   if (bytes < pod2g_setup_bytes(pat, k, batch, precision)) return POD2G_ESIZE;
-  const int n = pat->n, dim = pat->mesh.dim;
+  const int n = pat->n;
   SetupLayout S = setup_layout(n, k, batch, precision);
   char *w = (char *)work;
   pod2g_prec pr;
@@ -293,55 +355,26 @@ int pod2g_setup(const pod2g_pattern *pat, const double *vals, const float *vals3
   pr.P = P;
   pr.status = (int *)(w + S.status);
   pr.lam = (double *)(w + S.lam);
-  InstState *pst = (InstState *)(w + S.pst);
   pr.KP = k > 0 ? (double *)(w + S.kp) : nullptr;
   pr.L = k > 0 ? (double *)(w + S.L) : nullptr;
   pr.Linv = k > 0 ? (double *)(w + S.Linv) : nullptr;
-  double *kcpart = (double *)(w + S.kcpart);
-  double *ppart = (double *)(w + S.ppart);
   pr.P32 = (precision == POD2G_MIXED && k > 0) ? (float *)(w + S.p32) : nullptr;
   pr.dinv32 = precision == POD2G_MIXED ? (float *)(w + S.d32) : nullptr;
-  double *pw0 = (double *)(w + S.pw);
-  double *pw1 = (double *)(w + S.pw + align256(sizeof(double) * (size_t)batch * n));
-
-  hipLaunchKernelGGL(k_setup_init, dim3(ceil_div(batch, 64)), dim3(64), 0, stream, pst, pr.status,
-                     pr.lam, batch, n);
-  const int nb = ceil_div(n, NT);
-  if (k > 0) {
-    dim3 gk(nb, batch, ceil_div(k, KP_CH));
-    if (dim == 2)
-      hipLaunchKernelGGL(k_kp<2>, gk, dim3(NT), 0, stream, n, pat->n_nodes, k, pat->nvals,
-                         pat->colblk, vals, P, pr.KP);
-    else
-      hipLaunchKernelGGL(k_kp<3>, gk, dim3(NT), 0, stream, n, pat->n_nodes, k, pat->nvals,
-                         pat->colblk, vals, P, pr.KP);
-    hipLaunchKernelGGL(k_kc, dim3(S.nbk, batch), dim3(NT), 0, stream, n, k, S.rows_per_wg, S.nbk,
-                       P, (const double *)pr.KP, kcpart, pr.L, pr.Linv, pr.status, pst);
-    if (precision == POD2G_MIXED)
-      hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(NT), 0, stream, (size_t)k * n, P, pr.P32);
-  }
-  if (precision == POD2G_MIXED)
-    hipLaunchKernelGGL(k_to_f32, dim3(2048), dim3(NT), 0, stream, (size_t)batch * n, dinv, pr.dinv32);
-  if (power_iters > 0) {
-    hipLaunchKernelGGL(k_fill, dim3(1024), dim3(NT), 0, stream, (size_t)batch * n, 1.0, pw0);
-    double *x = pw0, *y = pw1;
-    for (int it = 0; it < power_iters; ++it) {
-      if (dim == 2)
-        hipLaunchKernelGGL(k_power<2>, dim3(nb, batch), dim3(NT), 0, stream, n, pat->n_nodes, nb,
-                           pat->nvals, pat->colblk, vals, dinv, (const double *)x, y, ppart, pst,
-                           pr.lam);
-      else
-        hipLaunchKernelGGL(k_power<3>, dim3(nb, batch), dim3(NT), 0, stream, n, pat->n_nodes, nb,
-                           pat->nvals, pat->colblk, vals, dinv, (const double *)x, y, ppart, pst,
-                           pr.lam);
-      double *t = x; x = y; y = t;
-    }
-    hipLaunchKernelGGL(k_smoother_guard, dim3(ceil_div(batch, 64)), dim3(64), 0, stream, batch,
-                       omega, (const double *)pr.lam, pr.status);
-  }
-  POD2G_HIP_CHECK(hipGetLastError());
+  pr.work = work;
+  int st = setup_run(pr, S, w, 0, batch, power_iters, true, stream);
+  if (st) return st;
   *out = pr;
   return POD2G_OK;
+}
+
+int pod2g_setup_slot(const pod2g_prec *prec, int slot, int power_iters, hipStream_t stream) {
+  if (!prec || !prec->work || !prec->status || slot < 0 || slot >= prec->batch || power_iters < 0)
+    return POD2G_EINVAL;
+  if (prec->k < 0 || prec->k > MAXK || (prec->k > 0 && (!prec->P || !prec->KP)) ||
+      (prec->precision == POD2G_MIXED && !prec->dinv32))
+    return POD2G_EINVAL;
+  SetupLayout S = setup_layout(prec->pat.n, prec->k, prec->batch, prec->precision);
+  return setup_run(*prec, S, (char *)prec->work, slot, 1, power_iters, false, stream);
 }
 
 int pod2g_setup_status(const pod2g_prec *prec, int *status_h, double *lam_h, hipStream_t stream) {

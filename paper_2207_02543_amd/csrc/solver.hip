@@ -39,6 +39,7 @@ struct Ctx {
   double *bpart;                 // [bgrid][k][batch] partials of the batched restriction
   float *rbuf;                   // [batch][n] FP32 residuals r' of the batched restriction
   int bgrid;                     // workgroups of the batched restriction
+  pod2g_slot_info *info;         // [batch] outcome of served solves
 };
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -358,7 +359,7 @@ __global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c, const double *__restrict_
   __shared__ int flag;
   const int b = inst_id();
   InstState *st = c.st + b;
-  if (st->done) return;
+  if (st->done || st->pending) return;
   const double beta = st->beta;
   if (blockIdx.x == 0 && threadIdx.x == 0) st->scale = cycle_scale(c, st->rr);
   const int blk = xcd_block(blockIdx.x, c.nb);
@@ -409,7 +410,7 @@ __global__ void __launch_bounds__(NT) k_pdir(Ctx c, const double *__restrict__ s
                                              double *__restrict__ pnew) {
   const int b = inst_id();
   const InstState *st = c.st + b;
-  if (st->done) return;
+  if (st->done || st->pending) return;
   const int row = blockIdx.x * NT + threadIdx.x;
   if (row >= c.n) return;
   const size_t off = (size_t)b * c.n;
@@ -420,7 +421,10 @@ __global__ void __launch_bounds__(NT) k_pdir(Ctx c, const double *__restrict__ s
 // beta); with a preconditioner also the next cycle's input and, for
 // mode 1, its first pre-relaxation sweep.  Last block: convergence,
 // iteration limit, non-finite checks; without a preconditioner (mode 0)
-// s = r, so rho and beta are formed here.
+// s = r, so rho and beta are formed here.  A pending instance (served
+// solve whose true residual f - K u sits in q) takes r = q instead, leaves
+// u and the iteration count alone, and restarts from there: this is the
+// first step of a newly admitted solve and of a residual replacement.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode, const double *__restrict__ p) {
   const int have_prec = mode != 0;
@@ -429,15 +433,21 @@ __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode, const double *__
   const int b = inst_id();
   InstState *st = c.st + b;
   if (st->done) return;
+  const bool pend = st->pending != 0;
   const int blk = blockIdx.x;
   const int row = blk * NT + threadIdx.x;
   const size_t off = (size_t)b * c.n;
   const double alpha = st->alpha;
-  const bool pr = have_prec && st->beta_kind == POD2G_BETA_PR;
+  const bool pr = have_prec && st->beta_kind == POD2G_BETA_PR && !pend;
   double rr = 0.0, rs = 0.0;
   if (row < c.n) {
-    c.u[off + row] += alpha * p[off + row];
-    const double rv = c.r[off + row] - alpha * c.q[off + row];
+    double rv;
+    if (pend) {
+      rv = c.q[off + row];
+    } else {
+      c.u[off + row] += alpha * p[off + row];
+      rv = c.r[off + row] - alpha * c.q[off + row];
+    }
     c.r[off + row] = rv;
     rr = rv * rv;
     if (pr) rs = rv * c.s[off + row];
@@ -453,14 +463,15 @@ __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode, const double *__
   const double trr = reduce_partials(slot(c, b, 0), c.nb, 1, lds);
   const double trs = pr ? reduce_partials(slot(c, b, 1), c.nb, 1, lds) : 0.0;
   if (threadIdx.x == 0) {
-    st->iter += 1;
+    if (pend) st->pending = 0;
+    else st->iter += 1;
     st->rr = trr;
     st->rs_prev = trs;
     if (!finite(trr)) { st->done = 1; st->status = POD2G_ENAN; }
     else if (trr <= st->tol2) { st->done = 1; st->status = POD2G_OK; }
     else if (st->iter >= st->maxit) { st->done = 1; st->status = POD2G_EMAXIT; }
     if (!have_prec) {
-      st->beta = trr / st->rho;
+      st->beta = pend ? 0.0 : trr / st->rho;
       st->rho = trr;
     }
   }
@@ -653,30 +664,82 @@ __global__ void __launch_bounds__(NT) k_prolong_b(Ctx c, const float *__restrict
   }
 }
 
-// q = f - K u with ||q||^2 for every instance (done or not).
+// Outcome of a served solve whose true residual rr_true = ||f - K u||^2 was
+// just formed (thread 0 of the last block).  A newly admitted instance
+// learns ||f|| and either stops at x0 or starts; a stopped one either
+// finishes (result published in info) or, if the recursive residual met the
+// tolerance but the true one does not, restarts from the true residual, as
+// the exit check of the one-shot solve does.
+__device__ void serve_decide(const Ctx &c, InstState *st, int b, double t, double tf, bool fresh) {
+  bool restart;
+  if (fresh) {
+    st->fresh = 0;
+    st->ff = tf;
+    st->tol2 *= tf;   // held rtol^2 since admission
+    if (!finite(t) || !finite(tf)) { st->status = POD2G_ENAN; restart = false; }
+    else { st->status = POD2G_OK; restart = t > st->tol2; }
+  } else {
+    if (!finite(t)) st->status = POD2G_ENAN;
+    restart = st->status == POD2G_OK && st->iter < st->maxit && t > st->tol2 && st->iter > 0;
+    if (!restart && st->status == POD2G_OK && t > st->tol2) st->status = POD2G_EMAXIT;
+  }
+  if (restart) {
+    st->pending = 1;
+    st->done = 0;
+    st->restart = 1;
+    st->beta = 0.0;
+    st->rr = t;
+    st->scale = cycle_scale(c, t);
+    return;
+  }
+  st->done = 1;
+  st->checked = 1;
+  pod2g_slot_info in;
+  in.done = 1;
+  in.iter = st->iter;
+  in.status = st->status;
+  in.pad = 0;
+  in.relres = st->ff > 0.0 ? sqrt(t / st->ff) : 0.0;
+  c.info[b] = in;
+}
+
+// q = f - K u with ||q||^2.  gate == 0: every instance, done or not (exit
+// check of the one-shot solve).  gate == 1 (served solves): only instances
+// that stopped and are not checked yet, which includes the newly admitted
+// ones (they also reduce ||f||^2); the last block decides their outcome.
 template <int DIM>
-__global__ void __launch_bounds__(NT) k_true_resid(Ctx c) {
+__global__ void __launch_bounds__(NT) k_true_resid(Ctx c, int gate) {
   __shared__ double lds[2 * NWAVE];
   __shared__ int flag;
   const int b = inst_id();
   InstState *st = c.st + b;
+  if (gate && !(st->done && !st->checked)) return;
+  const bool fresh = gate && st->fresh;
   const int blk = xcd_block(blockIdx.x, c.nb);
   const int row = blk * NT + threadIdx.x;
   const size_t off = (size_t)b * c.n;
-  double rr = 0.0;
+  double rr = 0.0, ff = 0.0;
   if (row < c.n) {
     const double kx = row_dot<DIM>(c.colblk, c.vals + (size_t)b * c.vstride, c.u + off, row,
                                    row / DIM, c.n, c.nn);
-    const double rv = c.f[row] - kx;
+    const double fv = c.f[row];
+    const double rv = fv - kx;
     c.q[off + row] = rv;
     rr = rv * rv;
+    ff = fv * fv;
   }
-  double dummy = 0.0;
-  block_sum2(rr, dummy, lds);
-  if (threadIdx.x == 0) put_partial(slot(c, b, 0) + blk, rr);
+  block_sum2(rr, ff, lds);
+  if (threadIdx.x == 0) {
+    put_partial(slot(c, b, 0) + blk, rr);
+    if (fresh) put_partial(slot(c, b, 1) + blk, ff);
+  }
   if (!arrive_last(&st->cnt[CNT_A], c.nb, &flag)) return;
   const double t = reduce_partials(slot(c, b, 0), c.nb, 1, lds);
-  if (threadIdx.x == 0) st->rr_true = t;
+  const double tf = fresh ? reduce_partials(slot(c, b, 1), c.nb, 1, lds) : 0.0;
+  if (threadIdx.x == 0) {
+    st->rr_true = t;
+    if (gate) serve_decide(c, st, b, t, tf, fresh);
+  }
 }
 
 // Residual replacement for the instances flagged by the host: r = q,
@@ -696,6 +759,50 @@ __global__ void __launch_bounds__(NT) k_replace(Ctx c, const int *__restrict__ f
     st->beta = 0.0;
     if (!have_prec) st->rho = st->rr_true;
   }
+}
+
+// Served solves: a free slot is stopped and checked, so no kernel touches
+// it; an admitted one is stopped, unchecked and fresh, so the next gated
+// true-residual pass forms r0 = f - K x0 and ||f|| and starts it.
+__global__ void k_serve_free(InstState *st, pod2g_slot_info *info, int batch) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= batch) return;
+  InstState s;
+  memset(&s, 0, sizeof(s));
+  s.done = 1;
+  s.checked = 1;
+  s.scale = 1.0;
+  st[b] = s;
+  pod2g_slot_info in;
+  memset(&in, 0, sizeof(in));
+  in.done = 1;
+  info[b] = in;
+}
+
+__global__ void k_serve_admit(InstState *st, pod2g_slot_info *info, int b, double rtol, int maxit,
+                              int beta_kind, const int *setup_status) {
+  if (threadIdx.x != 0) return;
+  InstState s;
+  memset(&s, 0, sizeof(s));
+  s.maxit = maxit;
+  s.beta_kind = beta_kind;
+  s.restart = 1;
+  s.scale = 1.0;
+  s.tol2 = rtol * rtol;
+  s.done = 1;
+  pod2g_slot_info in;
+  memset(&in, 0, sizeof(in));
+  const int ss = setup_status ? setup_status[b] : 0;
+  if (ss != 0) {
+    s.checked = 1;
+    s.status = ss;
+    in.done = 1;
+    in.status = ss;
+  } else {
+    s.fresh = 1;
+  }
+  st[b] = s;
+  info[b] = in;
 }
 
 // ---------------------------------------------------------------------------
@@ -738,7 +845,7 @@ static void accumulate(pod2g_timer *t, int used) {
 }
 
 struct Layout {
-  size_t st, ec, part, bpart, vec, vec32, flags, total;
+  size_t st, ec, part, bpart, vec, vec32, flags, info, total;
   int bgrid;
 };
 
@@ -760,6 +867,7 @@ static Layout layout(int n, int batch, int k, int precision) {
   if (precision == POD2G_MIXED && batch >= BATCH_MFMA_MIN && batch <= MAXB && k > 0)
     o += align256(sizeof(double) * (size_t)(L.bgrid + 1) * k * batch);
   L.flags = o; o += align256(sizeof(int) * (size_t)batch);
+  L.info = o;  o += align256(sizeof(pod2g_slot_info) * (size_t)batch);
   L.vec = o;   o += 7 * align256(sizeof(double) * (size_t)n * batch);   // r p0 p1 q s xa xb
   L.vec32 = o;
   if (precision == POD2G_MIXED) o += 2 * align256(sizeof(float) * (size_t)n * batch);  // b32, rbuf
@@ -791,6 +899,7 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
   c.part = (double *)(w + Lo.part);
   c.bpart = (double *)(w + Lo.bpart);
   c.bgrid = Lo.bgrid;
+  c.info = (pod2g_slot_info *)(w + Lo.info);
   const size_t vb = align256(sizeof(double) * (size_t)n * batch);
   c.r = (double *)(w + Lo.vec);
   c.p0 = (double *)(w + Lo.vec + vb);
@@ -964,6 +1073,19 @@ struct pod2g_plan {
   pod2g_timer *timer;
 };
 
+// Slot groups advanced together by one captured graph per step.
+struct pod2g_server {
+  struct Group {
+    pod2g::Ctx c;
+    pod2g_prec prec;
+    int dim;
+  };
+  std::vector<Group> groups;
+  int chunk, slots;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
 namespace pod2g {
 
 template <int DIM>
@@ -1017,7 +1139,7 @@ static int pcg_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int bet
     if (!plan && chunk < 16) chunk *= 2;
     if (!all_done) continue;
     // exit check on the true residual
-    hipLaunchKernelGGL(k_true_resid<DIM>, grid, blk, 0, stream, c);
+    hipLaunchKernelGGL(k_true_resid<DIM>, grid, blk, 0, stream, c, 0);
     POD2G_HIP_CHECK(hipGetLastError());
     st = read_states(c, h, stream);
     if (st) return st;
@@ -1205,6 +1327,101 @@ int pcg_plan_destroy(pod2g_plan *pl) {
   if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
   if (pl->graph) (void)hipGraphDestroy(pl->graph);
   delete pl;
+  return POD2G_OK;
+}
+
+static void serve_group_step(const pod2g_server::Group &g, int chunk, hipStream_t cs) {
+  dim3 grid(g.c.nb, g.c.batch), blk(NT);
+  if (g.dim == 2) {
+    hipLaunchKernelGGL(k_true_resid<2>, grid, blk, 0, cs, g.c, 1);
+    for (int i = 0; i < chunk; ++i) launch_iteration<2>(g.c, &g.prec, cs, nullptr, i & 1);
+    hipLaunchKernelGGL(k_true_resid<2>, grid, blk, 0, cs, g.c, 1);
+  } else {
+    hipLaunchKernelGGL(k_true_resid<3>, grid, blk, 0, cs, g.c, 1);
+    for (int i = 0; i < chunk; ++i) launch_iteration<3>(g.c, &g.prec, cs, nullptr, i & 1);
+    hipLaunchKernelGGL(k_true_resid<3>, grid, blk, 0, cs, g.c, 1);
+  }
+}
+
+int pod2g_server_create(const pod2g_group *groups, int n_groups, int chunk, pod2g_server **out,
+                        hipStream_t stream) {
+  if (!out || !groups || n_groups < 1 || n_groups > 64 || chunk < 2 || chunk > 256)
+    return POD2G_EINVAL;
+  chunk += chunk & 1;
+  pod2g_server *sv = new pod2g_server;
+  sv->chunk = chunk;
+  sv->slots = 0;
+  sv->graph = nullptr;
+  sv->exec = nullptr;
+  for (int g = 0; g < n_groups; ++g) {
+    const pod2g_group &G = groups[g];
+    if (!G.prec) { delete sv; return POD2G_EINVAL; }
+    const int batch = G.prec->batch;
+    int st = check_solve_args(G.pat, G.vals, batch, G.prec, G.f, G.u, POD2G_BETA_FR, G.work, G.bytes);
+    if (st) { delete sv; return st; }
+    pod2g_server::Group gr;
+    gr.prec = *G.prec;
+    gr.dim = G.pat->mesh.dim;
+    fill_ctx(gr.c, G.pat, G.vals, batch, G.prec, G.f, G.u, G.work);
+    sv->groups.push_back(gr);
+    sv->slots += batch;
+  }
+  for (auto &g : sv->groups)
+    hipLaunchKernelGGL(k_serve_free, dim3(ceil_div(g.c.batch, 64)), dim3(64), 0, stream, g.c.st,
+                       g.c.info, g.c.batch);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) {
+    delete sv;
+    return POD2G_EHIP;
+  }
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { delete sv; return POD2G_EHIP; }
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    for (const auto &g : sv->groups) serve_group_step(g, chunk, cs);
+    ok = hipStreamEndCapture(cs, &sv->graph) == hipSuccess;
+  }
+  if (ok && hipGraphInstantiate(&sv->exec, sv->graph, nullptr, nullptr, 0) != hipSuccess) ok = false;
+  (void)hipStreamDestroy(cs);
+  if (!ok) {
+    if (sv->graph) (void)hipGraphDestroy(sv->graph);
+    delete sv;
+    return POD2G_EHIP;
+  }
+  *out = sv;
+  return POD2G_OK;
+}
+
+int pod2g_server_admit(pod2g_server *sv, int group, int slot, double rtol, int maxit, int beta,
+                       hipStream_t stream) {
+  if (!sv || group < 0 || group >= (int)sv->groups.size()) return POD2G_EINVAL;
+  const pod2g_server::Group &g = sv->groups[group];
+  if (slot < 0 || slot >= g.c.batch || !(rtol >= 0.0) || maxit < 0) return POD2G_EINVAL;
+  if (beta != POD2G_BETA_FR && beta != POD2G_BETA_PR) return POD2G_EINVAL;
+  hipLaunchKernelGGL(k_serve_admit, dim3(1), dim3(64), 0, stream, g.c.st, g.c.info, slot, rtol,
+                     maxit, beta, (const int *)g.prec.status);
+  POD2G_HIP_CHECK(hipGetLastError());
+  return POD2G_OK;
+}
+
+int pod2g_serve_step(pod2g_server *sv, pod2g_slot_info *info_h, hipStream_t stream) {
+  if (!sv || !info_h) return POD2G_EINVAL;
+  POD2G_HIP_CHECK(hipGraphLaunch(sv->exec, stream));
+  size_t off = 0;
+  for (const auto &g : sv->groups) {
+    POD2G_HIP_CHECK(hipMemcpyAsync(info_h + off, g.c.info, sizeof(pod2g_slot_info) * g.c.batch,
+                                   hipMemcpyDeviceToHost, stream));
+    off += g.c.batch;
+  }
+  return POD2G_OK;
+}
+
+int pod2g_server_slots(const pod2g_server *sv) { return sv ? sv->slots : POD2G_EINVAL; }
+
+int pod2g_server_destroy(pod2g_server *sv) {
+  if (!sv) return POD2G_EINVAL;
+  if (sv->exec) (void)hipGraphExecDestroy(sv->exec);
+  if (sv->graph) (void)hipGraphDestroy(sv->graph);
+  delete sv;
   return POD2G_OK;
 }
 

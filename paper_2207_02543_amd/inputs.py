@@ -21,6 +21,7 @@ import numpy as np
 TRAIN_SEED0 = 1000   # training parameter i uses seed TRAIN_SEED0 + i
 QUERY_SEED0 = 2000   # query parameter j uses seed QUERY_SEED0 + j
 NOISE_SEED0 = 3000   # warm-start noise of query j uses seed NOISE_SEED0 + j
+ARRIVAL_SEED = 4000  # request stream of the serving workload
 
 
 @dataclass(frozen=True)
@@ -118,3 +119,24 @@ def warm_start(u_exact, g, rel: float = 0.01):
     nu = float((u_exact * u_exact).sum()) ** 0.5
     ng = float((g * g).sum()) ** 0.5
     return u_exact + (rel * nu / ng) * g
+
+
+def arrivals(rate: float, duration: float, n_classes: int, pool: int, seed: int = ARRIVAL_SEED):
+    """A Poisson request stream: arrival times (s, from 0) with exponential
+    gaps of mean 1/rate up to `duration`, a uniformly drawn class per
+    request and, per class, query indices cycling through a pool of `pool`
+    pre-generated queries.  Returns (times, classes, query indices)."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    times = []
+    t = g.exponential(1.0 / rate)
+    while t < duration:
+        times.append(t)
+        t += g.exponential(1.0 / rate)
+    times = np.asarray(times)
+    cls = g.integers(0, n_classes, size=len(times))
+    qidx = np.zeros(len(times), dtype=np.int64)
+    seen = np.zeros(n_classes, dtype=np.int64)
+    for i, c in enumerate(cls):
+        qidx[i] = seen[c] % pool
+        seen[c] += 1
+    return times, cls, qidx
