@@ -80,12 +80,70 @@ def cpu_baseline(w, xis, x0s, P, seconds):
                       f"PCG, oracle iterations {iters}) in {t_total:.1f} s on 1 host thread"}
 
 
+def serve_bench(args):
+    """Serving workload: Poisson arrivals over three problem classes, each
+    with its own basis; continuous batching through the library server."""
+    import numpy as np
+    import torch
+    from paper_2207_02543_amd import capi as L, inputs as I, pipeline, serve
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    names = ["c4a", "c4b", "c4c"]
+    ws = [I.with_(I.WORKLOADS[nm], precision="mixed") for nm in names]
+    free, total = torch.cuda.mem_get_info()
+    slots = serve.plan_slots([(w, w.k, "mixed") for w in ws], int(free * args.hbm_fraction),
+                             max_slots=args.max_slots)
+    log(f"[serve] free HBM {free / 2**30:.1f} GiB of {total / 2**30:.1f}; slots per class {slots}")
+    classes, pools = [], []
+    for w, m in zip(ws, slots):
+        prob = pipeline.Problem(w, dev)
+        t0 = time.perf_counter()
+        P, lam, U, its = pipeline.offline_basis(prob)
+        del U, prob
+        c = serve.ServedClass(w, P, m, precision="mixed")
+        pools.append(serve.make_pool(c, args.queries))
+        classes.append(c)
+        torch.cuda.synchronize()
+        log(f"[serve] class {w.name}: n {w.n}, k {w.k}, {m} slots, offline + pool "
+            f"{time.perf_counter() - t0:.1f} s")
+    srv = serve.Server(classes, chunk=args.chunk if args.chunk > 0 else 8)
+    # warm-up: every class, every slot once, queued at t = 0
+    nw = sum(slots)
+    wc = np.array([i for i, m in enumerate(slots) for _ in range(m)])
+    serve.run_stream(srv, pools, np.zeros(nw), wc, np.arange(nw) % args.queries, rtol=1e-8,
+                     realtime=False)
+    times, cls, qidx = I.arrivals(args.rate, args.serve_seconds, len(ws), args.queries)
+    log(f"[serve] {len(times)} requests over {args.serve_seconds:.0f} s at {args.rate:.0f}/s")
+    res = serve.run_stream(srv, pools, times, cls, qidx, rtol=1e-8, check_first=4)
+    s = serve.summarize(res, names)
+    srv.close()
+    log(f"[serve] {s['completed']} solves in {s['wall_s']:.1f} s; p50 {s['p50_ms']:.1f} ms, "
+        f"p99 {s['p99_ms']:.1f} ms; {s['steps']} steps")
+    result = {
+        "metric": METRIC, "value": s["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
+        "steps": s["steps"], "warmup": nw, "ms_per_step": s["wall_s"] / max(1, s["steps"]) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+        "data": "synthetic",
+        "config": {"workload": "c4 serving: Poisson arrivals over c4a (2D 128x128), c4b (2D "
+                               "256x256), c4c (3D 48x48x48), k=20 each, tol 1e-8",
+                   "rate_per_s": args.rate, "duration_s": args.serve_seconds,
+                   "slots": dict(zip(names, slots)), "graph_chunk": srv.chunk,
+                   "queries_per_class": args.queries},
+        "serving": s,
+        "roofline": None,
+    }
+    print(json.dumps(result), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2", help="c1, c2, c3, c4a, c4b, c4c, c5")
+    ap.add_argument("--workload", default="c2",
+                    help="c1, c2, c3, c4a, c4b, c4c, c5; c4 = the serving stream")
     ap.add_argument("--queries", type=int, default=8, help="distinct query parameters cycled")
     ap.add_argument("--kernel", default="sweep", choices=sorted(KERNELS),
                     help="kernel timed live for the roofline entry")
@@ -96,12 +154,20 @@ def main(argv=None):
     ap.add_argument("--markers", action="store_true",
                     help="launch the k_mark_begin / k_mark_end kernels around the timed steps "
                          "(for cutting a rocprofv3 trace to them)")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
+    ap.add_argument("--serve-seconds", type=float, default=60.0, help="serving: arrival window")
+    ap.add_argument("--hbm-fraction", type=float, default=0.5,
+                    help="serving: share of the free HBM given to resident queries")
+    ap.add_argument("--max-slots", type=int, default=32, help="serving: slots per class at most")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver "
               "shards over independent queries with no collectives; run one process per GPU.",
               file=sys.stderr)
         return 2
+
+    if args.workload == "c4":
+        return serve_bench(args)
 
     import numpy as np
     import torch
