@@ -159,6 +159,33 @@ __device__ __forceinline__ T row_dot(const int *__restrict__ colblk, const T *__
   return acc;
 }
 
+// (K x) for the DIM rows of one node (row = node DIM + r): per neighbour
+// slot one index load, one DIM-wide gather xg(c DIM + b) and DIM DIM-wide
+// value loads (the node's rows are adjacent in every (slot, component)
+// plane).  Each row sums in the order of row_dot, so the results agree
+// with it bit for bit.
+template <int DIM, typename T, typename XG>
+__device__ __forceinline__ void node_dot(const int *__restrict__ colblk, const T *__restrict__ vals,
+                                         XG xg, int node, int n, int nn, T acc[DIM]) {
+  constexpr int S = Stencil<DIM>::S;
+#pragma unroll
+  for (int r = 0; r < DIM; ++r) acc[r] = T(0);
+  const T *vn = vals + (size_t)node * DIM;
+#pragma unroll 9
+  for (int s = 0; s < S; ++s) {
+    const int c = colblk[s * nn + node];
+    T xv[DIM];
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) xv[b] = (T)xg((size_t)c * DIM + b);
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) {
+      const T *v = vn + (size_t)(s * DIM + b) * n;
+#pragma unroll
+      for (int r = 0; r < DIM; ++r) acc[r] += v[r] * xv[b];
+    }
+  }
+}
+
 inline int ceil_div(long long a, int b) { return (int)((a + b - 1) / b); }
 
 }  // namespace pod2g

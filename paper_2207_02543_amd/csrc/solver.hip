@@ -19,6 +19,8 @@ namespace pod2g {
 
 struct Ctx {
   int n, nn, k, batch, nb, ps;   // ps: partial stride per workgroup (doubles)
+  int nbn;                       // workgroups of the node-wise kernels (one thread per node)
+  int igroup;                    // instances per group in the node-wise block order (divides batch)
   int mixed;                     // FP32 cycle: its input is scaled by a power of two
   long long vstride;
   const int *colblk;
@@ -47,6 +49,26 @@ constexpr int MAXB = 32;             // instances of one batched contraction
 constexpr int BATCH_MFMA_MIN = 4;    // batched MFMA products from this batch size
 
 __device__ __forceinline__ int inst_id() { return blockIdx.y; }
+
+// Workgroup -> (node block, instance) of the node-wise kernels, whose grid
+// is (nbn, batch).  Workgroups reach the 8 XCDs round-robin in linear
+// order; each XCD gets one contiguous run of work items, and the items are
+// ordered by instance group (igroup instances), then node block, then the
+// instances of the group, so that a node block's shared column indices are
+// fetched once per group and the group's gathered vectors share one L2.
+struct NodeBlk {
+  int blk, b;
+};
+__device__ __forceinline__ NodeBlk node_block(const Ctx &c) {
+  const int lin = blockIdx.y * gridDim.x + blockIdx.x;
+  const int w = xcd_block(lin, c.nbn * c.batch);
+  const int per = c.nbn * c.igroup;
+  const int grp = w / per, rem = w - grp * per;
+  NodeBlk r;
+  r.blk = rem / c.igroup;
+  r.b = grp * c.igroup + rem % c.igroup;
+  return r;
+}
 
 // Partial sums: slot j of instance b holds one value per workgroup,
 // contiguous over workgroups.
@@ -147,40 +169,48 @@ __device__ __forceinline__ const T *cycle_rhs(const Ctx &c, size_t off) {
   return sizeof(T) == 8 ? (const T *)(c.r + off) : (const T *)c.b32 + off;
 }
 
-// x_out = x_in + omega D^-1 (b - K x_in).  With FINAL the result is the
-// preconditioned residual s = x_out / scale (FP64) and the block also
-// reduces r^T s; the last block forms rho and beta.
+// x_out = x_in + omega D^-1 (b - K x_in), one thread per node (its DIM
+// rows).  With FINAL the result is the preconditioned residual
+// s = x_out / scale (FP64) and the block also reduces r^T s; the last block
+// forms rho and beta.
 template <int DIM, typename T, bool FINAL>
 __global__ void __launch_bounds__(NT) k_sweep(Ctx c, const T *__restrict__ xin, T *__restrict__ xout,
                                               int want_dot) {
   __shared__ double lds[2 * NWAVE];
   __shared__ int flag;
-  const int b = inst_id();
+  const NodeBlk nbk = node_block(c);
+  const int b = nbk.b, blk = nbk.blk;
   InstState *st = c.st ? c.st + b : nullptr;   // null: standalone sweeps
   if (st && st->done) return;
-  const int blk = xcd_block(blockIdx.x, c.nb);
-  const int row = blk * NT + threadIdx.x;
+  const int node = blk * NT + threadIdx.x;
   const size_t off = (size_t)b * c.n;
   double rs = 0.0;
-  if (row < c.n) {
+  if (node < c.nn) {
     const T *vals = (const T *)c.svals + (size_t)b * c.vstride;
-    const T kx = row_dot<DIM>(c.colblk, vals, xin + off, row, row / DIM, c.n, c.nn);
-    const T bv = cycle_rhs<T>(c, off)[row];
-    const T xv = xin[off + row] + (T)c.omega * ((const T *)c.sdinv)[off + row] * (bv - kx);
-    if (FINAL) {
-      const double sv = (double)xv / st->scale;
-      c.s[off + row] = sv;
-      rs = c.r[off + row] * sv;
-    } else {
-      xout[off + row] = xv;
+    const T *xb = xin + off;
+    T kx[DIM];
+    node_dot<DIM>(c.colblk, vals, [xb](size_t i) { return xb[i]; }, node, c.n, c.nn, kx);
+    const size_t r0 = off + (size_t)node * DIM;
+    const T *rhs = cycle_rhs<T>(c, off) + (size_t)node * DIM;
+    const T *dv = (const T *)c.sdinv + r0;
+#pragma unroll
+    for (int r = 0; r < DIM; ++r) {
+      const T xv = xin[r0 + r] + (T)c.omega * dv[r] * (rhs[r] - kx[r]);
+      if (FINAL) {
+        const double sv = (double)xv / st->scale;
+        c.s[r0 + r] = sv;
+        rs += c.r[r0 + r] * sv;
+      } else {
+        xout[r0 + r] = xv;
+      }
     }
   }
   if (!FINAL || !want_dot) return;
   double dummy = 0.0;
   block_sum2(rs, dummy, lds);
   if (threadIdx.x == 0) put_partial(slot(c, b, 0) + blk, rs);
-  if (!arrive_last(&st->cnt[CNT_B], c.nb, &flag)) return;
-  const double trs = reduce_partials(slot(c, b, 0), c.nb, 1, lds);
+  if (!arrive_last(&st->cnt[CNT_B], c.nbn, &flag)) return;
+  const double trs = reduce_partials(slot(c, b, 0), c.nbn, 1, lds);
   if (threadIdx.x == 0) {
     double beta = 0.0;
     if (!st->restart) {
@@ -286,14 +316,19 @@ __global__ void __launch_bounds__(NT) k_restrict(Ctx c, const T *__restrict__ x)
 // instance, no reduction).
 template <int DIM>
 __global__ void __launch_bounds__(NT) k_resid32(Ctx c, const float *__restrict__ x) {
-  const int b = inst_id();
+  const NodeBlk nbk = node_block(c);
+  const int b = nbk.b;
   if (c.st[b].done) return;
-  const int row = xcd_block(blockIdx.x, c.nb) * NT + threadIdx.x;
-  if (row >= c.n) return;
+  const int node = nbk.blk * NT + threadIdx.x;
+  if (node >= c.nn) return;
   const size_t off = (size_t)b * c.n;
   const float *vals = (const float *)c.svals + (size_t)b * c.vstride;
-  c.rbuf[off + row] = ((const float *)c.b32)[off + row] -
-                      row_dot<DIM>(c.colblk, vals, x + off, row, row / DIM, c.n, c.nn);
+  const float *xb = x + off;
+  float kx[DIM];
+  node_dot<DIM>(c.colblk, vals, [xb](size_t i) { return xb[i]; }, node, c.n, c.nn, kx);
+  const size_t r0 = off + (size_t)node * DIM;
+#pragma unroll
+  for (int r = 0; r < DIM; ++r) c.rbuf[r0 + r] = ((const float *)c.b32)[r0 + r] - kx[r];
 }
 
 // Prolongation and correction: x_out = x_in + P e_c.
@@ -347,56 +382,56 @@ __global__ void __launch_bounds__(NT) k_finalize(Ctx c, const T *__restrict__ x,
   }
 }
 
-// q = K p and p^T q; the last block forms alpha = rho / p^T q.  With FUSED
-// the direction p = s + beta p_old is formed here (gathered where K needs
-// it, the owned rows written to pnew); otherwise k_pdir formed it already.
-// Workgroup 0 sets the input scale of the next cycle from the current ||r||.
+// q = K p and p^T q, one thread per node; the last block forms
+// alpha = rho / p^T q.  With FUSED the direction p = s + beta p_old is
+// formed here (gathered where K needs it, the owned rows written to pnew);
+// otherwise k_pdir formed it already.  Workgroup 0 sets the input scale of
+// the next cycle from the current ||r||.
 template <int DIM, bool FUSED>
 __global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c, const double *__restrict__ s,
                                                 const double *__restrict__ pold,
                                                 double *__restrict__ pnew) {
   __shared__ double lds[2 * NWAVE];
   __shared__ int flag;
-  const int b = inst_id();
+  const NodeBlk nbk = node_block(c);
+  const int b = nbk.b, blk = nbk.blk;
   InstState *st = c.st + b;
   if (st->done || st->pending) return;
   const double beta = st->beta;
-  if (blockIdx.x == 0 && threadIdx.x == 0) st->scale = cycle_scale(c, st->rr);
-  const int blk = xcd_block(blockIdx.x, c.nb);
-  const int row = blk * NT + threadIdx.x;
+  if (blk == 0 && threadIdx.x == 0) st->scale = cycle_scale(c, st->rr);
+  const int node = blk * NT + threadIdx.x;
   const size_t off = (size_t)b * c.n;
   double pq = 0.0;
-  if (row < c.n) {
+  if (node < c.nn) {
     const double *vals = c.vals + (size_t)b * c.vstride;
-    double kp, pv;
+    const double *sb = s + off, *pb = pold + off;
+    double *pn = pnew + off;
+    const size_t r0 = (size_t)node * DIM;
+    double kp[DIM], pv[DIM];
     if (FUSED) {
-      constexpr int S = Stencil<DIM>::S;
-      const double *sb = s + off, *pb = pold + off;
-      const int node = row / DIM;
-      kp = 0.0;
-#pragma unroll 9
-      for (int sl = 0; sl < S; ++sl) {
-        const int col = c.colblk[sl * c.nn + node];
+      node_dot<DIM>(c.colblk, vals, [sb, pb, beta](size_t i) { return pdir(sb[i], pb, i, beta); },
+                    node, c.n, c.nn, kp);
 #pragma unroll
-        for (int bc = 0; bc < DIM; ++bc) {
-          const size_t i = (size_t)col * DIM + bc;
-          kp += vals[(size_t)(sl * DIM + bc) * c.n + row] * pdir(sb[i], pb, i, beta);
-        }
+      for (int r = 0; r < DIM; ++r) {
+        pv[r] = pdir(sb[r0 + r], pb, r0 + r, beta);
+        pn[r0 + r] = pv[r];
       }
-      pv = pdir(sb[row], pb, row, beta);
-      pnew[off + row] = pv;
     } else {
-      kp = row_dot<DIM>(c.colblk, vals, pnew + off, row, row / DIM, c.n, c.nn);
-      pv = pnew[off + row];
+      node_dot<DIM>(c.colblk, vals, [pn](size_t i) { return pn[i]; }, node, c.n, c.nn, kp);
+#pragma unroll
+      for (int r = 0; r < DIM; ++r) pv[r] = pn[r0 + r];
     }
-    c.q[off + row] = kp;
-    pq = pv * kp;
+#pragma unroll
+    for (int r = 0; r < DIM; ++r) {
+      c.q[off + r0 + r] = kp[r];
+      pq += pv[r] * kp[r];
+    }
   }
   double dummy = 0.0;
   block_sum2(pq, dummy, lds);
   if (threadIdx.x == 0) put_partial(slot(c, b, 0) + blk, pq);
-  if (!arrive_last(&st->cnt[CNT_D], c.nb, &flag)) return;
-  const double g = reduce_partials(slot(c, b, 0), c.nb, 1, lds);
+  if (!arrive_last(&st->cnt[CNT_D], c.nbn, &flag)) return;
+  const double g = reduce_partials(slot(c, b, 0), c.nbn, 1, lds);
   if (threadIdx.x == 0) {
     st->gamma = g;
     if (!(g > 0.0)) { st->done = 1; st->status = finite(g) ? POD2G_EBREAKDOWN : POD2G_ENAN; }
@@ -875,6 +910,15 @@ static Layout layout(int n, int batch, int k, int precision) {
   return L;
 }
 
+// Instances per group of the node-wise block order: the largest divisor of
+// the batch that is at most IGROUP_MAX.
+constexpr int IGROUP_MAX = 1;
+static int default_igroup(int batch) {
+  int g = IGROUP_MAX;
+  while (g > 1 && batch % g) --g;
+  return g;
+}
+
 static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int batch,
                      const pod2g_prec *prec, const double *f, double *u, void *work) {
   memset(&c, 0, sizeof(c));
@@ -888,6 +932,8 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
   c.k = k;
   c.batch = batch;
   c.nb = ceil_div(n, NT);
+  c.nbn = ceil_div(pat->n_nodes, NT);
+  c.igroup = default_igroup(batch);
   c.ps = k > 2 ? k : 2;
   c.vstride = pat->nvals;
   c.colblk = pat->colblk;
@@ -939,19 +985,19 @@ static bool batched_products(const Ctx &c) {
 template <int DIM, typename T>
 static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, int want_dot,
                          Tm *tm) {
-  dim3 grid(c.nb, c.batch), blk(NT);
+  dim3 grid(c.nb, c.batch), gridn(c.nbn, c.batch), blk(NT);
   T *xa = (T *)c.xa, *xb = (T *)c.xb;
   T *cur = xa, *oth = xb;
   const bool have_x = pr->nu_pre >= 1;
   for (int i = 1; i < pr->nu_pre; ++i) {
-    launch(tm, POD2G_TK_SWEEP, k_sweep<DIM, T, false>, grid, blk, 0, stream, c, (const T *)cur, oth, 0);
+    launch(tm, POD2G_TK_SWEEP, k_sweep<DIM, T, false>, gridn, blk, 0, stream, c, (const T *)cur, oth, 0);
     T *t = cur; cur = oth; oth = t;
   }
   bool have = have_x;
   if (c.k > 0 && batched_products<T>(c)) {
     // shared basis, many instances: one MFMA contraction over the batch
     if (have) {
-      launch(tm, POD2G_TK_RESTRICT, k_resid32<DIM>, grid, blk, 0, stream, c, (const float *)cur);
+      launch(tm, POD2G_TK_RESTRICT, k_resid32<DIM>, gridn, blk, 0, stream, c, (const float *)cur);
       hipLaunchKernelGGL(k_ptr_b, dim3(c.bgrid), blk, sizeof(float) * c.k * PW_LD, stream, c,
                          (const float *)c.rbuf);
     } else {
@@ -983,9 +1029,9 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
     for (int i = 1; i < pr->nu_post; ++i) {
       const bool fin = (i == pr->nu_post - 1);
       if (fin)
-        hipLaunchKernelGGL((k_sweep<DIM, T, true>), grid, blk, 0, stream, c, cur, oth, want_dot);
+        hipLaunchKernelGGL((k_sweep<DIM, T, true>), gridn, blk, 0, stream, c, cur, oth, want_dot);
       else
-        hipLaunchKernelGGL((k_sweep<DIM, T, false>), grid, blk, 0, stream, c, cur, oth, 0);
+        hipLaunchKernelGGL((k_sweep<DIM, T, false>), gridn, blk, 0, stream, c, cur, oth, 0);
       T *t = cur; cur = oth; oth = t;
     }
     if (pr->nu_post == 1) hipLaunchKernelGGL((k_finalize<T>), grid, blk, 0, stream, c, cur, want_dot);
@@ -994,10 +1040,10 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
   for (int i = 0; i < pr->nu_post; ++i) {
     const bool fin = (i == pr->nu_post - 1);
     if (fin)
-      launch(tm, POD2G_TK_SWEEP_FINAL, k_sweep<DIM, T, true>, grid, blk, 0, stream, c, (const T *)cur, oth,
+      launch(tm, POD2G_TK_SWEEP_FINAL, k_sweep<DIM, T, true>, gridn, blk, 0, stream, c, (const T *)cur, oth,
              want_dot);
     else
-      launch(tm, POD2G_TK_SWEEP, k_sweep<DIM, T, false>, grid, blk, 0, stream, c, (const T *)cur, oth, 0);
+      launch(tm, POD2G_TK_SWEEP, k_sweep<DIM, T, false>, gridn, blk, 0, stream, c, (const T *)cur, oth, 0);
     T *t = cur; cur = oth; oth = t;
   }
   if (pr->nu_post == 0)
@@ -1026,7 +1072,7 @@ constexpr long long FUSE_DIR_MAX = 1ll << 20;   // rows x instances
 template <int DIM>
 static void launch_iteration(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, Tm *tm,
                              int parity) {
-  dim3 grid(c.nb, c.batch), blk(NT);
+  dim3 grid(c.nb, c.batch), gridn(c.nbn, c.batch), blk(NT);
   const double *pold = parity ? c.p1 : c.p0;
   double *pnew = parity ? c.p0 : c.p1;
   const double *sdir = pr ? (const double *)c.s : (const double *)c.r;
@@ -1034,10 +1080,10 @@ static void launch_iteration(const Ctx &c, const pod2g_prec *pr, hipStream_t str
   // SpMV; large ones are bandwidth-bound: a second gathered vector costs
   // more than one elementwise pass
   if ((long long)c.n * c.batch <= FUSE_DIR_MAX) {
-    launch(tm, POD2G_TK_SPMV_PQ, k_spmv_pq<DIM, true>, grid, blk, 0, stream, c, sdir, pold, pnew);
+    launch(tm, POD2G_TK_SPMV_PQ, k_spmv_pq<DIM, true>, gridn, blk, 0, stream, c, sdir, pold, pnew);
   } else {
     hipLaunchKernelGGL(k_pdir, grid, blk, 0, stream, c, sdir, pold, pnew);
-    launch(tm, POD2G_TK_SPMV_PQ, k_spmv_pq<DIM, false>, grid, blk, 0, stream, c, sdir, pold, pnew);
+    launch(tm, POD2G_TK_SPMV_PQ, k_spmv_pq<DIM, false>, gridn, blk, 0, stream, c, sdir, pold, pnew);
   }
   if (pr) {
     const int mode = pr->nu_pre >= 1 ? 1 : 2;
@@ -1525,13 +1571,15 @@ int pod2g_jacobi(const pod2g_pattern *pat, const double *vals, const double *din
   c.nn = pat->n_nodes;
   c.batch = batch;
   c.nb = ceil_div(pat->n, NT);
+  c.nbn = ceil_div(pat->n_nodes, NT);
+  c.igroup = default_igroup(batch);
   c.vstride = pat->nvals;
   c.colblk = pat->colblk;
   c.svals = vals;
   c.sdinv = dinv;
   c.omega = omega;
   c.r = const_cast<double *>(b);   // the sweep's right-hand side
-  dim3 grid(c.nb, batch);
+  dim3 grid(c.nbn, batch);
   double *cur = x, *oth = tmp;
   for (int i = 0; i < nsweeps; ++i) {
     if (pat->mesh.dim == 2)
