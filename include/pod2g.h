@@ -110,6 +110,9 @@ typedef struct pod2g_prec {
   float *P32;           /* [k][n] (MIXED), in the setup workspace */
   float *dinv32;        /* [batch][n] (MIXED), in the setup workspace */
   double *KP;           /* [batch][k][n] K P, in the setup workspace */
+  float *KP32;          /* [batch][k][n] FP32 K P (MIXED, 3D), in the setup workspace:
+                           the cycle's first post-relaxation residual is
+                           r' - (K P) e_c instead of a product with K */
   double *L;            /* [batch][k][k] row-major lower Cholesky factor of P^T K P */
   double *Linv;         /* [batch][k][k] row-major inverse of L (lower triangular):
                            the cycle's coarse solve is e_c = Linv^T (Linv r_c) */

@@ -43,7 +43,7 @@ class Prec(C.Structure):
                 ("nu_post", C.c_int), ("precision", C.c_int), ("omega", C.c_double),
                 ("vals", C.c_void_p), ("vals32", C.c_void_p), ("dinv", C.c_void_p),
                 ("P", C.c_void_p), ("P32", C.c_void_p), ("dinv32", C.c_void_p),
-                ("KP", C.c_void_p), ("L", C.c_void_p), ("Linv", C.c_void_p), ("lam", C.c_void_p),
+                ("KP", C.c_void_p), ("KP32", C.c_void_p), ("L", C.c_void_p), ("Linv", C.c_void_p), ("lam", C.c_void_p),
                 ("status", C.c_void_p), ("work", C.c_void_p)]
 
 

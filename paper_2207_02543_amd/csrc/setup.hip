@@ -13,13 +13,19 @@ constexpr int KP_CH = 8;   // columns of K P per pass over K
 constexpr int KC_TR = 64;  // rows per LDS tile of the coarse-matrix kernel
 
 struct SetupLayout {
-  size_t status, lam, pst, kp, L, Linv, kcpart, ppart, p32, d32, pw, total;
+  size_t status, lam, pst, kp, L, Linv, kcpart, ppart, p32, d32, kp32, pw, total;
   int nbk, rows_per_wg;
 };
 
 static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-static SetupLayout setup_layout(int n, int k, int batch, int precision) {
+// The FP32 copy of K P pays where a row of K P (k values) is shorter than a
+// row of K (27 blocks of 3 in 3D); in 2D (9 blocks of 2) it would not.
+static bool want_kp32(int dim, int k, int precision) {
+  return precision == POD2G_MIXED && dim == 3 && k > 0;
+}
+
+static SetupLayout setup_layout(int n, int k, int batch, int precision, int dim) {
   SetupLayout S;
   int rpt = n / (NT * 1024);
   if (rpt < 1) rpt = 1;
@@ -37,6 +43,7 @@ static SetupLayout setup_layout(int n, int k, int batch, int precision) {
   S.ppart = o;  o += align256(sizeof(double) * (size_t)batch * ceil_div(n, NT));
   S.p32 = o;    if (precision == POD2G_MIXED) o += align256(sizeof(float) * (size_t)k * n);
   S.d32 = o;    if (precision == POD2G_MIXED) o += align256(sizeof(float) * (size_t)batch * n);
+  S.kp32 = o;   if (want_kp32(dim, k, precision)) o += align256(sizeof(float) * (size_t)batch * k * n);
   S.pw = o;     o += 2 * align256(sizeof(double) * (size_t)batch * n);
   S.total = o;
   return S;
@@ -261,7 +268,7 @@ extern "C" {
 
 size_t pod2g_setup_bytes(const pod2g_pattern *pat, int k, int batch, int precision) {
   if (!pat || k < 0 || k > MAXK || batch < 1) return 0;
-  return setup_layout(pat->n, k, batch, precision).total;
+  return setup_layout(pat->n, k, batch, precision, pat->mesh.dim).total;
 }
 
 }  // extern "C"
@@ -301,6 +308,9 @@ static int setup_run(const pod2g_prec &pr, const SetupLayout &S, char *w, int b0
                        pr.P, (const double *)KP, kcpart, L, Linv, status, pst);
     if (convert_p && pr.precision == POD2G_MIXED)
       hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(NT), 0, stream, (size_t)k * n, pr.P, pr.P32);
+    if (pr.KP32)
+      hipLaunchKernelGGL(k_to_f32, dim3(2048), dim3(NT), 0, stream, (size_t)cnt * k * n,
+                         (const double *)KP, pr.KP32 + (size_t)b0 * k * n);
   }
   if (pr.precision == POD2G_MIXED)
     hipLaunchKernelGGL(k_to_f32, dim3(2048), dim3(NT), 0, stream, (size_t)cnt * n, dinv,
@@ -338,7 +348,7 @@ int pod2g_setup(const pod2g_pattern *pat, const double *vals, const float *vals3
     return POD2G_EINVAL;
   if (bytes < pod2g_setup_bytes(pat, k, batch, precision)) return POD2G_ESIZE;
   const int n = pat->n;
-  SetupLayout S = setup_layout(n, k, batch, precision);
+  SetupLayout S = setup_layout(n, k, batch, precision, pat->mesh.dim);
   char *w = (char *)work;
   pod2g_prec pr;
   memset(&pr, 0, sizeof(pr));
@@ -360,6 +370,7 @@ int pod2g_setup(const pod2g_pattern *pat, const double *vals, const float *vals3
   pr.Linv = k > 0 ? (double *)(w + S.Linv) : nullptr;
   pr.P32 = (precision == POD2G_MIXED && k > 0) ? (float *)(w + S.p32) : nullptr;
   pr.dinv32 = precision == POD2G_MIXED ? (float *)(w + S.d32) : nullptr;
+  pr.KP32 = want_kp32(pat->mesh.dim, k, precision) ? (float *)(w + S.kp32) : nullptr;
   pr.work = work;
   int st = setup_run(pr, S, w, 0, batch, power_iters, true, stream);
   if (st) return st;
@@ -373,7 +384,8 @@ int pod2g_setup_slot(const pod2g_prec *prec, int slot, int power_iters, hipStrea
   if (prec->k < 0 || prec->k > MAXK || (prec->k > 0 && (!prec->P || !prec->KP)) ||
       (prec->precision == POD2G_MIXED && !prec->dinv32))
     return POD2G_EINVAL;
-  SetupLayout S = setup_layout(prec->pat.n, prec->k, prec->batch, prec->precision);
+  SetupLayout S = setup_layout(prec->pat.n, prec->k, prec->batch, prec->precision,
+                                 prec->pat.mesh.dim);
   return setup_run(*prec, S, (char *)prec->work, slot, 1, power_iters, false, stream);
 }
 

@@ -29,6 +29,7 @@ struct Ctx {
   const void *sdinv;             // smoother D^-1
   const void *sP;                // cycle P (FP64 or FP32)
   const double *Linv;            // [batch][k][k] inverse Cholesky factor
+  const float *KP32;             // [batch][k][n] FP32 K P (batched FP32 cycle, 3D) or null
   double omega;
   const double *f;               // [n]
   double *u, *r, *q, *s;         // [batch][n] FP64
@@ -641,8 +642,13 @@ __global__ void __launch_bounds__(NT) k_ptr_sum(Ctx c) {
 // Prolongation and correction for all instances of a 256-row block:
 // X_out[b][row] = X_in[b][row] + sum_j P[j][row] E[j][b] with the k x B
 // product on MFMA (FP32), staged through LDS so the writes are coalesced.
+// With rp (the restricted residual r', [batch][n]) the kernel also applies
+// the first post-relaxation sweep: since b - K (x + P e_c) = r' - (K P) e_c,
+// x_out = x + P e_c + omega D^-1 (r' - (K P) e_c) reads the instance's K P
+// (k values per row) instead of its K and the gathered x.
 __global__ void __launch_bounds__(NT) k_prolong_b(Ctx c, const float *__restrict__ xin,
-                                                  float *__restrict__ xout) {
+                                                  float *__restrict__ xout,
+                                                  const float *__restrict__ rp) {
   __shared__ float E[MAXK][MAXB];           // 8 KB
   __shared__ float Out[MAXB][NT];           // 32 KB
   __shared__ int live[MAXB];
@@ -695,7 +701,14 @@ __global__ void __launch_bounds__(NT) k_prolong_b(Ctx c, const float *__restrict
   for (int b = 0; b < B; ++b) {
     if (!live[b]) continue;
     const size_t off = (size_t)b * n;
-    xout[off + row] = (xin ? xin[off + row] : 0.f) + Out[b][threadIdx.x];
+    float xv = (xin ? xin[off + row] : 0.f) + Out[b][threadIdx.x];
+    if (rp) {
+      const float *kp = c.KP32 + (size_t)b * k * n + row;
+      float d = rp[off + row];
+      for (int j = 0; j < k; ++j) d -= kp[(size_t)j * n] * E[j][b];
+      xv += (float)c.omega * ((const float *)c.sdinv)[off + row] * d;
+    }
+    xout[off + row] = xv;
   }
 }
 
@@ -962,6 +975,7 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
   if (prec) {
     c.omega = prec->omega;
     c.Linv = prec->Linv;
+    c.KP32 = prec->KP32;
     if (precision == POD2G_MIXED) {
       c.svals = prec->vals32;
       c.sdinv = prec->dinv32;
@@ -989,6 +1003,7 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
   T *xa = (T *)c.xa, *xb = (T *)c.xb;
   T *cur = xa, *oth = xb;
   const bool have_x = pr->nu_pre >= 1;
+  int post_done = 0;   // post-relaxation sweeps already applied
   for (int i = 1; i < pr->nu_pre; ++i) {
     launch(tm, POD2G_TK_SWEEP, k_sweep<DIM, T, false>, gridn, blk, 0, stream, c, (const T *)cur, oth, 0);
     T *t = cur; cur = oth; oth = t;
@@ -1007,10 +1022,14 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
     }
     hipLaunchKernelGGL(k_ptr_sum, dim3(ceil_div((long long)c.k * c.batch * PTR_TPO, NT)), blk, 0,
                        stream, c);
+    // with K P at hand, the first post-sweep comes from the restricted residual
+    const float *rp = nullptr;
+    if (c.KP32 && pr->nu_post >= 1) rp = have ? (const float *)c.rbuf : (const float *)c.b32;
     launch(tm, POD2G_TK_PROLONG, k_prolong_b, dim3(c.nb), blk, 0, stream, c,
-           have ? (const float *)cur : (const float *)nullptr, (float *)oth);
+           have ? (const float *)cur : (const float *)nullptr, (float *)oth, rp);
     T *t = cur; cur = oth; oth = t;
     have = true;
+    if (rp) post_done = 1;
   } else if (c.k > 0) {
     if (have)
       launch(tm, POD2G_TK_RESTRICT, k_restrict<DIM, T, false>, grid, blk, 0, stream, c, (const T *)cur);
@@ -1037,7 +1056,7 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
     if (pr->nu_post == 1) hipLaunchKernelGGL((k_finalize<T>), grid, blk, 0, stream, c, cur, want_dot);
     return;
   }
-  for (int i = 0; i < pr->nu_post; ++i) {
+  for (int i = post_done; i < pr->nu_post; ++i) {
     const bool fin = (i == pr->nu_post - 1);
     if (fin)
       launch(tm, POD2G_TK_SWEEP_FINAL, k_sweep<DIM, T, true>, gridn, blk, 0, stream, c, (const T *)cur, oth,
@@ -1046,7 +1065,7 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
       launch(tm, POD2G_TK_SWEEP, k_sweep<DIM, T, false>, gridn, blk, 0, stream, c, (const T *)cur, oth, 0);
     T *t = cur; cur = oth; oth = t;
   }
-  if (pr->nu_post == 0)
+  if (pr->nu_post == post_done)
     hipLaunchKernelGGL((k_finalize<T>), grid, blk, 0, stream, c, have ? (const T *)cur : (const T *)nullptr, want_dot);
 }
 

@@ -38,6 +38,9 @@ def test_batched_mixed_cycle(dim, N, k, batch):
     for b in range(batch):
         K = oprob.stiffness(w, xis[b])
         ref = twogrid.TwoGrid(K, P, w.omega, precision="fp32")(r[b])
+        ref64 = twogrid.TwoGrid(K, P, w.omega, precision="fp64")(r[b])
+        flush(f"  {b}: vs fp32 cycle {relerr(s[b], ref):.2e}, vs fp64 cycle {relerr(s[b], ref64):.2e}, "
+              f"fp32 vs fp64 {relerr(ref, ref64):.2e}")
         assert relerr(s[b], ref) < 5e-6, b
 
 
