@@ -171,7 +171,7 @@ def main(argv=None):
 
     import numpy as np
     import torch
-    from paper_2207_02543_amd import capi as L, inputs as I, pipeline
+    from paper_2207_02543_amd import capi as L, inputs as I, pipeline, profiling
 
     w = I.WORKLOADS[args.workload]
     mixed = w.precision == "mixed"
@@ -276,7 +276,9 @@ def main(argv=None):
                    "relres_max": float(np.max(stats["relres"])),
                    "err_vs_fp64_max": float(np.max(stats["err"]))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS if achieved else None,
+                     "traffic": profiling.traffic_lookup(os.path.join(ROOT, "profiles"), w.name,
+                                                         args.kernel),
                      "kernel": args.kernel, "bytes_per_launch": nbytes,
                      "avg_launch_us": avg_s * 1e6, "launches_timed": cnt},
     }

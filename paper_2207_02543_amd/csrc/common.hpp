@@ -31,12 +31,38 @@ struct alignas(128) InstState {
   int beta_kind;
   int checked;     // served solve: the true residual of the final iterate is known
   int pending;     // served solve: r is replaced by the true residual in the next update
-  unsigned cnt[8]; // last-workgroup counters, one per reduction site
   int fresh;       // served solve: admitted, r0 = f - K x0 not formed yet
   int pad1;
 };
 
-enum CounterSlot { CNT_A = 0, CNT_B = 1, CNT_C = 2, CNT_D = 3, CNT_E = 4, CNT_F = 5 };
+// Reduction sites of one instance; each has its own arrival counters.
+enum CounterSlot { CNT_A = 0, CNT_B = 1, CNT_C = 2, CNT_D = 3, CNT_E = 4, CNT_F = 5, NSITE = 8 };
+
+// Arrival counters of one reduction site: a workgroup counts on the counter
+// of its group (block index mod ARR_GROUPS), the last of each group on the
+// top counter.  Atomics on one address serialise (about 12 ns each), so a
+// single counter for hundreds of workgroups puts microseconds on the
+// critical path of every reduction; two levels of at most ~32 arrivals
+// keep that chain short.  Each counter has its own 128-byte line.
+constexpr int ARR_GROUPS = 32;
+struct alignas(128) ArrCounter {
+  unsigned v;
+  unsigned pad[31];
+};
+struct Arrival {
+  ArrCounter top;
+  ArrCounter grp[ARR_GROUPS];
+};
+
+// Zero the counters of `count` sites (one thread per site and counter).
+__device__ __forceinline__ void zero_arrivals(Arrival *a, int count, int tid, int nthreads) {
+  for (int i = tid; i < count * (ARR_GROUPS + 1); i += nthreads) {
+    Arrival *s = a + i / (ARR_GROUPS + 1);
+    const int j = i % (ARR_GROUPS + 1);
+    if (j == 0) s->top.v = 0u;
+    else s->grp[j - 1].v = 0u;
+  }
+}
 
 // Blocks are handed to the 8 XCDs round-robin; map them so that every XCD
 // works on one contiguous range of rows (its L2 then holds that range's
@@ -93,17 +119,26 @@ __device__ __forceinline__ void put_partial(double *p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Report whether this workgroup is the last of `total` to arrive at
-// `counter`.  Every wave first waits for its outstanding stores (so its
-// put_partial writes are complete before the counter moves); the last
-// workgroup resets the counter, acquires, and may then read every partial.
-__device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned total, int *lds_flag) {
+// Report whether this workgroup (block index blk of `total`) is the last to
+// arrive at the site.  Every wave first waits for its outstanding stores
+// (so its put_partial writes are complete before the counters move); the
+// last workgroup of a group resets the group counter, the last of all the
+// top counter; it then acquires and may read every partial.
+__device__ __forceinline__ bool arrive_last(Arrival *a, int blk, unsigned total, int *lds_flag) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int last = (prev == total - 1u);
-    if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned g = (unsigned)blk % ARR_GROUPS;
+    const unsigned members = total / ARR_GROUPS + (g < total % ARR_GROUPS ? 1u : 0u);
+    int last = 0;
+    const unsigned prev = __hip_atomic_fetch_add(&a->grp[g].v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == members - 1u) {
+      __hip_atomic_store(&a->grp[g].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned groups = total < (unsigned)ARR_GROUPS ? total : (unsigned)ARR_GROUPS;
+      const unsigned p2 = __hip_atomic_fetch_add(&a->top.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      last = (p2 == groups - 1u);
+      if (last) __hip_atomic_store(&a->top.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     *lds_flag = last;
   }
   __syncthreads();

@@ -13,7 +13,7 @@ constexpr int KP_CH = 8;   // columns of K P per pass over K
 constexpr int KC_TR = 64;  // rows per LDS tile of the coarse-matrix kernel
 
 struct SetupLayout {
-  size_t status, lam, pst, kp, L, Linv, kcpart, ppart, p32, d32, kp32, pw, total;
+  size_t status, lam, pst, arr, kp, L, Linv, kcpart, ppart, p32, d32, kp32, pw, total;
   int nbk, rows_per_wg;
 };
 
@@ -36,6 +36,7 @@ static SetupLayout setup_layout(int n, int k, int batch, int precision, int dim)
   S.status = o; o += align256(sizeof(int) * batch);
   S.lam = o;    o += align256(sizeof(double) * batch);
   S.pst = o;    o += align256(sizeof(InstState) * batch);
+  S.arr = o;    o += sizeof(Arrival) * 2 * (size_t)batch;   // sites: coarse matrix, power step
   S.kp = o;     o += align256(sizeof(double) * (size_t)batch * k * n);
   S.L = o;      o += align256(sizeof(double) * (size_t)batch * k * k);
   S.Linv = o;   o += align256(sizeof(double) * (size_t)batch * k * k);
@@ -49,9 +50,11 @@ static SetupLayout setup_layout(int n, int k, int batch, int precision, int dim)
   return S;
 }
 
-__global__ void k_setup_init(InstState *pst, int *status, double *lam, int batch, int n) {
+__global__ void k_setup_init(InstState *pst, Arrival *arr, int *status, double *lam, int batch,
+                             int n) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
+  zero_arrivals(arr + (size_t)b * 2, 2, 0, 1);
   InstState s;
   memset(&s, 0, sizeof(s));
   s.xnorm2 = (double)n;
@@ -60,37 +63,49 @@ __global__ void k_setup_init(InstState *pst, int *status, double *lam, int batch
   lam[b] = 0.0;
 }
 
-// KP[:, j0 .. j0 + KP_CH) = K P[:, j0 ..] for one instance per grid row.
+// KP[:, j0 .. j0 + KP_CH) = K P[:, j0 ..] for one instance per grid row,
+// one thread per node (its DIM rows): per neighbour slot and component the
+// node's DIM values of K meet KP_CH gathered basis entries.
 template <int DIM>
 __global__ void __launch_bounds__(NT) k_kp(int n, int nn, int k, long long vstride,
                                            const int *__restrict__ colblk,
                                            const double *__restrict__ vals,
                                            const double *__restrict__ P, double *__restrict__ KP) {
   const int b = blockIdx.y;
-  const int row = xcd_block(blockIdx.x, gridDim.x) * NT + threadIdx.x;
+  const int node = xcd_block(blockIdx.x, gridDim.x) * NT + threadIdx.x;
   const int j0 = blockIdx.z * KP_CH;
-  if (row >= n) return;
-  const int node = row / DIM;
-  const double *v = vals + (size_t)b * vstride;
-  double acc[KP_CH];
+  if (node >= nn) return;
+  const double *v = vals + (size_t)b * vstride + (size_t)node * DIM;
+  double acc[DIM][KP_CH];
 #pragma unroll
-  for (int jj = 0; jj < KP_CH; ++jj) acc[jj] = 0.0;
+  for (int r = 0; r < DIM; ++r)
+#pragma unroll
+    for (int jj = 0; jj < KP_CH; ++jj) acc[r][jj] = 0.0;
   const int jn = k - j0 < KP_CH ? k - j0 : KP_CH;
   for (int s = 0; s < Stencil<DIM>::S; ++s) {
     const int c = colblk[s * nn + node];
 #pragma unroll
     for (int bc = 0; bc < DIM; ++bc) {
-      const double a = v[(size_t)(s * DIM + bc) * n + row];
-      const int col = c * DIM + bc;
+      double a[DIM];
 #pragma unroll
-      for (int jj = 0; jj < KP_CH; ++jj)
-        if (jj < jn) acc[jj] += a * P[(size_t)(j0 + jj) * n + col];
+      for (int r = 0; r < DIM; ++r) a[r] = v[(size_t)(s * DIM + bc) * n + r];
+      const double *pc = P + (size_t)j0 * n + (size_t)c * DIM + bc;
+#pragma unroll
+      for (int jj = 0; jj < KP_CH; ++jj) {
+        if (jj < jn) {
+          const double pv = pc[(size_t)jj * n];
+#pragma unroll
+          for (int r = 0; r < DIM; ++r) acc[r][jj] += a[r] * pv;
+        }
+      }
     }
   }
-  double *out = KP + (size_t)b * k * n;
+  double *out = KP + (size_t)b * k * n + (size_t)node * DIM;
 #pragma unroll
   for (int jj = 0; jj < KP_CH; ++jj)
-    if (jj < jn) out[(size_t)(j0 + jj) * n + row] = acc[jj];
+    if (jj < jn)
+#pragma unroll
+      for (int r = 0; r < DIM; ++r) out[(size_t)(j0 + jj) * n + r] = acc[r][jj];
 }
 
 __device__ __forceinline__ void tri_index(int e, int &j, int &l) {
@@ -109,7 +124,7 @@ __global__ void __launch_bounds__(NT) k_kc(int n, int k, int rows_per_wg, int nb
                                            const double *__restrict__ P,
                                            const double *__restrict__ KP, double *__restrict__ part,
                                            double *__restrict__ Lout, double *__restrict__ Linv,
-                                           int *__restrict__ status, InstState *pst) {
+                                           int *__restrict__ status, Arrival *arr) {
   constexpr int MAXE = (MAXK * (MAXK + 1) / 2 + NT - 1) / NT;
   __shared__ double sp[MAXK * KC_TR];
   __shared__ double skp[MAXK * KC_TR];
@@ -153,7 +168,7 @@ __global__ void __launch_bounds__(NT) k_kc(int n, int k, int rows_per_wg, int nb
     const int e = threadIdx.x + m * NT;
     if (e < ntri) put_partial(pb + (size_t)wg * ntri + e, acc[m]);
   }
-  if (!arrive_last(&pst[b].cnt[CNT_A], nbk, &flag)) return;
+  if (!arrive_last(arr + (size_t)b * 2, wg, nbk, &flag)) return;
   // K_c into LDS (full symmetric), then Cholesky
   double *A = sp;  // k x k, row-major
   for (int e = threadIdx.x; e < ntri; e += NT) {
@@ -226,7 +241,7 @@ __global__ void __launch_bounds__(NT) k_power(int n, int nn, int nb, long long v
                                               const double *__restrict__ vals,
                                               const double *__restrict__ dinv,
                                               const double *__restrict__ x, double *__restrict__ y,
-                                              double *__restrict__ part, InstState *pst,
+                                              double *__restrict__ part, InstState *pst, Arrival *arr,
                                               double *lam) {
   __shared__ double lds[NWAVE];
   __shared__ int flag;
@@ -244,7 +259,7 @@ __global__ void __launch_bounds__(NT) k_power(int n, int nn, int nb, long long v
   }
   yy = block_sum(yy, lds);
   if (threadIdx.x == 0) put_partial(part + (size_t)b * nb + blk, yy);
-  if (!arrive_last(&pst[b].cnt[CNT_B], nb, &flag)) return;
+  if (!arrive_last(arr + (size_t)b * 2 + 1, blk, nb, &flag)) return;
   double s = 0.0;
   for (int i = threadIdx.x; i < nb; i += NT) s += part[(size_t)b * nb + i];
   s = block_sum(s, lds);
@@ -286,6 +301,7 @@ static int setup_run(const pod2g_prec &pr, const SetupLayout &S, char *w, int b0
   int *status = pr.status + b0;
   double *lam = pr.lam + b0;
   InstState *pst = (InstState *)(w + S.pst) + b0;
+  Arrival *arr = (Arrival *)(w + S.arr) + (size_t)b0 * 2;
   double *KP = k > 0 ? pr.KP + (size_t)b0 * k * n : nullptr;
   double *L = k > 0 ? pr.L + (size_t)b0 * k * k : nullptr;
   double *Linv = k > 0 ? pr.Linv + (size_t)b0 * k * k : nullptr;
@@ -294,10 +310,10 @@ static int setup_run(const pod2g_prec &pr, const SetupLayout &S, char *w, int b0
   double *pw0 = (double *)(w + S.pw) + (size_t)b0 * n;
   double *pw1 = (double *)(w + S.pw + align256(sizeof(double) * (size_t)pr.batch * n)) + (size_t)b0 * n;
 
-  hipLaunchKernelGGL(k_setup_init, dim3(ceil_div(cnt, 64)), dim3(64), 0, stream, pst, status, lam,
+  hipLaunchKernelGGL(k_setup_init, dim3(ceil_div(cnt, 64)), dim3(64), 0, stream, pst, arr, status, lam,
                      cnt, n);
   if (k > 0) {
-    dim3 gk(nb, cnt, ceil_div(k, KP_CH));
+    dim3 gk(ceil_div(pat->n_nodes, NT), cnt, ceil_div(k, KP_CH));
     if (dim == 2)
       hipLaunchKernelGGL(k_kp<2>, gk, dim3(NT), 0, stream, n, pat->n_nodes, k, pat->nvals,
                          pat->colblk, vals, pr.P, KP);
@@ -305,7 +321,7 @@ static int setup_run(const pod2g_prec &pr, const SetupLayout &S, char *w, int b0
       hipLaunchKernelGGL(k_kp<3>, gk, dim3(NT), 0, stream, n, pat->n_nodes, k, pat->nvals,
                          pat->colblk, vals, pr.P, KP);
     hipLaunchKernelGGL(k_kc, dim3(S.nbk, cnt), dim3(NT), 0, stream, n, k, S.rows_per_wg, S.nbk,
-                       pr.P, (const double *)KP, kcpart, L, Linv, status, pst);
+                       pr.P, (const double *)KP, kcpart, L, Linv, status, arr);
     if (convert_p && pr.precision == POD2G_MIXED)
       hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(NT), 0, stream, (size_t)k * n, pr.P, pr.P32);
     if (pr.KP32)
@@ -321,10 +337,10 @@ static int setup_run(const pod2g_prec &pr, const SetupLayout &S, char *w, int b0
     for (int it = 0; it < power_iters; ++it) {
       if (dim == 2)
         hipLaunchKernelGGL(k_power<2>, dim3(nb, cnt), dim3(NT), 0, stream, n, pat->n_nodes, nb,
-                           pat->nvals, pat->colblk, vals, dinv, (const double *)x, y, ppart, pst, lam);
+                           pat->nvals, pat->colblk, vals, dinv, (const double *)x, y, ppart, pst, arr, lam);
       else
         hipLaunchKernelGGL(k_power<3>, dim3(nb, cnt), dim3(NT), 0, stream, n, pat->n_nodes, nb,
-                           pat->nvals, pat->colblk, vals, dinv, (const double *)x, y, ppart, pst, lam);
+                           pat->nvals, pat->colblk, vals, dinv, (const double *)x, y, ppart, pst, arr, lam);
       double *t = x; x = y; y = t;
     }
     hipLaunchKernelGGL(k_smoother_guard, dim3(ceil_div(cnt, 64)), dim3(64), 0, stream, cnt,

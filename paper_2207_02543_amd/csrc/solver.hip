@@ -43,6 +43,7 @@ struct Ctx {
   float *rbuf;                   // [batch][n] FP32 residuals r' of the batched restriction
   int bgrid;                     // workgroups of the batched restriction
   pod2g_slot_info *info;         // [batch] outcome of served solves
+  Arrival *arr;                  // [batch][NSITE] arrival counters of the reductions
 };
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -71,6 +72,10 @@ __device__ __forceinline__ NodeBlk node_block(const Ctx &c) {
   return r;
 }
 
+__device__ __forceinline__ Arrival *site(const Ctx &c, int b, int s) {
+  return c.arr + (size_t)b * NSITE + s;
+}
+
 // Partial sums: slot j of instance b holds one value per workgroup,
 // contiguous over workgroups.
 __device__ __forceinline__ double *slot(const Ctx &c, int b, int j) {
@@ -97,10 +102,11 @@ __device__ __forceinline__ double pow2_scale(double rr) {
 }
 
 // ---------------------------------------------------------------- state ---
-__global__ void k_state_init(InstState *st, int batch, double rtol, int maxit, int beta_kind,
-                             const int *setup_status) {
+__global__ void k_state_init(InstState *st, Arrival *arr, int batch, double rtol, int maxit,
+                             int beta_kind, const int *setup_status) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
+  zero_arrivals(arr + (size_t)b * NSITE, NSITE, 0, 1);
   InstState s;
   memset(&s, 0, sizeof(s));
   s.maxit = maxit;
@@ -136,7 +142,7 @@ __global__ void __launch_bounds__(NT) k_init(Ctx c, int have_prec) {
   }
   block_sum2(rr, ff, lds);
   if (threadIdx.x == 0) { put_partial(slot(c, b, 0) + blk, rr); put_partial(slot(c, b, 1) + blk, ff); }
-  if (!arrive_last(&st->cnt[CNT_A], c.nb, &flag)) return;
+  if (!arrive_last(site(c, b, CNT_A), blk, c.nb, &flag)) return;
   double trr = reduce_partials(slot(c, b, 0), c.nb, 1, lds);
   double tff = reduce_partials(slot(c, b, 1), c.nb, 1, lds);
   if (threadIdx.x == 0) {
@@ -210,7 +216,7 @@ __global__ void __launch_bounds__(NT) k_sweep(Ctx c, const T *__restrict__ xin, 
   double dummy = 0.0;
   block_sum2(rs, dummy, lds);
   if (threadIdx.x == 0) put_partial(slot(c, b, 0) + blk, rs);
-  if (!arrive_last(&st->cnt[CNT_B], c.nbn, &flag)) return;
+  if (!arrive_last(site(c, b, CNT_B), blk, c.nbn, &flag)) return;
   const double trs = reduce_partials(slot(c, b, 0), c.nbn, 1, lds);
   if (threadIdx.x == 0) {
     double beta = 0.0;
@@ -280,7 +286,7 @@ __global__ void __launch_bounds__(NT) k_restrict(Ctx c, const T *__restrict__ x)
   }
   __syncthreads();
   if (threadIdx.x < c.k) put_partial(slot(c, b, threadIdx.x) + blk, rc[threadIdx.x]);
-  if (!arrive_last(&st->cnt[CNT_C], c.nb, &flag)) return;
+  if (!arrive_last(site(c, b, CNT_C), blk, c.nb, &flag)) return;
   // r_c: tpc threads per column, each summing a strided share of the
   // column's partials, then the shares in order
   const int k = c.k;
@@ -370,7 +376,7 @@ __global__ void __launch_bounds__(NT) k_finalize(Ctx c, const T *__restrict__ x,
   double dummy = 0.0;
   block_sum2(rs, dummy, lds);
   if (threadIdx.x == 0) put_partial(slot(c, b, 0) + blk, rs);
-  if (!arrive_last(&st->cnt[CNT_B], c.nb, &flag)) return;
+  if (!arrive_last(site(c, b, CNT_B), blk, c.nb, &flag)) return;
   const double trs = reduce_partials(slot(c, b, 0), c.nb, 1, lds);
   if (threadIdx.x == 0) {
     double beta = 0.0;
@@ -431,7 +437,7 @@ __global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c, const double *__restrict_
   double dummy = 0.0;
   block_sum2(pq, dummy, lds);
   if (threadIdx.x == 0) put_partial(slot(c, b, 0) + blk, pq);
-  if (!arrive_last(&st->cnt[CNT_D], c.nbn, &flag)) return;
+  if (!arrive_last(site(c, b, CNT_D), blk, c.nbn, &flag)) return;
   const double g = reduce_partials(slot(c, b, 0), c.nbn, 1, lds);
   if (threadIdx.x == 0) {
     st->gamma = g;
@@ -495,7 +501,7 @@ __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode, const double *__
   }
   block_sum2(rr, rs, lds);
   if (threadIdx.x == 0) { put_partial(slot(c, b, 0) + blk, rr); put_partial(slot(c, b, 1) + blk, rs); }
-  if (!arrive_last(&st->cnt[CNT_E], c.nb, &flag)) return;
+  if (!arrive_last(site(c, b, CNT_E), blk, c.nb, &flag)) return;
   const double trr = reduce_partials(slot(c, b, 0), c.nb, 1, lds);
   const double trs = pr ? reduce_partials(slot(c, b, 1), c.nb, 1, lds) : 0.0;
   if (threadIdx.x == 0) {
@@ -618,7 +624,7 @@ __global__ void __launch_bounds__(NT) k_ptr_sum(Ctx c) {
   for (int d = PTR_TPO / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, PTR_TPO);
   double *rc = c.bpart + (size_t)c.bgrid * k * B;   // k * B sums after the partials
   if (q == 0 && o < k * B) put_partial(rc + o, v);
-  if (!arrive_last(&c.st[0].cnt[CNT_F], gridDim.x, &flag)) return;
+  if (!arrive_last(site(c, 0, CNT_F), blockIdx.x, gridDim.x, &flag)) return;
   for (int t = threadIdx.x; t < k * B; t += NT) {
     const int b = t / k, i = t % k;
     double y = 0.0;
@@ -781,7 +787,7 @@ __global__ void __launch_bounds__(NT) k_true_resid(Ctx c, int gate) {
     put_partial(slot(c, b, 0) + blk, rr);
     if (fresh) put_partial(slot(c, b, 1) + blk, ff);
   }
-  if (!arrive_last(&st->cnt[CNT_A], c.nb, &flag)) return;
+  if (!arrive_last(site(c, b, CNT_A), blk, c.nb, &flag)) return;
   const double t = reduce_partials(slot(c, b, 0), c.nb, 1, lds);
   const double tf = fresh ? reduce_partials(slot(c, b, 1), c.nb, 1, lds) : 0.0;
   if (threadIdx.x == 0) {
@@ -812,9 +818,10 @@ __global__ void __launch_bounds__(NT) k_replace(Ctx c, const int *__restrict__ f
 // Served solves: a free slot is stopped and checked, so no kernel touches
 // it; an admitted one is stopped, unchecked and fresh, so the next gated
 // true-residual pass forms r0 = f - K x0 and ||f|| and starts it.
-__global__ void k_serve_free(InstState *st, pod2g_slot_info *info, int batch) {
+__global__ void k_serve_free(InstState *st, Arrival *arr, pod2g_slot_info *info, int batch) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
+  zero_arrivals(arr + (size_t)b * NSITE, NSITE, 0, 1);
   InstState s;
   memset(&s, 0, sizeof(s));
   s.done = 1;
@@ -827,8 +834,9 @@ __global__ void k_serve_free(InstState *st, pod2g_slot_info *info, int batch) {
   info[b] = in;
 }
 
-__global__ void k_serve_admit(InstState *st, pod2g_slot_info *info, int b, double rtol, int maxit,
-                              int beta_kind, const int *setup_status) {
+__global__ void k_serve_admit(InstState *st, Arrival *arr, pod2g_slot_info *info, int b, double rtol,
+                              int maxit, int beta_kind, const int *setup_status) {
+  zero_arrivals(arr + (size_t)b * NSITE, NSITE, threadIdx.x, blockDim.x);
   if (threadIdx.x != 0) return;
   InstState s;
   memset(&s, 0, sizeof(s));
@@ -893,7 +901,7 @@ static void accumulate(pod2g_timer *t, int used) {
 }
 
 struct Layout {
-  size_t st, ec, part, bpart, vec, vec32, flags, info, total;
+  size_t st, ec, part, bpart, vec, vec32, flags, info, arr, total;
   int bgrid;
 };
 
@@ -916,6 +924,7 @@ static Layout layout(int n, int batch, int k, int precision) {
     o += align256(sizeof(double) * (size_t)(L.bgrid + 1) * k * batch);
   L.flags = o; o += align256(sizeof(int) * (size_t)batch);
   L.info = o;  o += align256(sizeof(pod2g_slot_info) * (size_t)batch);
+  L.arr = o;   o += sizeof(Arrival) * NSITE * (size_t)batch;
   L.vec = o;   o += 7 * align256(sizeof(double) * (size_t)n * batch);   // r p0 p1 q s xa xb
   L.vec32 = o;
   if (precision == POD2G_MIXED) o += 2 * align256(sizeof(float) * (size_t)n * batch);  // b32, rbuf
@@ -959,6 +968,7 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
   c.bpart = (double *)(w + Lo.bpart);
   c.bgrid = Lo.bgrid;
   c.info = (pod2g_slot_info *)(w + Lo.info);
+  c.arr = (Arrival *)(w + Lo.arr);
   const size_t vb = align256(sizeof(double) * (size_t)n * batch);
   c.r = (double *)(w + Lo.vec);
   c.p0 = (double *)(w + Lo.vec + vb);
@@ -1158,7 +1168,7 @@ static int pcg_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int bet
                    int *iters_h, double *relres_h, int *status_h, pod2g_timer *timer,
                    pod2g_plan *plan, hipStream_t stream) {
   dim3 grid(c.nb, c.batch), blk(NT);
-  hipLaunchKernelGGL(k_state_init, dim3(ceil_div(c.batch, 64)), dim3(64), 0, stream, c.st, c.batch,
+  hipLaunchKernelGGL(k_state_init, dim3(ceil_div(c.batch, 64)), dim3(64), 0, stream, c.st, c.arr, c.batch,
                      rtol, maxit, beta, pr ? (const int *)pr->status : (const int *)nullptr);
   hipLaunchKernelGGL(k_init<DIM>, grid, blk, 0, stream, c, pr ? 1 : 0);
   // s = B r and rho; the restart flag makes beta = 0, so the next
@@ -1432,7 +1442,7 @@ int pod2g_server_create(const pod2g_group *groups, int n_groups, int chunk, pod2
     sv->slots += batch;
   }
   for (auto &g : sv->groups)
-    hipLaunchKernelGGL(k_serve_free, dim3(ceil_div(g.c.batch, 64)), dim3(64), 0, stream, g.c.st,
+    hipLaunchKernelGGL(k_serve_free, dim3(ceil_div(g.c.batch, 64)), dim3(64), 0, stream, g.c.st, g.c.arr,
                        g.c.info, g.c.batch);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(stream) != hipSuccess) {
     delete sv;
@@ -1462,7 +1472,7 @@ int pod2g_server_admit(pod2g_server *sv, int group, int slot, double rtol, int m
   const pod2g_server::Group &g = sv->groups[group];
   if (slot < 0 || slot >= g.c.batch || !(rtol >= 0.0) || maxit < 0) return POD2G_EINVAL;
   if (beta != POD2G_BETA_FR && beta != POD2G_BETA_PR) return POD2G_EINVAL;
-  hipLaunchKernelGGL(k_serve_admit, dim3(1), dim3(64), 0, stream, g.c.st, g.c.info, slot, rtol,
+  hipLaunchKernelGGL(k_serve_admit, dim3(1), dim3(64), 0, stream, g.c.st, g.c.arr, g.c.info, slot, rtol,
                      maxit, beta, (const int *)g.prec.status);
   POD2G_HIP_CHECK(hipGetLastError());
   return POD2G_OK;
@@ -1531,9 +1541,10 @@ int pod2g_timer_destroy(pod2g_timer *t) {
 }
 
 // s = B r: the same kernels as inside PCG, on a scratch state.
-__global__ void k_apply_init(InstState *st, int batch, const double *sc) {
+__global__ void k_apply_init(InstState *st, Arrival *arr, int batch, const double *sc) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= batch) return;
+  zero_arrivals(arr + (size_t)b * NSITE, NSITE, 0, 1);
   InstState s;
   memset(&s, 0, sizeof(s));
   s.scale = sc ? sc[b] : 1.0;
@@ -1551,7 +1562,7 @@ int pod2g_apply(const pod2g_prec *prec, const double *r, double *s, void *work, 
   // the cycle reads r from c.r and writes c.s; run it on the caller's arrays
   c.r = const_cast<double *>(r);
   c.s = s;
-  hipLaunchKernelGGL(k_apply_init, dim3(ceil_div(c.batch, 64)), dim3(64), 0, stream, c.st, c.batch,
+  hipLaunchKernelGGL(k_apply_init, dim3(ceil_div(c.batch, 64)), dim3(64), 0, stream, c.st, c.arr, c.batch,
                      (const double *)nullptr);
   if (prec->pat.mesh.dim == 2) {
     launch_first<2>(c, prec, stream);

@@ -9,6 +9,13 @@ same region (rocprofv3 ``--pmc`` output).
 ``python -m paper_2207_02543_amd.profiling calib`` runs, between markers,
 three plain device copies of 256 MiB (torch ``copy_``): the reference that
 scales the FETCH_SIZE / WRITE_SIZE counters to bytes.
+``python -m paper_2207_02543_amd.profiling run --workload W --kernel K
+--out DIR`` drives rocprofv3 (as child processes) over ``bench.py`` for
+that workload: one kernel trace, one FETCH_SIZE pass, one WRITE_SIZE pass
+and the two calibration passes, and prints a report with the commands, the
+trace summary, the kernel's counters, the calibration and a line
+``traffic <workload> <kernel> <bytes per launch> source <digest>`` that
+bench.py reads back while the library sources are unchanged.
 """
 from __future__ import annotations
 
@@ -70,10 +77,124 @@ def calib(mib=256, reps=3):
     print(f"copied {reps} x {mib} MiB")
 
 
+# kernel name patterns of the timed kernels (bench.py --kernel)
+KERNEL_PATTERNS = {
+    "sweep": r"k_sweep<\d, \w+, false>",
+    "sweep_final": r"k_sweep<\d, \w+, true>",
+    "spmv_pq": r"k_spmv_pq<",
+    "restrict": r"k_resid32<|k_restrict<",
+    "prolong": r"k_prolong",
+    "update": r"k_update<",
+}
+CALIB_BYTES = 256 * 2 ** 20   # one calibration copy reads and writes this much
+
+
+def source_digest():
+    """Digest of the library sources (kernels and the C ABI header)."""
+    import glob
+    import hashlib
+    import os
+    here = os.path.dirname(os.path.abspath(__file__))
+    files = sorted(glob.glob(os.path.join(here, "csrc", "*.hip")) +
+                   glob.glob(os.path.join(here, "csrc", "*.hpp")))
+    files.append(os.path.join(os.path.dirname(here), "include", "pod2g.h"))
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def per_dispatch(path, pattern, counter):
+    """Mean per-dispatch value of `counter` over the marked region's
+    dispatches whose kernel name matches `pattern`."""
+    import re
+    rows = list(csv.DictReader(open(path)))
+    ids = {r["Dispatch_Id"] for r in _region([{"Dispatch_Id": r["Dispatch_Id"],
+                                               "Kernel_Name": r["Kernel_Name"]} for r in rows])}
+    v = [float(r["Counter_Value"]) for r in rows
+         if r["Dispatch_Id"] in ids and r["Counter_Name"] == counter
+         and re.search(pattern, r["Kernel_Name"])]
+    return (sum(v) / len(v), len(v)) if v else (float("nan"), 0)
+
+
+def run(workload, kernel, out, steps, extra):
+    """Profile bench.py on one workload (see the module docstring)."""
+    import os
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    bench = [sys.executable, os.path.join(root, "bench.py"), "--workload", workload,
+             "--steps", str(steps), "--warmup", "1", "--no-cpu-baseline", "--markers",
+             "--kernel", kernel] + extra
+    calib_cmd = [sys.executable, "-m", "paper_2207_02543_amd.profiling", "calib"]
+    env = dict(os.environ, TMPDIR="/tmp", PYTHONPATH=root)
+    os.makedirs(out, exist_ok=True)
+    cmds = []
+
+    def prof(args, prog, sub, limit):
+        d = os.path.join(out, sub)
+        cmd = ["rocprofv3"] + args + ["--output-format", "csv", "-d", d, "-o", "p", "--"] + prog
+        cmds.append(" ".join(cmd))
+        print(f"[profiling] {sub}", file=sys.stderr, flush=True)
+        subprocess.run(cmd, check=True, env=env, cwd="/tmp", timeout=limit)
+        return d
+
+    pat = KERNEL_PATTERNS[kernel]
+    t = prof(["--kernel-trace"], bench, "trace", 900)
+    f = prof(["--pmc", "FETCH_SIZE", "--kernel-include-regex", f"{pat}|k_mark"], bench, "fetch", 900)
+    w = prof(["--pmc", "WRITE_SIZE", "--kernel-include-regex", f"{pat}|k_mark"], bench, "write", 900)
+    cf = prof(["--pmc", "FETCH_SIZE"], calib_cmd, "calib_fetch", 120)
+    cw = prof(["--pmc", "WRITE_SIZE"], calib_cmd, "calib_write", 120)
+    fetch, nf = per_dispatch(os.path.join(f, "p_counter_collection.csv"), pat, "FETCH_SIZE")
+    write, nw = per_dispatch(os.path.join(w, "p_counter_collection.csv"), pat, "WRITE_SIZE")
+    cfe, _ = per_dispatch(os.path.join(cf, "p_counter_collection.csv"), ".", "FETCH_SIZE")
+    cwr, _ = per_dispatch(os.path.join(cw, "p_counter_collection.csv"), ".", "WRITE_SIZE")
+    kf, kw = CALIB_BYTES / (cfe * 1024), CALIB_BYTES / (cwr * 1024)
+    traffic = fetch * 1024 * kf + write * 1024 * kw
+    lines = [f"# rocprofv3 summary: kernel {kernel} ({pat}), workload {workload}",
+             "# commands (run from /tmp with TMPDIR=/tmp, PYTHONPATH=<repo>):"]
+    lines += [f"#   {c}" for c in cmds]
+    lines += ["", "## kernel trace of the timed steps (between the markers)",
+              trace_summary(os.path.join(t, "p_kernel_trace.csv")), "",
+              "## counters of the timed steps, mean per dispatch (KiB)",
+              f"FETCH_SIZE {fetch:.1f} over {nf} dispatches",
+              f"WRITE_SIZE {write:.1f} over {nw} dispatches", "",
+              f"## calibration: {CALIB_BYTES} B copies read FETCH_SIZE {cfe:.1f} KiB and write "
+              f"WRITE_SIZE {cwr:.1f} KiB per dispatch",
+              f"bytes per FETCH_SIZE KiB {kf * 1024:.1f}; bytes per WRITE_SIZE KiB {kw * 1024:.1f}", "",
+              f"traffic {workload} {kernel} {traffic:.0f} source {source_digest()}"]
+    return "\n".join(lines)
+
+
+def traffic_lookup(profiles_dir, workload, kernel):
+    """HBM bytes per launch from a committed report, if the library sources
+    are the ones the counters were taken with; else None."""
+    import glob
+    import os
+    digest = source_digest()
+    for path in sorted(glob.glob(os.path.join(profiles_dir, "*.txt"))):
+        for line in open(path):
+            p = line.split()
+            if len(p) == 6 and p[0] == "traffic" and p[1] == workload and p[2] == kernel \
+                    and p[4] == "source" and p[5] == digest:
+                return float(p[3])
+    return None
+
+
 if __name__ == "__main__":
     kind = sys.argv[1]
     if kind == "calib":
         calib()
+    elif kind == "run":
+        import argparse
+        ap = argparse.ArgumentParser()
+        ap.add_argument("run")
+        ap.add_argument("--workload", required=True)
+        ap.add_argument("--kernel", default="sweep")
+        ap.add_argument("--out", required=True)
+        ap.add_argument("--steps", type=int, default=2)
+        a, extra = ap.parse_known_args()
+        print(run(a.workload, a.kernel, a.out, a.steps, extra))
     else:
         path = sys.argv[2]
         print(trace_summary(path) if kind == "trace" else counter_summary(path))
