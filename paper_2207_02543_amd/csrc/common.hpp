@@ -149,20 +149,22 @@ __device__ __forceinline__ bool arrive_last(Arrival *a, int blk, unsigned total,
 
 // Deterministic sum of m partials (strided by `stride` doubles) by one
 // workgroup: fixed per-thread order, then the fixed block tree.
-// Sum of part[i * stride] for i = first, first + step, ... < m with four
-// independent accumulators (loads in flight together; order fixed by m).
+// Sum of part[i * stride] for i = first, first + step, ... < m with eight
+// independent accumulators: the partials come from other XCDs (a trip to
+// the memory side each), so up to eight loads per thread are in flight
+// together.  The order is fixed by m and step.
 __device__ __forceinline__ double strided_sum(const double *part, int first, int m, int step,
                                               int stride) {
-  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   int i = first;
-  for (; i + 3 * step < m; i += 4 * step) {
-    a0 += part[(size_t)i * stride];
-    a1 += part[(size_t)(i + step) * stride];
-    a2 += part[(size_t)(i + 2 * step) * stride];
-    a3 += part[(size_t)(i + 3 * step) * stride];
+  for (; i + 7 * step < m; i += 8 * step) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += part[(size_t)(i + u * step) * stride];
   }
-  for (; i < m; i += step) a0 += part[(size_t)i * stride];
-  return (a0 + a1) + (a2 + a3);
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+    if (i + u * step < m) a[u] += part[(size_t)(i + u * step) * stride];
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
 __device__ __forceinline__ double reduce_partials(const double *part, int m, int stride,
