@@ -32,27 +32,80 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+# the kernel with the largest share of a step's time on each workload
+# (rocprofv3 kernel traces of the timed steps)
+DOMINANT = {"c1": "restrict", "c2": "restrict", "c4a": "restrict", "c4b": "restrict",
+            "c3": "spmv_pq", "c4c": "spmv_pq", "c5": "spmv_pq"}
+
+
 def kernel_bytes(w, kernel, mixed):
     """Algorithmic HBM bytes of one launch of `kernel` over the batch: each
-    stored matrix value, index and vector entry moved once."""
+    stored matrix value, index and vector entry moved once; what all
+    instances share (indices, basis) counted once."""
     S = 3 ** w.dim
-    n, nn = w.n, w.n_nodes_free
+    n, nn, k, B = w.n, w.n_nodes_free, w.k, w.batch
     nvals = n * S * w.dim
-    B = w.batch
-    vb = 4 if (mixed and kernel in ("sweep", "sweep_final", "restrict")) else 8
-    idx = 4 * S * nn                       # shared block-column indices
-    if kernel == "sweep":                  # vals, x_in, b, D^-1 read; x_out written
-        per = vb * nvals + 4 * vb * n
-    elif kernel == "sweep_final":          # + r (FP64) read, s (FP64) written
-        per = vb * nvals + 3 * vb * n + 16 * n
-    elif kernel == "spmv_pq":              # vals, p read; q written
-        per = 8 * nvals + 16 * n
-    elif kernel == "restrict":             # vals, x, b read; P (shared) read once
-        per = vb * nvals + 2 * vb * n
-        idx += vb * w.k * n
-    else:
-        raise ValueError(kernel)
-    return idx + B * per
+    batched = mixed and 4 <= B <= 32 and k > 0        # MFMA products over the batch
+    fused = n * B <= (1 << 20)                          # direction update inside the SpMV
+    vb = 4 if mixed else 8                              # cycle precision
+    idx = 4 * S * nn                                    # block-column indices
+    if kernel == "sweep":        # K, x (gathered), b, D^-1 read; x_out written
+        return idx + B * (vb * nvals + 4 * vb * n)
+    if kernel == "sweep_final":  # + r (FP64) read, s (FP64) written instead of x_out
+        return idx + B * (vb * nvals + 3 * vb * n + 16 * n)
+    if kernel == "spmv_pq":      # K, p read (fused: s, p_old read, p written); q written
+        return idx + B * (8 * nvals + (32 if fused else 16) * n)
+    if kernel == "restrict":
+        if batched:              # r' = b - K x in FP32: K, x, b read; r' written
+            return idx + B * (4 * nvals + 12 * n)
+        return idx + vb * k * n + B * (vb * nvals + 2 * vb * n)   # + P once
+    if kernel == "prolong":
+        if batched and w.dim == 3:   # x + P e + omega D^-1 (r' - K P e): P once, K P per instance
+            return 4 * k * n + B * (4 * k * n + 16 * n)
+        return vb * k * n + B * 2 * vb * n
+    if kernel == "update":       # u, p, r, q (, s) read; u, r written; cycle input and first sweep
+        return B * (48 * n + (8 * n if mixed else 0) + (12 * n if mixed else 24 * n))
+    raise ValueError(kernel)
+
+
+def plain_baseline(prob, P, xi_d, x0, ustar, count, chunk):
+    """The one-solve-at-a-time FP64 path on the same queries: assembly,
+    FP64 setup and a captured FP64 PCG per query (batch 1)."""
+    import numpy as np
+    import torch
+    from paper_2207_02543_amd import capi as L
+    w = prob.w
+    sysm = prob.alloc_system(1)
+    u = torch.empty(1, w.n, dtype=torch.float64, device=xi_d.device)
+    sysm.xi.copy_(xi_d[:1])
+    prob.assemble(sysm)
+    prec0 = prob.setup(sysm, P, key="setup_plain")
+    plan = prob.plan(sysm, prec0, u, chunk=chunk, key="pcg_plain")
+    iters, errs = [], []
+
+    def one(j):
+        sysm.xi.copy_(xi_d[j:j + 1])
+        prob.assemble(sysm)
+        prob.setup(sysm, P, key="setup_plain")
+        u.copy_(x0[j:j + 1])
+        ret, its, rr, st = plan.solve(w.tol, beta=L.BETA_FR)
+        if ret != L.OK:
+            raise L.Pod2gError(ret, f"plain solve {j}: {st}")
+        return its[0]
+
+    one(0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(count):
+        iters.append(one(j))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    for j in [count - 1]:
+        errs.append(float(torch.linalg.norm(u[0] - ustar[j]) / torch.linalg.norm(ustar[j])))
+    plan.close()
+    return {"value": count / dt, "unit": "solves/s", "solves": count,
+            "iters_mean": float(np.mean(iters)), "err_vs_fp64_last": errs[0],
+            "path": "FP64 cycle and PCG, one query per solve (batch 1), captured chunks"}
 
 
 def cpu_baseline(w, xis, x0s, P, seconds):
@@ -145,8 +198,12 @@ def main(argv=None):
     ap.add_argument("--workload", default="c2",
                     help="c1, c2, c3, c4a, c4b, c4c, c5; c4 = the serving stream")
     ap.add_argument("--queries", type=int, default=8, help="distinct query parameters cycled")
-    ap.add_argument("--kernel", default="sweep", choices=sorted(KERNELS),
-                    help="kernel timed live for the roofline entry")
+    ap.add_argument("--kernel", default=None, choices=sorted(KERNELS),
+                    help="kernel timed live for the roofline entry (default: the workload's "
+                         "dominant kernel)")
+    ap.add_argument("--compare-plain", type=int, default=None,
+                    help="batched workloads: also time this many one-at-a-time FP64 solves "
+                         "(default 4 for batched workloads, 0 to skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--chunk", type=int, default=8,
@@ -175,6 +232,8 @@ def main(argv=None):
 
     w = I.WORKLOADS[args.workload]
     mixed = w.precision == "mixed"
+    if args.kernel is None:
+        args.kernel = DOMINANT.get(w.name, "sweep")
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     log(f"[bench] workload {w.name}: dim {w.dim} N {w.N} n {w.n} k {w.k} batch {w.batch} "
@@ -282,6 +341,14 @@ def main(argv=None):
                      "kernel": args.kernel, "bytes_per_launch": nbytes,
                      "avg_launch_us": avg_s * 1e6, "launches_timed": cnt},
     }
+    ncmp = args.compare_plain if args.compare_plain is not None else (4 if w.batch > 1 else 0)
+    if ncmp > 0:
+        log(f"[bench] timing {ncmp} one-at-a-time FP64 solves of the same queries ...")
+        pl = plain_baseline(prob, P, xi_d, x0, ustar, ncmp, args.chunk if args.chunk > 0 else 8)
+        pl["speedup_batched"] = value / pl["value"]
+        result["plain_fp64"] = pl
+        log(f"[bench] plain FP64: {pl['value']:.2f} solves/s ({pl['iters_mean']:.1f} iterations); "
+            f"batched {w.precision}: x{pl['speedup_batched']:.2f}")
     if not args.no_cpu_baseline:
         log("[bench] timing the oracle on the host ...")
         x0h = x0.cpu().numpy()
