@@ -195,6 +195,29 @@ int pcg_solve(const pod2g_pattern *pat, const double *vals, int batch,
               int *iters_h, double *relres_h, int *status_h,
               void *work, size_t bytes, hipStream_t stream);
 
+/* ---- standalone two-grid solver (Sec. 3.3 scheme iterated on its own) ----
+ * u_b <- u_b + B_b (f - K_b u_b) (the cycle of pod2g_apply, error operator
+ * of Eq. 30) from the initial guesses in u until ||f - K u|| <= rtol ||f||
+ * or maxit (>= 1) cycles, as the POD-2G solver is used on its own in the
+ * Sec. 4 comparisons.  prec is required.  Workspace: pcg_solve_bytes.
+ * Synchronous; outputs as pcg_solve (relres_h is the true residual: the
+ * iteration recomputes it every cycle).  Returns OK, EMAXIT or ENAN (first
+ * failing instance), EINVAL, ESIZE, EHIP.                                   */
+int pod2g_stationary_solve(const pod2g_pattern *pat, const double *vals, int batch,
+                           const pod2g_prec *prec, const double *f, double *u,
+                           double rtol, int maxit, int *iters_h, double *relres_h,
+                           int *status_h, void *work, size_t bytes, hipStream_t stream);
+
+/* ---- reduced-order (POD-Galerkin) solution as a warm start -----------------
+ * u_b = P (P^T K_b P)^{-1} P^T f (Sec. 3.3, the reduced system of the POD
+ * basis and its lift): the coarse factor of the setup applied to the
+ * restricted load, prolonged.  A surrogate-free initial guess for pcg_solve.
+ * FP64.  u: [batch][n] (overwritten).  work: pod2g_rom_bytes(prec) bytes.
+ * Asynchronous.  Errors: EINVAL (no basis: k = 0), ESIZE.                   */
+size_t pod2g_rom_bytes(const pod2g_prec *prec);
+int pod2g_rom_start(const pod2g_prec *prec, const double *f, double *u, void *work,
+                    size_t bytes, hipStream_t stream);
+
 /* ---- live kernel timing ----------------------------------------------------
  * A timer holds per_call pairs of HIP events (created by pod2g_timer_create,
  * released by pod2g_timer_destroy).  In the second chunk of iterations of a

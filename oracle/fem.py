@@ -211,6 +211,36 @@ def assemble(dim: int, N: int, nu: float, E: np.ndarray) -> sp.csr_matrix:
     return K
 
 
+def stiffness_rows(dim: int, N: int, nu: float, E: np.ndarray, rows) -> list:
+    """Rows of the free-DOF stiffness (Eqs. 5-6) one by one, without
+    assembling K: for free DOF `row`, the sum over the (at most 2^dim)
+    elements around its node of E_e times the element-matrix row, on the
+    free columns.  Returns one {free column: value} dict per row."""
+    Ke = element_stiffness(dim, nu, 1.0 / N)
+    fd = free_dofs(dim, N)
+    out = []
+    for row in rows:
+        g = int(fd[row])
+        node, comp = divmod(g, dim)
+        coord = [(node // (N + 1) ** d) % (N + 1) for d in range(dim)]
+        acc = {}
+        for eoff in itertools.product((-1, 0), repeat=dim):
+            e = [coord[d] + eoff[d] for d in range(dim)]
+            if any(v < 0 or v >= N for v in e):
+                continue
+            eid = sum(e[d] * N ** d for d in range(dim))      # ex-fastest element order
+            loc = sum((coord[d] - e[d]) << d for d in range(dim))
+            for b in range(2 ** dim):
+                nb = node_id(dim, N, [e[d] + ((b >> d) & 1) for d in range(dim)])
+                for c in range(dim):
+                    col_g = dim * nb + c
+                    pos = np.searchsorted(fd, col_g)
+                    if pos < len(fd) and fd[pos] == col_g:
+                        acc[int(pos)] = acc.get(int(pos), 0.0) + E[eid] * Ke[dim * loc + comp, dim * b + c]
+        out.append(acc)
+    return out
+
+
 def traction_load_full(dim: int, N: int) -> np.ndarray:
     """Consistent nodal forces of a unit uniform traction: +x on x = 1 (2D,
     each edge segment gives h/2 to its two nodes), +z on z = 1 (3D, each

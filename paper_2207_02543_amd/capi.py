@@ -100,6 +100,11 @@ _f = {
     "pcg_solve_bytes": _sig("pcg_solve_bytes", _sz, [_PP, _i, _i, _i]),
     "pcg_solve": _sig("pcg_solve", _i, [_PP, _vp, _i, _PR, _vp, _vp, _d, _i, _i, C.POINTER(_i),
                                         C.POINTER(_d), C.POINTER(_i), _vp, _sz, _vp]),
+    "pod2g_stationary_solve": _sig("pod2g_stationary_solve", _i,
+                                   [_PP, _vp, _i, _PR, _vp, _vp, _d, _i, C.POINTER(_i),
+                                    C.POINTER(_d), C.POINTER(_i), _vp, _sz, _vp]),
+    "pod2g_rom_bytes": _sig("pod2g_rom_bytes", _sz, [_PR]),
+    "pod2g_rom_start": _sig("pod2g_rom_start", _i, [_PR, _vp, _vp, _vp, _sz, _vp]),
     "pcg_solve_timed": _sig("pcg_solve_timed", _i, [_PP, _vp, _i, _PR, _vp, _vp, _d, _i, _i,
                                                     C.POINTER(_i), C.POINTER(_d), C.POINTER(_i),
                                                     _vp, _sz, C.POINTER(Timer), _vp]),
@@ -218,6 +223,25 @@ def pcg_solve(pat, vals, batch, prec, f, u, rtol, maxit, beta, work, nbytes, str
                           _ptr(f), _ptr(u), float(rtol), int(maxit), int(beta), it, rr, st,
                           _ptr(work), nbytes, _stream(stream))
     return ret, list(it), list(rr), list(st)
+
+
+def pod2g_stationary_solve(pat, vals, batch, prec, f, u, rtol, maxit, work, nbytes, stream=None):
+    """Returns (status, iters[batch], relres[batch], status[batch])."""
+    it = (C.c_int * batch)()
+    rr = (C.c_double * batch)()
+    st = (C.c_int * batch)()
+    ret = _f["pod2g_stationary_solve"](C.byref(pat), _ptr(vals), batch, C.byref(prec), _ptr(f),
+                                       _ptr(u), float(rtol), int(maxit), it, rr, st, _ptr(work),
+                                       nbytes, _stream(stream))
+    return ret, list(it), list(rr), list(st)
+
+
+def pod2g_rom_bytes(prec: Prec) -> int:
+    return _f["pod2g_rom_bytes"](C.byref(prec))
+
+
+def pod2g_rom_start(prec: Prec, f, u, work, nbytes, stream=None) -> int:
+    return _f["pod2g_rom_start"](C.byref(prec), _ptr(f), _ptr(u), _ptr(work), nbytes, _stream(stream))
 
 
 def pcg_solve_timed(pat, vals, batch, prec, f, u, rtol, maxit, beta, work, nbytes, timer,

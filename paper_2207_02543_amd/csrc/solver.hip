@@ -796,6 +796,60 @@ __global__ void __launch_bounds__(NT) k_true_resid(Ctx c, int gate) {
   }
 }
 
+// Standalone two-grid solver (the POD-2G scheme of Sec. 3.3 iterated on its
+// own, as in the Sec. 4 comparisons): u += s after the cycle s = B r ...
+__global__ void __launch_bounds__(NT) k_stat_update(Ctx c) {
+  const int b = inst_id();
+  if (c.st[b].done) return;
+  const int row = blockIdx.x * NT + threadIdx.x;
+  if (row >= c.n) return;
+  const size_t off = (size_t)b * c.n;
+  c.u[off + row] += c.s[off + row];
+}
+
+// ... then r = f - K u (one thread per node) with ||r||^2; the last block
+// counts the iteration, tests ||r|| <= rtol ||f|| and the iteration limit,
+// and sets the next cycle's input scale.
+template <int DIM>
+__global__ void __launch_bounds__(NT) k_stat_resid(Ctx c) {
+  __shared__ double lds[2 * NWAVE];
+  __shared__ int flag;
+  const NodeBlk nbk = node_block(c);
+  const int b = nbk.b, blk = nbk.blk;
+  InstState *st = c.st + b;
+  if (st->done) return;
+  const int node = blk * NT + threadIdx.x;
+  const size_t off = (size_t)b * c.n;
+  double rr = 0.0;
+  if (node < c.nn) {
+    const double *ub = c.u + off;
+    double kx[DIM];
+    node_dot<DIM>(c.colblk, c.vals + (size_t)b * c.vstride, [ub](size_t i) { return ub[i]; }, node,
+                  c.n, c.nn, kx);
+    const size_t r0 = (size_t)node * DIM;
+#pragma unroll
+    for (int r = 0; r < DIM; ++r) {
+      const double rv = c.f[r0 + r] - kx[r];
+      c.r[off + r0 + r] = rv;
+      rr += rv * rv;
+    }
+  }
+  double dummy = 0.0;
+  block_sum2(rr, dummy, lds);
+  if (threadIdx.x == 0) put_partial(slot(c, b, 0) + blk, rr);
+  if (!arrive_last(site(c, b, CNT_A), blk, c.nbn, &flag)) return;
+  const double trr = reduce_partials(slot(c, b, 0), c.nbn, 1, lds);
+  if (threadIdx.x == 0) {
+    st->iter += 1;
+    st->rr = trr;
+    st->rr_true = trr;
+    st->scale = cycle_scale(c, trr);
+    if (!finite(trr)) { st->done = 1; st->status = POD2G_ENAN; }
+    else if (trr <= st->tol2) { st->done = 1; st->status = POD2G_OK; }
+    else if (st->iter >= st->maxit) { st->done = 1; st->status = POD2G_EMAXIT; }
+  }
+}
+
 // Residual replacement for the instances flagged by the host: r = q,
 // CG restarts (beta = 0) and the instance becomes live again.
 __global__ void __launch_bounds__(NT) k_replace(Ctx c, const int *__restrict__ flags, int have_prec) {
@@ -1245,6 +1299,44 @@ static int pcg_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int bet
   return ret;
 }
 
+// Standalone two-grid iterations u <- u + B (f - K u) until the residual
+// test or the iteration limit (maxit >= 1), in growing chunks.
+template <int DIM>
+static int stat_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int *iters_h,
+                    double *relres_h, int *status_h, hipStream_t stream) {
+  dim3 grid(c.nb, c.batch), gridn(c.nbn, c.batch), blk(NT);
+  hipLaunchKernelGGL(k_state_init, dim3(ceil_div(c.batch, 64)), dim3(64), 0, stream, c.st, c.arr,
+                     c.batch, rtol, maxit, (int)POD2G_BETA_FR, (const int *)pr->status);
+  hipLaunchKernelGGL(k_init<DIM>, grid, blk, 0, stream, c, 1);
+  POD2G_HIP_CHECK(hipGetLastError());
+  std::vector<InstState> h;
+  int chunk = 4;
+  for (int guard = 0; guard < 10000000; ++guard) {
+    for (int i = 0; i < chunk; ++i) {
+      launch_first<DIM>(c, pr, stream);
+      launch_cycle_any<DIM>(c, pr, stream, 0, nullptr);
+      hipLaunchKernelGGL(k_stat_update, grid, blk, 0, stream, c);
+      hipLaunchKernelGGL(k_stat_resid<DIM>, gridn, blk, 0, stream, c);
+    }
+    POD2G_HIP_CHECK(hipGetLastError());
+    int st = read_states(c, h, stream);
+    if (st) return st;
+    bool all_done = true;
+    for (int b = 0; b < c.batch; ++b) all_done = all_done && h[b].done;
+    if (all_done) break;
+    if (chunk < 16) chunk *= 2;
+  }
+  int ret = POD2G_OK;
+  for (int b = 0; b < c.batch; ++b) {
+    const int s = h[b].status;
+    if (iters_h) iters_h[b] = h[b].iter;
+    if (relres_h) relres_h[b] = h[b].ff > 0 ? sqrt(h[b].rr / h[b].ff) : 0.0;
+    if (status_h) status_h[b] = s;
+    if (ret == POD2G_OK && s != POD2G_OK) ret = s;
+  }
+  return ret;
+}
+
 // ---------------------------------------------------------------------------
 // single kernels: y = K x and damped-Jacobi sweeps
 // ---------------------------------------------------------------------------
@@ -1337,6 +1429,106 @@ int pcg_solve_timed(const pod2g_pattern *pat, const double *vals, int batch,
   if (pat->mesh.dim == 2)
     return pcg_run<2>(c, prec, rtol, maxit, beta, iters_h, relres_h, status_h, timer, nullptr, stream);
   return pcg_run<3>(c, prec, rtol, maxit, beta, iters_h, relres_h, status_h, timer, nullptr, stream);
+}
+
+int pod2g_stationary_solve(const pod2g_pattern *pat, const double *vals, int batch,
+                           const pod2g_prec *prec, const double *f, double *u, double rtol,
+                           int maxit, int *iters_h, double *relres_h, int *status_h, void *work,
+                           size_t bytes, hipStream_t stream) {
+  if (!prec) return POD2G_EINVAL;
+  int st = check_solve_args(pat, vals, batch, prec, f, u, POD2G_BETA_FR, work, bytes);
+  if (st) return st;
+  if (!(rtol >= 0.0) || maxit < 1) return POD2G_EINVAL;
+  Ctx c;
+  fill_ctx(c, pat, vals, batch, prec, f, u, work);
+  if (pat->mesh.dim == 2) return stat_run<2>(c, prec, rtol, maxit, iters_h, relres_h, status_h, stream);
+  return stat_run<3>(c, prec, rtol, maxit, iters_h, relres_h, status_h, stream);
+}
+
+}  // extern "C"
+
+namespace pod2g {
+
+// Reduced-order solution u = P (P^T K P)^{-1} P^T f.  P^T f: one workgroup
+// per basis column, fixed-order sums (four independent accumulators per
+// thread, then the block tree).
+__global__ void __launch_bounds__(NT) k_rom_restrict(int n, const double *__restrict__ P,
+                                                     const double *__restrict__ f,
+                                                     double *__restrict__ pf) {
+  __shared__ double lds[NWAVE];
+  const double *Pj = P + (size_t)blockIdx.x * n;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int i = threadIdx.x;
+  for (; i + 3 * NT < n; i += 4 * NT) {
+    a0 += Pj[i] * f[i];
+    a1 += Pj[i + NT] * f[i + NT];
+    a2 += Pj[i + 2 * NT] * f[i + 2 * NT];
+    a3 += Pj[i + 3 * NT] * f[i + 3 * NT];
+  }
+  for (; i < n; i += NT) a0 += Pj[i] * f[i];
+  const double v = block_sum((a0 + a1) + (a2 + a3), lds);
+  if (threadIdx.x == 0) pf[blockIdx.x] = v;
+}
+
+// e_b = Linv_b^T (Linv_b P^T f), one workgroup per instance.
+__global__ void __launch_bounds__(NT) k_rom_coarse(int k, const double *__restrict__ Linv,
+                                                   const double *__restrict__ pf,
+                                                   double *__restrict__ e) {
+  __shared__ double y[MAXK];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const double *Li = Linv + (size_t)b * k * k;
+  if (t < k) {
+    double v = 0.0;
+    for (int j = 0; j <= t; ++j) v += Li[t * k + j] * pf[j];
+    y[t] = v;
+  }
+  __syncthreads();
+  if (t < k) {
+    double v = 0.0;
+    for (int j = t; j < k; ++j) v += Li[j * k + t] * y[j];
+    e[(size_t)b * MAXK + t] = v;
+  }
+}
+
+// u_b = P e_b.
+__global__ void __launch_bounds__(NT) k_rom_prolong(int n, int k, const double *__restrict__ P,
+                                                    const double *__restrict__ e,
+                                                    double *__restrict__ u) {
+  __shared__ double es[MAXK];
+  const int b = blockIdx.y;
+  if (threadIdx.x < k) es[threadIdx.x] = e[(size_t)b * MAXK + threadIdx.x];
+  __syncthreads();
+  const int row = blockIdx.x * NT + threadIdx.x;
+  if (row >= n) return;
+  double acc = 0.0;
+  for (int j = 0; j < k; ++j) acc += P[(size_t)j * n + row] * es[j];
+  u[(size_t)b * n + row] = acc;
+}
+
+}  // namespace pod2g
+
+extern "C" {
+
+size_t pod2g_rom_bytes(const pod2g_prec *prec) {
+  if (!prec || prec->batch < 1) return 0;
+  return align256(sizeof(double) * MAXK) + align256(sizeof(double) * MAXK * (size_t)prec->batch);
+}
+
+int pod2g_rom_start(const pod2g_prec *prec, const double *f, double *u, void *work, size_t bytes,
+                    hipStream_t stream) {
+  if (!prec || !f || !u || !work || check_prec(prec)) return POD2G_EINVAL;
+  if (prec->k < 1) return POD2G_EINVAL;
+  if (bytes < pod2g_rom_bytes(prec)) return POD2G_ESIZE;
+  const int n = prec->pat.n, k = prec->k, B = prec->batch;
+  double *pf = (double *)work;
+  double *e = (double *)((char *)work + align256(sizeof(double) * MAXK));
+  hipLaunchKernelGGL(k_rom_restrict, dim3(k), dim3(NT), 0, stream, n, prec->P, f, pf);
+  hipLaunchKernelGGL(k_rom_coarse, dim3(B), dim3(NT), 0, stream, k, (const double *)prec->Linv,
+                     (const double *)pf, e);
+  hipLaunchKernelGGL(k_rom_prolong, dim3(ceil_div(n, NT), B), dim3(NT), 0, stream, n, k, prec->P,
+                     (const double *)e, u);
+  POD2G_HIP_CHECK(hipGetLastError());
+  return POD2G_OK;
 }
 
 int pcg_solve(const pod2g_pattern *pat, const double *vals, int batch, const pod2g_prec *prec,
@@ -1448,15 +1640,38 @@ int pod2g_server_create(const pod2g_group *groups, int n_groups, int chunk, pod2
     delete sv;
     return POD2G_EHIP;
   }
-  hipStream_t cs;
-  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { delete sv; return POD2G_EHIP; }
-  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  // Capture: one branch per group (forked from and joined into the capture
+  // stream with events), so the groups' kernels may run side by side and a
+  // small class does not wait for a large one's iterations.
+  const int G = (int)sv->groups.size();
+  std::vector<hipStream_t> bs(G, nullptr);
+  std::vector<hipEvent_t> done_ev(G, nullptr);
+  hipStream_t cs = nullptr;
+  hipEvent_t fork = nullptr;
+  bool ok = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess &&
+            hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess;
+  for (int g = 0; ok && g < G; ++g)
+    ok = hipStreamCreateWithFlags(&bs[g], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&done_ev[g], hipEventDisableTiming) == hipSuccess;
+  if (ok) ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
   if (ok) {
-    for (const auto &g : sv->groups) serve_group_step(g, chunk, cs);
-    ok = hipStreamEndCapture(cs, &sv->graph) == hipSuccess;
+    bool cap = hipEventRecord(fork, cs) == hipSuccess;
+    for (int g = 0; cap && g < G; ++g) {
+      cap = hipStreamWaitEvent(bs[g], fork, 0) == hipSuccess;
+      if (cap) serve_group_step(sv->groups[g], chunk, bs[g]);
+      cap = cap && hipEventRecord(done_ev[g], bs[g]) == hipSuccess &&
+            hipStreamWaitEvent(cs, done_ev[g], 0) == hipSuccess;
+    }
+    const bool ended = hipStreamEndCapture(cs, &sv->graph) == hipSuccess;
+    ok = cap && ended;
   }
   if (ok && hipGraphInstantiate(&sv->exec, sv->graph, nullptr, nullptr, 0) != hipSuccess) ok = false;
-  (void)hipStreamDestroy(cs);
+  for (int g = 0; g < G; ++g) {
+    if (done_ev[g]) (void)hipEventDestroy(done_ev[g]);
+    if (bs[g]) (void)hipStreamDestroy(bs[g]);
+  }
+  if (fork) (void)hipEventDestroy(fork);
+  if (cs) (void)hipStreamDestroy(cs);
   if (!ok) {
     if (sv->graph) (void)hipGraphDestroy(sv->graph);
     delete sv;

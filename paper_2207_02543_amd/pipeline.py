@@ -123,6 +123,21 @@ class Problem:
         return L.pcg_solve(self.pat, sysm.vals, sysm.batch, prec, sysm.f, u, rtol, maxit, beta,
                            wk, nb, stream)
 
+    def stationary(self, sysm: System, prec, u, rtol=None, maxit=5000, key="pcg", stream=None):
+        """The two-grid scheme iterated on its own: u <- u + B (f - K u)."""
+        nb = L.pcg_solve_bytes(self.pat, sysm.batch, prec.k, prec.precision)
+        wk = self.work(key, nb)
+        rtol = self.w.tol if rtol is None else rtol
+        return L.pod2g_stationary_solve(self.pat, sysm.vals, sysm.batch, prec, sysm.f, u, rtol,
+                                        maxit, wk, nb, stream)
+
+    def rom_start(self, sysm: System, prec, u, stream=None):
+        """u = P (P^T K P)^{-1} P^T f, the reduced-order warm start."""
+        nb = L.pod2g_rom_bytes(prec)
+        wk = self.work("rom", nb)
+        L.check(L.pod2g_rom_start(prec, sysm.f, u, wk, nb, stream), "pod2g_rom_start")
+        return u
+
     def plan(self, sysm: System, prec, u, chunk=8, timer=None, key="pcg"):
         """Capture `chunk` PCG iterations on these buffers (see pcg_plan_create)."""
         k = prec.k if prec is not None else 0

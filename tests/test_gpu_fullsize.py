@@ -1,0 +1,140 @@
+"""The workloads at their full sizes, in the launch configuration the
+benchmark times (captured chunks of 8 iterations, the workload's batch and
+precision), checked on outputs the oracle computes one by one and through
+properties that hold at any size:
+
+* assembly: sampled rows of K(theta) against the oracle's row-by-row
+  element sums (1e-13);
+* SpMV: the same rows of K x for a seeded x;
+* the cycle: B symmetric (r^T B s = s^T B r) and positive (r^T B r > 0);
+* PCG: every instance converges, its reported true residual matches
+  ||f - K u|| / ||f|| formed from the checked SpMV, and the solution agrees
+  with the FP64 path's to 1e-6.
+
+The basis comes from fewer training solves than the benchmark's (stated per
+workload): it changes iteration counts, not the kernels or their launch
+shapes."""
+import numpy as np
+import pytest
+
+from gpu_helpers import flush, relerr
+from oracle import fem
+from paper_2207_02543_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+# workload -> training solves used here (the benchmark uses w.n_train; at
+# least k of them, at training tolerance 1e-8 instead of 1e-12)
+CASES = {"c2": 40, "c4a": 40, "c4b": 40, "c4c": 40, "c3": 40, "c5": 50}
+
+
+def _rows(w, count=48, seed=11):
+    rng = np.random.default_rng(seed)
+    edge = [0, 1, w.dim, w.n - 1, w.n - w.dim, w.n // 2]
+    return sorted(set(edge + [int(x) for x in rng.integers(0, w.n, size=count)]))
+
+
+def _gpu_rows(prob, sysm, b, rows, torch):
+    """Row dicts {column: value} of instance b from the block-ELL arrays."""
+    w = prob.w
+    S, dim, n, nn = 3 ** w.dim, w.dim, w.n, w.n_nodes_free
+    colblk = prob.pat_buf[: S * nn * 4].view(torch.int32)
+    rows_t = torch.tensor(rows, device="cuda", dtype=torch.long)
+    nodes = rows_t // dim
+    out = [dict() for _ in rows]
+    for s in range(S):
+        cb = colblk[s * nn + nodes].long()
+        for c in range(dim):
+            v = sysm.vals[b][(s * dim + c) * n + rows_t].cpu().numpy()
+            cols = (cb * dim + c).cpu().numpy()
+            for i in range(len(rows)):
+                out[i][int(cols[i])] = out[i].get(int(cols[i]), 0.0) + float(v[i])
+    return out
+
+
+def _check_rows(got, ref, tol=1e-13):
+    for g, r in zip(got, ref):
+        scale = max(abs(v) for v in r.values())
+        for c in set(g) | set(r):
+            assert abs(g.get(c, 0.0) - r.get(c, 0.0)) <= tol * scale, c
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", list(CASES))
+def test_full_size_workload(name):
+    import torch
+    from paper_2207_02543_amd import capi, pipeline
+    w = I.WORKLOADS[name]
+    # served classes run as slot groups of the mixed batched path
+    served = name.startswith("c4")
+    mixed = w.precision == "mixed" or served
+    B = 4 if served else w.batch
+    flush(f"full size {name}: dim {w.dim} N {w.N} n {w.n} k {w.k} batch {B} "
+          f"{'mixed' if mixed else 'fp64'}")
+    prob = pipeline.Problem(w)
+    xis = I.query_xis(w, B)
+    sysm = prob.alloc_system(B, fp32=mixed)
+    prob.assemble(sysm, xis)
+
+    # assembly and SpMV on sampled rows
+    rows = _rows(w)
+    for b in sorted({0, B - 1}):
+        E = fem.young_modulus(w.dim, w.N, xis[b], w.kl_scale)
+        ref = fem.stiffness_rows(w.dim, w.N, w.nu, E, rows)
+        _check_rows(_gpu_rows(prob, sysm, b, rows, torch), ref)
+        x = torch.tensor(np.random.default_rng(3 + b).standard_normal(w.n), device="cuda")
+        xs = torch.zeros(B, w.n, dtype=torch.float64, device="cuda")
+        xs[b] = x
+        ys = torch.empty_like(xs)
+        capi.check(capi.pod2g_spmv(prob.pat, sysm.vals, B, xs, ys), "pod2g_spmv")
+        yh, xh = ys[b].cpu().numpy(), x.cpu().numpy()
+        for i, r in enumerate(rows):
+            yr = sum(v * xh[c] for c, v in ref[i].items())
+            assert abs(yh[r] - yr) <= 1e-13 * sum(abs(v * xh[c]) for c, v in ref[i].items())
+    flush("  sampled rows of K and K x agree")
+
+    # basis from a reduced offline phase
+    P, lam, U, its = pipeline.offline_basis(prob, n_train=CASES[name], k=w.k, rtol=1e-8)
+    del U
+    flush(f"  basis from {CASES[name]} training solves ({sum(its)} iterations)")
+    precision = capi.MIXED if mixed else capi.FP64
+    pr = prob.setup(sysm, P, precision=precision)
+    st, _ = capi.pod2g_setup_status(pr)
+    assert st == [capi.OK] * B
+
+    # the cycle is symmetric positive definite (one instance, batch as timed)
+    g = torch.Generator(device="cpu").manual_seed(5)
+    r1 = torch.randn(B, w.n, dtype=torch.float64, generator=g).cuda()
+    r2 = torch.randn(B, w.n, dtype=torch.float64, generator=g).cuda()
+    s1, s2 = torch.empty_like(r1), torch.empty_like(r2)
+    prob.apply(pr, r1, s1)
+    prob.apply(pr, r2, s2)
+    for b in sorted({0, B - 1}):
+        a, c = float(r2[b] @ s1[b]), float(r1[b] @ s2[b])
+        e1, e2 = float(r1[b] @ s1[b]), float(r2[b] @ s2[b])
+        assert e1 > 0.0 and e2 > 0.0
+        # relative to the B-norm bound |r2^T B r1| <= (r1^T B r1 r2^T B r2)^(1/2);
+        # FP32 cycle: 24-bit rounding through the sweeps and products
+        tol = 1e-5 if mixed else 1e-11
+        assert abs(a - c) <= tol * (e1 * e2) ** 0.5, (a, c)
+    flush("  cycle symmetric and positive")
+
+    # PCG in the timed configuration, against the FP64 path
+    ustar = pipeline.exact_solutions(prob, xis, P, rtol=1e-11)
+    u = torch.empty(B, w.n, dtype=torch.float64, device="cuda")
+    gn = torch.tensor(np.stack([I.noise(w, j) for j in range(B)]), device="cuda")
+    x0 = torch.stack([I.warm_start(ustar[j], gn[j], w.noise) for j in range(B)])
+    u.copy_(x0)
+    plan = prob.plan(sysm, pr, u, chunk=8)
+    ret, it, rr, stt = plan.solve(w.tol)
+    plan.close()
+    flush(f"  pcg: iterations {it}, relres max {max(rr):.2e}")
+    assert ret == capi.OK, stt
+    y = torch.empty_like(u)
+    capi.check(capi.pod2g_spmv(prob.pat, sysm.vals, B, u, y), "pod2g_spmv")
+    torch.cuda.synchronize()
+    for b in range(B):
+        res = float(torch.linalg.norm(sysm.f - y[b]) / torch.linalg.norm(sysm.f))
+        assert rr[b] <= w.tol and abs(res - rr[b]) <= 1e-3 * rr[b] + 1e-15
+        assert relerr(u[b].cpu().numpy(), ustar[b].cpu().numpy()) <= 1e-6
+    flush("  converged; true residuals and errors within bounds")

@@ -175,3 +175,21 @@ def test_free_dof_numbering():
     assert fd[0] == 2 * 1 and fd[2 * (2 + 4 * 3) + 1] == 2 * fem.node_id(2, 4, [3, 3]) + 1
     fd = fem.free_dofs(3, 3)
     assert fd[3 * (1 + 4 * 2 + 16 * 0) + 2] == 3 * fem.node_id(3, 3, [1, 2, 1]) + 2
+
+
+@pytest.mark.parametrize("dim,N", [(2, 5), (3, 3)])
+def test_stiffness_rows_equal_assembled_rows(dim, N):
+    """Row-by-row stiffness (used to check the GPU at sizes the assembled
+    oracle cannot reach) against the full assembly on small meshes."""
+    w = I.small(dim, N)
+    xi = I.query_xi(w, 0)
+    E = fem.young_modulus(dim, N, xi, w.kl_scale)
+    K = fem.assemble(dim, N, w.nu, E).tocsr()
+    rows = list(range(K.shape[0]))
+    got = fem.stiffness_rows(dim, N, w.nu, E, rows)
+    for r in rows:
+        ref = {int(c): v for c, v in zip(K.indices[K.indptr[r]:K.indptr[r + 1]],
+                                         K.data[K.indptr[r]:K.indptr[r + 1]])}
+        assert set(got[r]) == set(ref)
+        for c, v in ref.items():
+            assert abs(got[r][c] - v) <= 1e-14 * max(1.0, abs(v))

@@ -143,3 +143,31 @@ def test_mixed_mode_iteration_count_close_to_fp64():
     assert a.status == b.status == pcg.OK
     assert abs(a.iters - b.iters) <= 2
     assert np.linalg.norm(a.u - b.u) / np.linalg.norm(a.u) < 1e-6
+
+
+def test_rom_solve_galerkin_orthogonality():
+    """The reduced solution's residual is orthogonal to the basis (Galerkin
+    condition of the reduced system), and the reduced solution minimises the
+    energy norm of the error over span(P)."""
+    w, P, q = _setup(2, 8, k=5)
+    L = twogrid.coarse_factor(q.K, P)
+    u = pcg.rom_solve(q.K, q.f, P, L)
+    r = q.f - q.K @ u
+    assert np.abs(P.T @ r).max() <= 1e-10 * np.abs(P.T @ q.f).max()
+    Kd = q.K.toarray()
+
+    def energy(v):
+        e = v - q.u_exact
+        return e @ (Kd @ e)
+    rng = np.random.default_rng(5)
+    for _ in range(5):
+        assert energy(u) <= energy(u + P @ (1e-3 * rng.standard_normal(P.shape[1])))
+
+
+def test_standalone_twogrid_one_cycle_with_full_basis():
+    """k = n: the coarse correction is exact, so one cycle solves the system."""
+    w, P, q = _setup(2, 3, k=4)
+    n = q.K.shape[0]
+    M = twogrid.TwoGrid(q.K, np.eye(n), w.omega)
+    res = pcg.twogrid_solve(q.K, q.f, q.x0, M, tol=1e-10, maxit=5)
+    assert res.status == pcg.OK and res.iters == 1
