@@ -211,6 +211,13 @@ def main(argv=None):
     ap.add_argument("--markers", action="store_true",
                     help="launch the k_mark_begin / k_mark_end kernels around the timed steps "
                          "(for cutting a rocprofv3 trace to them)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default launch parameters (no timing of candidates)")
+    ap.add_argument("--warm", default="noisy", choices=["noisy", "rom", "zero"],
+                    help="initial guess: exact + 1%% noise (surrogate stand-in), the reduced-order "
+                         "solution P K_c^-1 P^T f formed inside the step, or zero")
+    ap.add_argument("--solver", default="pcg", choices=["pcg", "stationary"],
+                    help="PCG preconditioned by the cycle, or the cycle iterated on its own")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
     ap.add_argument("--serve-seconds", type=float, default=60.0, help="serving: arrival window")
     ap.add_argument("--hbm-fraction", type=float, default=0.5,
@@ -265,20 +272,31 @@ def main(argv=None):
     timer = L.pod2g_timer_create(KERNELS[args.kernel], 6)
     stats = {"iters": [], "relres": [], "err": []}
     plan = None
-    if args.chunk > 0:
+    tuning = None
+    if args.chunk > 0 and args.solver == "pcg":
         # capture the PCG iterations once: every step reuses these buffers
         sysm.xi.copy_(xi_d[:w.batch])
         prob.assemble(sysm)
         prec0 = prob.setup(sysm, P, precision=precision)
         plan = prob.plan(sysm, prec0, u, chunk=args.chunk, timer=timer)
+        if not args.no_tune:
+            tuning = plan.tune()
+            log(f"[bench] tuned launch parameters: {tuning}")
 
     def step(i, timed):
         idx = [(i * w.batch + b) % Q for b in range(w.batch)]
         sysm.xi.copy_(xi_d[idx])
         prob.assemble(sysm)
         prec = prob.setup(sysm, P, precision=precision)
-        u.copy_(x0[idx])
-        if plan is not None:
+        if args.warm == "noisy":
+            u.copy_(x0[idx])
+        elif args.warm == "rom":
+            prob.rom_start(sysm, prec, u)
+        else:
+            u.zero_()
+        if args.solver == "stationary":
+            ret, its, rr, st = prob.stationary(sysm, prec, u, maxit=20000)
+        elif plan is not None:
             ret, its, rr, st = plan.solve(w.tol)
         else:
             ret, its, rr, st = prob.solve(sysm, prec, u, timer=timer if timed else None)
@@ -317,7 +335,8 @@ def main(argv=None):
     achieved = nbytes / avg_s / 1e9 if cnt else None
     log(f"[bench] {solves} solves in {dt:.3f} s; mean iterations "
         f"{np.mean(stats['iters']):.1f}; {args.kernel}: {cnt} timed launches, "
-        f"{avg_s * 1e6:.1f} us avg, {nbytes / 1e6:.2f} MB -> {achieved:.0f} GB/s")
+        f"{avg_s * 1e6:.1f} us avg, {nbytes / 1e6:.2f} MB -> "
+        f"{f'{achieved:.0f}' if achieved else '-'} GB/s")
 
     result = {
         "metric": METRIC, "value": value, "unit": "solves/s", "n_gpus": 1,
@@ -330,7 +349,8 @@ def main(argv=None):
                    "n": w.n, "k": w.k, "n_train": w.n_train, "batch": w.batch,
                    "precision": w.precision, "tol": w.tol, "omega": w.omega,
                    "sweeps": [w.nu_pre, w.nu_post], "queries": Q,
-                   "graph_chunk": args.chunk,
+                   "graph_chunk": args.chunk if args.solver == "pcg" else 0,
+                   "warm_start": args.warm, "solver": args.solver, "tuning": tuning,
                    "iters_mean": float(np.mean(stats["iters"])),
                    "relres_max": float(np.max(stats["relres"])),
                    "err_vs_fp64_max": float(np.max(stats["err"]))},

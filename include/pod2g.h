@@ -273,6 +273,22 @@ int pcg_plan_solve(pod2g_plan *plan, double rtol, int maxit, int beta,
                    int *iters_h, double *relres_h, int *status_h, hipStream_t stream);
 int pcg_plan_destroy(pod2g_plan *plan);
 
+/* Launch-parameter tuning of a plan on its own buffers: times `trials`
+ * (2..1000) PCG iterations from a fresh start for each candidate value of
+ * one parameter at a time and keeps the fastest, then recaptures the plan:
+ * the workgroups of the batched restriction (128..1024, batched FP32 cycle
+ * only), the direction update folded into the outer SpMV or run as its own
+ * pass, and the instance grouping of the node-wise block order (divisors of
+ * the batch up to 8).  It overwrites u and the solve workspace: call it
+ * before loading the initial guess.  Synchronous.  out may be NULL.       */
+typedef struct pod2g_tuning {
+  int bgrid;               /* workgroups of the batched restriction */
+  int fuse_dir;            /* 1: p = s + beta p formed inside the outer SpMV */
+  int igroup;              /* instances per group in the node-wise block order */
+  float ms_per_iteration;  /* time of one iteration with the chosen values */
+} pod2g_tuning;
+int pcg_plan_tune(pod2g_plan *plan, int trials, pod2g_tuning *out, hipStream_t stream);
+
 /* ---- served solves (continuous batching over slot groups) -----------------
  * Many independent queries theta (Sec. 3, the multi-query setting) arrive
  * over time.  A server owns n_groups slot groups; group g is one problem

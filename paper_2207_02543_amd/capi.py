@@ -47,6 +47,11 @@ class Prec(C.Structure):
                 ("status", C.c_void_p), ("work", C.c_void_p)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("bgrid", C.c_int), ("fuse_dir", C.c_int), ("igroup", C.c_int),
+                ("ms_per_iteration", C.c_float)]
+
+
 class SlotInfo(C.Structure):
     _fields_ = [("done", C.c_int), ("iter", C.c_int), ("status", C.c_int), ("pad", C.c_int),
                 ("relres", C.c_double)]
@@ -116,6 +121,7 @@ _f = {
     "pcg_plan_solve": _sig("pcg_plan_solve", _i, [_vp, _d, _i, _i, C.POINTER(_i), C.POINTER(_d),
                                                   C.POINTER(_i), _vp]),
     "pcg_plan_destroy": _sig("pcg_plan_destroy", _i, [_vp]),
+    "pcg_plan_tune": _sig("pcg_plan_tune", _i, [_vp, _i, C.POINTER(Tuning), _vp]),
     "pod2g_mark": _sig("pod2g_mark", _i, [_i, _vp]),
     "pod2g_spmv": _sig("pod2g_spmv", _i, [_PP, _vp, _i, _vp, _vp, _vp]),
     "pod2g_jacobi": _sig("pod2g_jacobi", _i, [_PP, _vp, _vp, _i, _d, _i, _vp, _vp, _vp, _vp]),
@@ -287,6 +293,12 @@ def pcg_plan_solve(plan, rtol, maxit, beta, batch, stream=None):
     st = (C.c_int * batch)()
     ret = _f["pcg_plan_solve"](plan, float(rtol), int(maxit), int(beta), it, rr, st, _stream(stream))
     return ret, list(it), list(rr), list(st)
+
+
+def pcg_plan_tune(plan, trials, stream=None) -> Tuning:
+    t = Tuning()
+    check(_f["pcg_plan_tune"](plan, trials, C.byref(t), _stream(stream)), "pcg_plan_tune")
+    return t
 
 
 def pcg_plan_destroy(plan) -> int:

@@ -21,6 +21,7 @@ struct Ctx {
   int n, nn, k, batch, nb, ps;   // ps: partial stride per workgroup (doubles)
   int nbn;                       // workgroups of the node-wise kernels (one thread per node)
   int igroup;                    // instances per group in the node-wise block order (divides batch)
+  int fuse_dir;                  // direction update folded into the outer SpMV
   int mixed;                     // FP32 cycle: its input is scaled by a power of two
   long long vstride;
   const int *colblk;
@@ -959,9 +960,13 @@ struct Layout {
   int bgrid;
 };
 
-static int batched_grid(int n) {
+constexpr int BGRID_DEFAULT = 512;    // workgroups of the batched restriction
+constexpr int BGRID_MAX = 1024;       // largest the tuner tries (workspace is sized for it)
+constexpr long long FUSE_DIR_MAX = 1ll << 20;   // rows x instances with the fused update
+
+static int batched_grid(int n, int cap) {
   const int nb = ceil_div(n, NT);
-  return nb < 512 ? nb : 512;
+  return nb < cap ? nb : cap;
 }
 
 static Layout layout(int n, int batch, int k, int precision) {
@@ -972,10 +977,10 @@ static Layout layout(int n, int batch, int k, int precision) {
   L.st = o;    o += align256(sizeof(InstState) * (size_t)batch);
   L.ec = o;    o += align256(sizeof(double) * MAXK * (size_t)batch);
   L.part = o;  o += align256(sizeof(double) * (size_t)ps * nb * batch);
-  L.bgrid = batched_grid(n);
+  L.bgrid = batched_grid(n, BGRID_DEFAULT);
   L.bpart = o;
   if (precision == POD2G_MIXED && batch >= BATCH_MFMA_MIN && batch <= MAXB && k > 0)
-    o += align256(sizeof(double) * (size_t)(L.bgrid + 1) * k * batch);
+    o += align256(sizeof(double) * (size_t)(batched_grid(n, BGRID_MAX) + 1) * k * batch);
   L.flags = o; o += align256(sizeof(int) * (size_t)batch);
   L.info = o;  o += align256(sizeof(pod2g_slot_info) * (size_t)batch);
   L.arr = o;   o += sizeof(Arrival) * NSITE * (size_t)batch;
@@ -1010,6 +1015,7 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
   c.nb = ceil_div(n, NT);
   c.nbn = ceil_div(pat->n_nodes, NT);
   c.igroup = default_igroup(batch);
+  c.fuse_dir = (long long)n * batch <= FUSE_DIR_MAX;
   c.ps = k > 2 ? k : 2;
   c.vstride = pat->nvals;
   c.colblk = pat->colblk;
@@ -1148,8 +1154,6 @@ static void launch_first(const Ctx &c, const pod2g_prec *pr, hipStream_t stream)
   else if (wx) hipLaunchKernelGGL((k_cyc_first<double>), grid, dim3(NT), 0, stream, c, wx);
 }
 
-constexpr long long FUSE_DIR_MAX = 1ll << 20;   // rows x instances
-
 // One PCG iteration.  Iterations alternate the two direction buffers
 // (parity 0 reads p0 and writes p1), so chunks have an even length.
 template <int DIM>
@@ -1162,7 +1166,7 @@ static void launch_iteration(const Ctx &c, const pod2g_prec *pr, hipStream_t str
   // small problems are launch-bound: fold the direction update into the
   // SpMV; large ones are bandwidth-bound: a second gathered vector costs
   // more than one elementwise pass
-  if ((long long)c.n * c.batch <= FUSE_DIR_MAX) {
+  if (c.fuse_dir) {
     launch(tm, POD2G_TK_SPMV_PQ, k_spmv_pq<DIM, true>, gridn, blk, 0, stream, c, sdir, pold, pnew);
   } else {
     hipLaunchKernelGGL(k_pdir, grid, blk, 0, stream, c, sdir, pold, pnew);
@@ -1538,6 +1542,126 @@ int pcg_solve(const pod2g_pattern *pat, const double *vals, int batch, const pod
                          status_h, work, bytes, nullptr, stream);
 }
 
+}  // extern "C"
+
+namespace pod2g {
+
+// (Re)capture the plan's chunk of iterations into its graph.
+static int capture_plan(pod2g_plan *pl) {
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  pl->exec = nullptr;
+  pl->graph = nullptr;
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return POD2G_EHIP;
+  const pod2g_prec *pr = pl->has_prec ? &pl->prec : nullptr;
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    for (int i = 0; i < pl->chunk; ++i) {
+      if (pl->pat.mesh.dim == 2) launch_iteration<2>(pl->c, pr, cs, nullptr, i & 1);
+      else launch_iteration<3>(pl->c, pr, cs, nullptr, i & 1);
+    }
+    ok = hipStreamEndCapture(cs, &pl->graph) == hipSuccess;
+  }
+  if (ok && hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(pl->graph);
+    pl->graph = nullptr;
+    ok = false;
+  }
+  (void)hipStreamDestroy(cs);
+  return ok ? POD2G_OK : POD2G_EHIP;
+}
+
+// Average time of one PCG iteration with the Ctx's launch parameters: a
+// fresh start with rtol = 0 (no instance stops), two warm-up iterations,
+// then `trials` timed ones (eager launches).
+template <int DIM>
+static int time_iterations(Ctx &c, const pod2g_prec *pr, int trials, hipStream_t s, float *ms) {
+  dim3 grid(c.nb, c.batch), blk(NT);
+  const int beta = pr && pr->precision == POD2G_MIXED ? POD2G_BETA_PR : POD2G_BETA_FR;
+  hipLaunchKernelGGL(k_state_init, dim3(ceil_div(c.batch, 64)), dim3(64), 0, s, c.st, c.arr, c.batch,
+                     0.0, 1 << 30, beta, pr ? (const int *)pr->status : (const int *)nullptr);
+  hipLaunchKernelGGL(k_init<DIM>, grid, blk, 0, s, c, pr ? 1 : 0);
+  if (pr) {
+    launch_first<DIM>(c, pr, s);
+    launch_cycle_any<DIM>(c, pr, s, 1, nullptr);
+  }
+  launch_iteration<DIM>(c, pr, s, nullptr, 0);
+  launch_iteration<DIM>(c, pr, s, nullptr, 1);
+  hipEvent_t e0, e1;
+  POD2G_HIP_CHECK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return POD2G_EHIP; }
+  int st = POD2G_OK;
+  if (hipEventRecord(e0, s) != hipSuccess) st = POD2G_EHIP;
+  for (int i = 0; st == POD2G_OK && i < trials; ++i) launch_iteration<DIM>(c, pr, s, nullptr, i & 1);
+  if (st == POD2G_OK && (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+                         hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(ms, e0, e1) != hipSuccess))
+    st = POD2G_EHIP;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st == POD2G_OK) *ms /= trials;
+  return st;
+}
+
+}  // namespace pod2g
+
+extern "C" {
+
+int pcg_plan_tune(pod2g_plan *pl, int trials, pod2g_tuning *out, hipStream_t stream) {
+  if (!pl || trials < 2 || trials > 1000) return POD2G_EINVAL;
+  Ctx &c = pl->c;
+  const pod2g_prec *pr = pl->has_prec ? &pl->prec : nullptr;
+  auto measure = [&](float *ms) {
+    return pl->pat.mesh.dim == 2 ? time_iterations<2>(c, pr, trials, stream, ms)
+                                 : time_iterations<3>(c, pr, trials, stream, ms);
+  };
+  float best = 0.f;
+  int st = measure(&best);
+  if (st) return st;
+  // one parameter at a time, keeping the best value of each
+  std::vector<int> grids;
+  if (pr && pr->precision == POD2G_MIXED && batched_products<float>(c) && c.k > 0) {
+    const int cap = batched_grid(c.n, BGRID_MAX);
+    for (int g : {128, 256, 512, 1024})
+      if (g <= cap) grids.push_back(g);
+  }
+  for (int g : grids) {
+    if (g == c.bgrid) continue;
+    const int keep = c.bgrid;
+    c.bgrid = g;
+    float ms;
+    if ((st = measure(&ms))) return st;
+    if (ms < best) best = ms;
+    else c.bgrid = keep;
+  }
+  {
+    const int keep = c.fuse_dir;
+    c.fuse_dir = !keep;
+    float ms;
+    if ((st = measure(&ms))) return st;
+    if (ms < best) best = ms;
+    else c.fuse_dir = keep;
+  }
+  for (int g : {1, 2, 4, 8}) {
+    if (g == c.igroup || c.batch % g) continue;
+    const int keep = c.igroup;
+    c.igroup = g;
+    float ms;
+    if ((st = measure(&ms))) return st;
+    if (ms < best) best = ms;
+    else c.igroup = keep;
+  }
+  if ((st = capture_plan(pl))) return st;
+  if (out) {
+    out->bgrid = c.bgrid;
+    out->fuse_dir = c.fuse_dir;
+    out->igroup = c.igroup;
+    out->ms_per_iteration = best;
+  }
+  return POD2G_OK;
+}
+
 int pcg_plan_create(const pod2g_pattern *pat, const double *vals, int batch, const pod2g_prec *prec,
                     const double *f, double *u, int chunk, void *work, size_t bytes,
                     pod2g_timer *timer, pod2g_plan **out) {
@@ -1554,24 +1678,7 @@ int pcg_plan_create(const pod2g_pattern *pat, const double *vals, int batch, con
   pl->chunk = chunk;
   pl->timer = timer;
   fill_ctx(pl->c, pat, vals, batch, prec, f, u, work);
-  hipStream_t cs;
-  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) { delete pl; return POD2G_EHIP; }
-  const pod2g_prec *pr = prec ? &pl->prec : nullptr;
-  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
-  if (ok) {
-    for (int i = 0; i < chunk; ++i) {
-      if (pat->mesh.dim == 2) launch_iteration<2>(pl->c, pr, cs, nullptr, i & 1);
-      else launch_iteration<3>(pl->c, pr, cs, nullptr, i & 1);
-    }
-    ok = hipStreamEndCapture(cs, &pl->graph) == hipSuccess;
-  }
-  if (ok && hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0) != hipSuccess) {
-    (void)hipGraphDestroy(pl->graph);
-    pl->graph = nullptr;
-    ok = false;
-  }
-  (void)hipStreamDestroy(cs);
-  if (!ok) {
+  if (capture_plan(pl) != POD2G_OK) {
     delete pl;
     return POD2G_EHIP;
   }

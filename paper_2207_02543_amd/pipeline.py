@@ -165,6 +165,13 @@ class Plan:
             beta = L.BETA_PR if self.precision == L.MIXED else L.BETA_FR
         return L.pcg_plan_solve(self.handle, rtol, maxit, beta, self.batch, stream)
 
+    def tune(self, trials=8, stream=None) -> dict:
+        """Pick the launch parameters by timing (overwrites u: call before
+        loading the initial guess)."""
+        t = L.pcg_plan_tune(self.handle, trials, stream)
+        return {"bgrid": t.bgrid, "fuse_dir": t.fuse_dir, "igroup": t.igroup,
+                "ms_per_iteration": t.ms_per_iteration}
+
     def close(self):
         if self.handle:
             L.pcg_plan_destroy(self.handle)

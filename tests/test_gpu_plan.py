@@ -56,3 +56,39 @@ def test_plan_replays_match_eager(dim, N, prec, chunk, batch):
     assert timer.launches > 0 and timer.total_ms > 0.0
     plan.close()
     capi.pod2g_timer_destroy(timer)
+
+
+@pytest.mark.parametrize("dim,N,prec,batch", [(2, 24, "fp64", 1), (3, 6, "mixed", 8)])
+def test_tuned_plan_solves_like_eager(dim, N, prec, batch):
+    """The tuner only changes launch parameters (grid of the batched
+    restriction, fused or separate direction update, block order): the tuned
+    plan converges like the eager solve (iterations within 2, same accuracy)."""
+    import torch
+    from paper_2207_02543_amd import capi, pipeline
+    flush(f"tuned plan dim={dim} N={N} {prec} batch={batch}")
+    w = I.small(dim, N, k=6, n_train=12)
+    P, lam, U = oprob.basis(w, I.train_xis(w))
+    Pd = torch.tensor(np.ascontiguousarray(P.T), device="cuda")
+    precision = capi.MIXED if prec == "mixed" else capi.FP64
+    queries = [oprob.query(w, I.query_xi(w, j), I.noise(w, j)) for j in range(batch)]
+    prob = pipeline.Problem(w)
+    sysm = prob.alloc_system(batch, fp32=(prec == "mixed"))
+    prob.assemble(sysm, np.stack([q.xi for q in queries]))
+    pr = prob.setup(sysm, Pd, precision=precision)
+    x0 = torch.tensor(np.stack([q.x0 for q in queries]), device="cuda")
+    u = x0.clone()
+    ret, it_e, rr_e, st = prob.solve(sysm, pr, u)
+    assert ret == capi.OK
+    u_e = u.cpu().numpy().copy()
+    plan = prob.plan(sysm, pr, u, chunk=8)
+    t = plan.tune(trials=4)
+    flush(f"  tuning {t}")
+    assert t["bgrid"] in (128, 256, 512, 1024) or t["bgrid"] <= 512
+    assert t["fuse_dir"] in (0, 1) and batch % t["igroup"] == 0 and t["ms_per_iteration"] > 0
+    u.copy_(x0)
+    ret, it, rr, st = plan.solve(w.tol)
+    assert ret == capi.OK
+    for b in range(batch):
+        assert abs(it[b] - it_e[b]) <= 2 and rr[b] <= w.tol
+        assert np.linalg.norm(u[b].cpu().numpy() - u_e[b]) <= 1e-6 * np.linalg.norm(u_e[b])
+    plan.close()
