@@ -14,7 +14,10 @@ preconditioner of Alg. 3 (s = AMG(0; K, r, r1, r2)):
 
 The paper analyses Gauss-Seidel relaxation but leaves the smoother of its
 experiments open; damped Jacobi keeps the cycle symmetric, so it is a valid
-CG preconditioner.
+CG preconditioner.  ``smoother="sgs"`` uses Gauss-Seidel instead, forward
+sweeps before and backward sweeps after the coarse correction in one fixed
+(multicolour) order, which keeps the cycle symmetric as well (in the FP32
+mode its sweeps round their result to binary32 after each sweep only).
 
 ``precision="fp32"`` emulates an FP32 preconditioner: K, D^{-1}, P and the
 residual scaled by ``scale`` are rounded to binary32 and every cycle step
@@ -44,6 +47,43 @@ def jacobi_sweeps(K, dinv, b, x, omega, nsweeps):
     return x
 
 
+def multicolor_order(dim, N):
+    """Free DOFs in multicolour order on the node grid (the Gauss-Seidel
+    relaxation of Sec. 2.2 run colour by colour): node (i, j[, l]) has colour
+    (i mod 2) + 2 (j mod 2) [+ 4 (l mod 2)]; colours in increasing order,
+    nodes by id within a colour, components in order.  Two nodes of one
+    colour differ by an even, non-zero step in some coordinate, so they share
+    no element and no matrix entry."""
+    from .fem import free_dofs
+    fd = free_dofs(dim, N)
+    nodes = fd[::dim] // dim                  # free nodes in rank order
+    i = nodes % (N + 1)
+    j = (nodes // (N + 1)) % (N + 1)
+    colour = (i % 2) + 2 * (j % 2)
+    if dim == 3:
+        colour = colour + 4 * ((nodes // (N + 1) ** 2) % 2)
+    ranks = np.argsort(colour, kind="stable")
+    return (dim * ranks[:, None] + np.arange(dim)[None, :]).reshape(-1)
+
+
+def gauss_seidel_sweeps(K, b, x, order, nsweeps, backward=False):
+    """nsweeps Gauss-Seidel sweeps visiting the unknowns in `order` (reversed
+    for backward sweeps): each x_i in turn takes the value that zeroes
+    residual i given the current x.  One sweep is x <- x + T^{-1} (b - K x)
+    with T the lower (backward: upper) triangle, diagonal included, of K in
+    that order."""
+    K = sp.csr_matrix(K)
+    Kp = K[order][:, order].tocsr()
+    T = sp.tril(Kp, format="csr") if not backward else sp.triu(Kp, format="csr")
+    from scipy.sparse.linalg import spsolve_triangular
+    x = np.array(x, copy=True)
+    for _ in range(nsweeps):
+        rp = (b - K @ x)[order]
+        dx = spsolve_triangular(T, rp, lower=not backward)
+        x[order] = x[order] + dx
+    return x
+
+
 def coarse_matrix(K, P):
     """K_c = P^T K P (Alg. 2, restrict-and-solve step; Sec. 3.3 Eq. 28)."""
     return P.T @ (K @ P)
@@ -67,7 +107,12 @@ def coarse_solve(L, rc):
 class TwoGrid:
     """The POD two-grid cycle with fixed K, D^{-1}, P and smoother settings."""
 
-    def __init__(self, K, P, omega, nu_pre=2, nu_post=2, precision="fp64"):
+    def __init__(self, K, P, omega, nu_pre=2, nu_post=2, precision="fp64", smoother="jacobi",
+                 order=None):
+        self.smoother = smoother
+        self.order = order
+        if smoother == "sgs" and order is None:
+            raise ValueError("the symmetric Gauss-Seidel smoother needs the sweep order")
         self.K = sp.csr_matrix(K)
         self.dinv = 1.0 / self.K.diagonal()
         self.P = np.asarray(P, dtype=np.float64)
@@ -83,16 +128,25 @@ class TwoGrid:
             self.omega32 = np.float32(self.omega)
 
     # -- FP64 cycle ---------------------------------------------------------
+    def _relax(self, K, dinv, b, x, w, nsweeps, post):
+        if self.smoother == "sgs":
+            # symmetric: forward sweeps before, backward sweeps after the
+            # coarse correction
+            y = gauss_seidel_sweeps(K, b.astype(np.float64), x.astype(np.float64), self.order,
+                                    nsweeps, backward=post)
+            return y.astype(x.dtype)
+        return jacobi_sweeps(K, dinv, b, x, w, nsweeps)
+
     def _cycle64(self, r):
         K, dinv, P, w = self.K, self.dinv, self.P, self.omega
         x = np.zeros_like(r)
-        x = jacobi_sweeps(K, dinv, r, x, w, self.nu_pre)
+        x = self._relax(K, dinv, r, x, w, self.nu_pre, False)
         if self.L is not None:
             rr = r - K @ x
             rc = P.T @ rr
             ec = coarse_solve(self.L, rc)
             x = x + P @ ec
-        x = jacobi_sweeps(K, dinv, r, x, w, self.nu_post)
+        x = self._relax(K, dinv, r, x, w, self.nu_post, True)
         return x
 
     # -- FP32-emulated cycle (coarse solve in FP64) --------------------------
@@ -100,13 +154,13 @@ class TwoGrid:
         K, dinv, P, w = self.K32, self.dinv32, self.P32, self.omega32
         b = (r * scale).astype(np.float32)
         x = np.zeros_like(b)
-        x = jacobi_sweeps(K, dinv, b, x, w, self.nu_pre).astype(np.float32)
+        x = self._relax(K, dinv, b, x, w, self.nu_pre, False).astype(np.float32)
         if self.L is not None:
             rr = (b - K @ x).astype(np.float32)
             rc = (P.T @ rr).astype(np.float32)
             ec = coarse_solve(self.L, rc.astype(np.float64)).astype(np.float32)
             x = (x + P @ ec).astype(np.float32)
-        x = jacobi_sweeps(K, dinv, b, x, w, self.nu_post).astype(np.float32)
+        x = self._relax(K, dinv, b, x, w, self.nu_post, True).astype(np.float32)
         return x.astype(np.float64) / scale
 
     def apply(self, r, scale=None):

@@ -145,3 +145,85 @@ def test_fp32_cycle_close_and_scale_exact():
     b = M32.apply(r, scale=2.0 ** -7)
     c = M32.apply(r, scale=2.0 ** 11)
     assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+# -- symmetric Gauss-Seidel in multicolour order --------------------------------
+def _gs_loop(Kd, b, x, order, backward):
+    """One Gauss-Seidel sweep written as the plain loop of its definition."""
+    x = x.copy()
+    seq = order[::-1] if backward else order
+    for i in seq:
+        x[i] += (b[i] - Kd[i] @ x) / Kd[i, i]
+    return x
+
+
+@pytest.mark.parametrize("dim,N", [(2, 3), (3, 2)])
+def test_gauss_seidel_sweep_is_the_sequential_update(dim, N):
+    w = I.small(dim, N)
+    K = problem.stiffness(w, I.query_xi(w, 0))
+    Kd = K.toarray()
+    order = twogrid.multicolor_order(dim, N)
+    assert sorted(order) == list(range(K.shape[0]))
+    rng = np.random.default_rng(1)
+    b, x = rng.standard_normal(K.shape[0]), rng.standard_normal(K.shape[0])
+    for back in (False, True):
+        np.testing.assert_allclose(twogrid.gauss_seidel_sweeps(K, b, x, order, 1, back),
+                                   _gs_loop(Kd, b, x, order, back), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("dim,N", [(2, 6), (3, 3)])
+def test_multicolour_nodes_of_one_colour_are_uncoupled(dim, N):
+    """A valid colouring: reversing the node order inside every colour leaves
+    a sweep unchanged (same-colour nodes share no matrix entry)."""
+    w = I.small(dim, N)
+    K = problem.stiffness(w, I.query_xi(w, 1))
+    order = twogrid.multicolor_order(dim, N)
+    nodes = order[::dim] // dim
+    from oracle.fem import free_dofs
+    fd = free_dofs(dim, N)
+    gnode = fd[::dim][nodes] // dim
+    col = (gnode % (N + 1)) % 2 + 2 * ((gnode // (N + 1)) % (N + 1) % 2)
+    if dim == 3:
+        col = col + 4 * ((gnode // (N + 1) ** 2) % 2)
+    assert np.all(np.diff(col) >= 0)
+    Kd = K.toarray()
+    for c in np.unique(col):
+        idx = np.concatenate([np.arange(dim * r, dim * r + dim) for r in nodes[col == c]])
+        blk = Kd[np.ix_(idx, idx)]
+        # only the nodes' own dim x dim blocks are non-zero
+        for a in range(len(idx) // dim):
+            blk[dim * a:dim * a + dim, dim * a:dim * a + dim] = 0.0
+        assert np.abs(blk).max() == 0.0
+    rev = np.concatenate([np.concatenate([np.arange(dim * r, dim * r + dim) for r in nodes[col == c][::-1]])
+                          for c in np.unique(col)])
+    rng = np.random.default_rng(2)
+    b, x = rng.standard_normal(K.shape[0]), rng.standard_normal(K.shape[0])
+    np.testing.assert_allclose(twogrid.gauss_seidel_sweeps(K, b, x, order, 2),
+                               twogrid.gauss_seidel_sweeps(K, b, x, rev, 2), rtol=1e-12, atol=1e-13)
+
+
+def test_sgs_cycle_symmetric_pd_and_error_operator():
+    """B symmetric positive definite with forward pre- and backward
+    post-sweeps; I - B K = S_b^{nu2} C S_f^{nu1} (Eqs. 21-22, 30 with
+    Gauss-Seidel relaxation); Gauss-Seidel contracts the energy norm."""
+    w = I.small(2, 5, k=4, n_train=8)
+    P, lam, U = problem.basis(w, I.train_xis(w))
+    K = problem.stiffness(w, I.query_xi(w, 0))
+    Kd = K.toarray()
+    n = Kd.shape[0]
+    order = twogrid.multicolor_order(2, 5)
+    M = twogrid.TwoGrid(K, P, w.omega, 2, 2, smoother="sgs", order=order)
+    B = np.stack([M(np.eye(n)[:, i]) for i in range(n)], axis=1)
+    np.testing.assert_allclose(B, B.T, atol=1e-12 * np.abs(B).max())
+    assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0
+    Pm = np.eye(n)[order]                    # row i of Pm selects unknown order[i]
+    Kp = Pm @ Kd @ Pm.T
+    Sf = np.eye(n) - Pm.T @ np.linalg.solve(np.tril(Kp), Pm @ Kd)
+    Sb = np.eye(n) - Pm.T @ np.linalg.solve(np.triu(Kp), Pm @ Kd)
+    C = np.eye(n) - P @ np.linalg.solve(P.T @ Kd @ P, P.T @ Kd)
+    E = Sb @ Sb @ C @ Sf @ Sf
+    np.testing.assert_allclose(np.eye(n) - B @ Kd, E, atol=1e-10)
+    rng = np.random.default_rng(3)
+    e = rng.standard_normal(n)
+    for S in (Sf, Sb):
+        assert (S @ e) @ Kd @ (S @ e) < e @ Kd @ e
