@@ -79,6 +79,12 @@ extern "C" {
 
 #define POD2G_MAX_K 64        /* largest coarse size k                       */
 
+#define POD2G_SMOOTHER_JACOBI 0  /* damped Jacobi, omega (default)            */
+#define POD2G_SMOOTHER_SGS    1  /* symmetric Gauss-Seidel: forward sweeps
+                                    before, backward sweeps after the coarse
+                                    correction, node colours (i mod 2) +
+                                    2 (j mod 2) [+ 4 (l mod 2)] in turn       */
+
 typedef struct pod2g_mesh {
   int dim;          /* 2 or 3 */
   int N;            /* elements per side, >= 1 */
@@ -119,6 +125,7 @@ typedef struct pod2g_prec {
   double *lam;          /* [batch] power-iteration estimate of lambda_max(D^-1 K) */
   int *status;          /* [batch] per-instance setup status (device) */
   void *work;           /* the setup workspace this handle lives in */
+  int smoother;         /* POD2G_SMOOTHER_*; pod2g_setup sets JACOBI */
 } pod2g_prec;
 
 const char *pod2g_strerror(int status);
@@ -159,6 +166,11 @@ int pod2g_setup(const pod2g_pattern *pat, const double *vals, const float *vals3
                 const double *dinv, const double *P, int k, double omega,
                 int nu_pre, int nu_post, int precision, int batch, int power_iters,
                 void *work, size_t bytes, pod2g_prec *out, hipStream_t stream);
+/* Selects the relaxation of the cycle (Sec. 2.2: the relaxation slot of
+ * Alg. 2; Gauss-Seidel is the paper's own form): POD2G_SMOOTHER_JACOBI or
+ * POD2G_SMOOTHER_SGS.  The Jacobi stability guard of pod2g_setup concerns
+ * damped Jacobi only.  Host-only.  Errors: EINVAL.                          */
+int pod2g_set_smoother(pod2g_prec *prec, int smoother);
 /* Redoes the setup of instance `slot` of an existing handle, in place, from
  * that instance's current vals / dinv (after the caller re-assembled it):
  * K P, K_c, L, Linv, status, lambda estimate and the FP32 D^-1.  The shared
@@ -360,6 +372,13 @@ int pod2g_spmv(const pod2g_pattern *pat, const double *vals, int batch,
 int pod2g_jacobi(const pod2g_pattern *pat, const double *vals, const double *dinv,
                  int batch, double omega, int nsweeps, const double *b, double *x,
                  double *tmp, hipStream_t stream);
+
+/* nsweeps Gauss-Seidel sweeps on K x = b in place on x (FP64), in the
+ * multicolour order of POD2G_SMOOTHER_SGS, forward or (backward != 0)
+ * reversed: the same kernels as the cycle's sweeps.  Asynchronous.          */
+int pod2g_gauss_seidel(const pod2g_pattern *pat, const double *vals, const double *dinv,
+                       int batch, int nsweeps, int backward, const double *b, double *x,
+                       hipStream_t stream);
 
 /* ---- offline POD (Sec. 3.3, steps 1-2) ----------------------------------
  * From N snapshots U ([N][n], one solution per row block), the Gram matrix

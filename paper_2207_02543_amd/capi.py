@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libpod2g.so")
 OK, EINVAL, ESIZE, EHIP, ENOTSPD, ESMOOTHER, EMAXIT, EBREAKDOWN, ENAN = 0, -1, -2, -3, -4, -5, -6, -7, -8
 TK_SPMV_PQ, TK_SWEEP, TK_SWEEP_FINAL, TK_RESTRICT, TK_PROLONG, TK_UPDATE = 1, 2, 3, 4, 5, 6
 FP64, MIXED = 0, 1
+SMOOTHER_JACOBI, SMOOTHER_SGS = 0, 1
 BETA_FR, BETA_PR = 0, 1
 MAX_K = 64
 
@@ -44,7 +45,7 @@ class Prec(C.Structure):
                 ("vals", C.c_void_p), ("vals32", C.c_void_p), ("dinv", C.c_void_p),
                 ("P", C.c_void_p), ("P32", C.c_void_p), ("dinv32", C.c_void_p),
                 ("KP", C.c_void_p), ("KP32", C.c_void_p), ("L", C.c_void_p), ("Linv", C.c_void_p), ("lam", C.c_void_p),
-                ("status", C.c_void_p), ("work", C.c_void_p)]
+                ("status", C.c_void_p), ("work", C.c_void_p), ("smoother", C.c_int)]
 
 
 class Tuning(C.Structure):
@@ -93,6 +94,8 @@ _f = {
     "pod2g_setup": _sig("pod2g_setup", _i, [_PP, _vp, _vp, _vp, _vp, _i, _d, _i, _i, _i, _i, _i,
                                             _vp, _sz, _PR, _vp]),
     "pod2g_setup_slot": _sig("pod2g_setup_slot", _i, [_PR, _i, _i, _vp]),
+    "pod2g_set_smoother": _sig("pod2g_set_smoother", _i, [_PR, _i]),
+    "pod2g_gauss_seidel": _sig("pod2g_gauss_seidel", _i, [_PP, _vp, _vp, _i, _i, _i, _vp, _vp, _vp]),
     "pod2g_server_create": _sig("pod2g_server_create", _i, [C.POINTER(Group), _i, _i,
                                                             C.POINTER(_vp), _vp]),
     "pod2g_server_admit": _sig("pod2g_server_admit", _i, [_vp, _i, _i, _d, _i, _i, _vp]),
@@ -198,6 +201,15 @@ def pod2g_setup(pat, vals, vals32, dinv, P, k, omega, nu_pre, nu_post, precision
 
 def pod2g_setup_slot(prec: Prec, slot: int, power_iters: int, stream=None) -> int:
     return _f["pod2g_setup_slot"](C.byref(prec), slot, power_iters, _stream(stream))
+
+
+def pod2g_set_smoother(prec: Prec, smoother: int) -> int:
+    return _f["pod2g_set_smoother"](C.byref(prec), smoother)
+
+
+def pod2g_gauss_seidel(pat, vals, dinv, batch, nsweeps, backward, b, x, stream=None) -> int:
+    return _f["pod2g_gauss_seidel"](C.byref(pat), _ptr(vals), _ptr(dinv), batch, nsweeps,
+                                    int(backward), _ptr(b), _ptr(x), _stream(stream))
 
 
 def pod2g_setup_status(prec: Prec, stream=None):

@@ -388,9 +388,17 @@ int pod2g_setup(const pod2g_pattern *pat, const double *vals, const float *vals3
   pr.dinv32 = precision == POD2G_MIXED ? (float *)(w + S.d32) : nullptr;
   pr.KP32 = want_kp32(pat->mesh.dim, k, precision) ? (float *)(w + S.kp32) : nullptr;
   pr.work = work;
+  pr.smoother = POD2G_SMOOTHER_JACOBI;
   int st = setup_run(pr, S, w, 0, batch, power_iters, true, stream);
   if (st) return st;
   *out = pr;
+  return POD2G_OK;
+}
+
+int pod2g_set_smoother(pod2g_prec *prec, int smoother) {
+  if (!prec || (smoother != POD2G_SMOOTHER_JACOBI && smoother != POD2G_SMOOTHER_SGS))
+    return POD2G_EINVAL;
+  prec->smoother = smoother;
   return POD2G_OK;
 }
 

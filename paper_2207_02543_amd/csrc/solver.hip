@@ -20,6 +20,7 @@ namespace pod2g {
 struct Ctx {
   int n, nn, k, batch, nb, ps;   // ps: partial stride per workgroup (doubles)
   int nbn;                       // workgroups of the node-wise kernels (one thread per node)
+  int N;                         // mesh elements per side
   int igroup;                    // instances per group in the node-wise block order (divides batch)
   int fuse_dir;                  // direction update folded into the outer SpMV
   int mixed;                     // FP32 cycle: its input is scaled by a power of two
@@ -870,6 +871,95 @@ __global__ void __launch_bounds__(NT) k_replace(Ctx c, const int *__restrict__ f
   }
 }
 
+// ---------------------------------------------------------------------------
+// Gauss-Seidel relaxation in multicolour node order (the relaxation of
+// Alg. 2 in the Gauss-Seidel form the paper analyses).  Node (i, j[, l]) has
+// colour (i mod 2) + 2 (j mod 2) [+ 4 (l mod 2)]; nodes of one colour share
+// no matrix entry, so one launch updates a colour, one thread per node,
+// its DIM unknowns in turn (reversed in backward sweeps) against the
+// current values of its own unknowns and its neighbours'.
+// ---------------------------------------------------------------------------
+struct Colour {
+  int i0, ni, j0, nj, l0, nl;   // first index and count per grid direction
+};
+
+// Free nodes: 2D i in [1, N] (x = 0 clamped), j in [0, N];
+// 3D i, j in [0, N], l in [1, N] (z = 0 clamped).
+static Colour colour_of(int dim, int N, int col) {
+  const int px = col & 1, py = (col >> 1) & 1, pz = (col >> 2) & 1;
+  auto span = [N](int lo) { return lo <= N ? (N - lo) / 2 + 1 : 0; };
+  Colour c;
+  if (dim == 2) {
+    c.i0 = px ? 1 : 2; c.ni = span(c.i0);
+    c.j0 = py;         c.nj = span(c.j0);
+    c.l0 = 0;          c.nl = 1;
+  } else {
+    c.i0 = px;         c.ni = span(c.i0);
+    c.j0 = py;         c.nj = span(c.j0);
+    c.l0 = pz ? 1 : 2; c.nl = span(c.l0);
+  }
+  return c;
+}
+
+template <int DIM, typename T, bool BACK>
+__global__ void __launch_bounds__(NT) k_gs_colour(Ctx c, const T *__restrict__ rhs_in,
+                                                  T *__restrict__ x, Colour col) {
+  constexpr int S = Stencil<DIM>::S, SC = S / 2;   // SC: the node's own block
+  const int b = blockIdx.y;
+  if (c.st && c.st[b].done) return;
+  const int t = blockIdx.x * NT + threadIdx.x;
+  if (t >= col.ni * col.nj * col.nl) return;
+  const int i = col.i0 + 2 * (t % col.ni);
+  const int rest = t / col.ni;
+  const int j = col.j0 + 2 * (rest % col.nj);
+  const int node = DIM == 2 ? j * c.N + (i - 1)
+                            : ((col.l0 + 2 * (rest / col.nj)) - 1) * (c.N + 1) * (c.N + 1) +
+                                  j * (c.N + 1) + i;
+  const size_t off = (size_t)b * c.n;
+  const T *vn = (const T *)c.svals + (size_t)b * c.vstride + (size_t)node * DIM;
+  T *xb = x + off;
+  T acc[DIM];
+#pragma unroll
+  for (int r = 0; r < DIM; ++r) acc[r] = T(0);
+#pragma unroll 9
+  for (int s = 0; s < S; ++s) {
+    if (s == SC) continue;
+    const int cn = c.colblk[s * c.nn + node];
+#pragma unroll
+    for (int bc = 0; bc < DIM; ++bc) {
+      const T xv = xb[(size_t)cn * DIM + bc];
+      const T *v = vn + (size_t)(s * DIM + bc) * c.n;
+#pragma unroll
+      for (int r = 0; r < DIM; ++r) acc[r] += v[r] * xv;
+    }
+  }
+  T xo[DIM], kc[DIM][DIM];
+#pragma unroll
+  for (int r = 0; r < DIM; ++r) xo[r] = xb[(size_t)node * DIM + r];
+#pragma unroll
+  for (int bc = 0; bc < DIM; ++bc)
+#pragma unroll
+    for (int r = 0; r < DIM; ++r) kc[r][bc] = vn[(size_t)(SC * DIM + bc) * c.n + r];
+  const T *rhs = (rhs_in ? rhs_in + off : cycle_rhs<T>(c, off)) + (size_t)node * DIM;
+  const T *dv = (const T *)c.sdinv + off + (size_t)node * DIM;
+#pragma unroll
+  for (int q = 0; q < DIM; ++q) {
+    const int r = BACK ? DIM - 1 - q : q;
+    T a = acc[r];
+#pragma unroll
+    for (int bc = 0; bc < DIM; ++bc) a += kc[r][bc] * xo[bc];
+    xo[r] += dv[r] * (rhs[r] - a);
+  }
+#pragma unroll
+  for (int r = 0; r < DIM; ++r) xb[(size_t)node * DIM + r] = xo[r];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(NT) k_zero(T *__restrict__ x, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * NT + threadIdx.x; i < count; i += (size_t)gridDim.x * NT)
+    x[i] = T(0);
+}
+
 // Served solves: a free slot is stopped and checked, so no kernel touches
 // it; an admitted one is stopped, unchecked and fresh, so the next gated
 // true-residual pass forms r0 = f - K x0 and ||f|| and starts it.
@@ -1014,6 +1104,7 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
   c.batch = batch;
   c.nb = ceil_div(n, NT);
   c.nbn = ceil_div(pat->n_nodes, NT);
+  c.N = pat->mesh.N;
   c.igroup = default_igroup(batch);
   c.fuse_dir = (long long)n * batch <= FUSE_DIR_MAX;
   c.ps = k > 2 ? k : 2;
@@ -1139,16 +1230,80 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
     hipLaunchKernelGGL((k_finalize<T>), grid, blk, 0, stream, c, have ? (const T *)cur : (const T *)nullptr, want_dot);
 }
 
+// nsweeps Gauss-Seidel sweeps in place on x: colours in turn (reversed
+// for backward sweeps).
+template <int DIM, typename T>
+static void gs_sweeps(const Ctx &c, const T *rhs, T *x, int nsweeps, bool backward,
+                      hipStream_t stream) {
+  constexpr int NC = 1 << DIM;
+  for (int sw = 0; sw < nsweeps; ++sw) {
+    for (int q = 0; q < NC; ++q) {
+      const Colour col = colour_of(DIM, c.N, backward ? NC - 1 - q : q);
+      const int cnt = col.ni * col.nj * col.nl;
+      if (cnt == 0) continue;
+      dim3 g(ceil_div(cnt, NT), c.batch);
+      if (backward) hipLaunchKernelGGL((k_gs_colour<DIM, T, true>), g, dim3(NT), 0, stream, c, rhs, x, col);
+      else hipLaunchKernelGGL((k_gs_colour<DIM, T, false>), g, dim3(NT), 0, stream, c, rhs, x, col);
+    }
+  }
+}
+
+// The cycle with symmetric Gauss-Seidel relaxation: nu_pre forward sweeps
+// from x = 0, restriction, coarse solve and prolongation as in the Jacobi
+// cycle, nu_post backward sweeps, then s = x / scale with r^T s.
+template <int DIM, typename T>
+static void launch_cycle_sgs(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, int want_dot) {
+  dim3 grid(c.nb, c.batch), gridn(c.nbn, c.batch), blk(NT);
+  T *x = (T *)c.xa, *y = (T *)c.xb;
+  const bool have = pr->nu_pre >= 1;
+  if (have) {
+    hipLaunchKernelGGL(k_zero<T>, dim3(2048), blk, 0, stream, x, (size_t)c.n * c.batch);
+    gs_sweeps<DIM, T>(c, nullptr, x, pr->nu_pre, false, stream);
+  }
+  T *cur = have ? x : nullptr;
+  if (c.k > 0) {
+    if (batched_products<T>(c)) {
+      if (have) {
+        hipLaunchKernelGGL(k_resid32<DIM>, gridn, blk, 0, stream, c, (const float *)x);
+        hipLaunchKernelGGL(k_ptr_b, dim3(c.bgrid), blk, sizeof(float) * c.k * PW_LD, stream, c,
+                           (const float *)c.rbuf);
+      } else {
+        hipLaunchKernelGGL(k_ptr_b, dim3(c.bgrid), blk, sizeof(float) * c.k * PW_LD, stream, c,
+                           (const float *)c.b32);
+      }
+      hipLaunchKernelGGL(k_ptr_sum, dim3(ceil_div((long long)c.k * c.batch * PTR_TPO, NT)), blk, 0,
+                         stream, c);
+      hipLaunchKernelGGL(k_prolong_b, dim3(c.nb), blk, 0, stream, c, (const float *)cur, (float *)y,
+                         (const float *)nullptr);
+    } else {
+      if (have) hipLaunchKernelGGL((k_restrict<DIM, T, false>), grid, blk, 0, stream, c, (const T *)x);
+      else hipLaunchKernelGGL((k_restrict<DIM, T, true>), grid, blk, 0, stream, c, (const T *)nullptr);
+      hipLaunchKernelGGL(k_prolong<T>, grid, blk, 0, stream, c, (const T *)cur, y);
+    }
+    cur = y;
+  } else if (!have) {
+    hipLaunchKernelGGL(k_zero<T>, dim3(2048), blk, 0, stream, x, (size_t)c.n * c.batch);
+    cur = x;
+  }
+  if (pr->nu_post >= 1) gs_sweeps<DIM, T>(c, nullptr, cur, pr->nu_post, true, stream);
+  hipLaunchKernelGGL((k_finalize<T>), grid, blk, 0, stream, c, (const T *)cur, want_dot);
+}
+
 template <int DIM>
 static void launch_cycle_any(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, int want_dot,
                              Tm *tm) {
+  if (pr->smoother == POD2G_SMOOTHER_SGS) {
+    if (pr->precision == POD2G_MIXED) launch_cycle_sgs<DIM, float>(c, pr, stream, want_dot);
+    else launch_cycle_sgs<DIM, double>(c, pr, stream, want_dot);
+    return;
+  }
   if (pr->precision == POD2G_MIXED) launch_cycle<DIM, float>(c, pr, stream, want_dot, tm);
   else launch_cycle<DIM, double>(c, pr, stream, want_dot, tm);
 }
 
 template <int DIM>
 static void launch_first(const Ctx &c, const pod2g_prec *pr, hipStream_t stream) {
-  const int wx = pr->nu_pre >= 1;
+  const int wx = pr->nu_pre >= 1 && pr->smoother == POD2G_SMOOTHER_JACOBI;
   dim3 grid(c.nb, c.batch);
   if (pr->precision == POD2G_MIXED) hipLaunchKernelGGL((k_cyc_first<float>), grid, dim3(NT), 0, stream, c, wx);
   else if (wx) hipLaunchKernelGGL((k_cyc_first<double>), grid, dim3(NT), 0, stream, c, wx);
@@ -1173,7 +1328,7 @@ static void launch_iteration(const Ctx &c, const pod2g_prec *pr, hipStream_t str
     launch(tm, POD2G_TK_SPMV_PQ, k_spmv_pq<DIM, false>, gridn, blk, 0, stream, c, sdir, pold, pnew);
   }
   if (pr) {
-    const int mode = pr->nu_pre >= 1 ? 1 : 2;
+    const int mode = pr->nu_pre >= 1 && pr->smoother == POD2G_SMOOTHER_JACOBI ? 1 : 2;
     if (pr->precision == POD2G_MIXED)
       launch(tm, POD2G_TK_UPDATE, k_update<float>, grid, blk, 0, stream, c, mode, (const double *)pnew);
     else
@@ -1908,6 +2063,30 @@ int pod2g_spmv(const pod2g_pattern *pat, const double *vals, int batch, const do
   else
     hipLaunchKernelGGL(k_spmv<3>, grid, dim3(NT), 0, stream, pat->n, pat->n_nodes, nb, pat->nvals,
                        pat->colblk, vals, x, y);
+  POD2G_HIP_CHECK(hipGetLastError());
+  return POD2G_OK;
+}
+
+int pod2g_gauss_seidel(const pod2g_pattern *pat, const double *vals, const double *dinv,
+                       int batch, int nsweeps, int backward, const double *b, double *x,
+                       hipStream_t stream) {
+  if (!pat || !vals || !dinv || !b || !x || batch < 1 || batch > 65535 || nsweeps < 0)
+    return POD2G_EINVAL;
+  Ctx c;
+  memset(&c, 0, sizeof(c));
+  c.n = pat->n;
+  c.nn = pat->n_nodes;
+  c.batch = batch;
+  c.nb = ceil_div(pat->n, NT);
+  c.nbn = ceil_div(pat->n_nodes, NT);
+  c.N = pat->mesh.N;
+  c.igroup = 1;
+  c.vstride = pat->nvals;
+  c.colblk = pat->colblk;
+  c.svals = vals;
+  c.sdinv = dinv;
+  if (pat->mesh.dim == 2) gs_sweeps<2, double>(c, b, x, nsweeps, backward != 0, stream);
+  else gs_sweeps<3, double>(c, b, x, nsweeps, backward != 0, stream);
   POD2G_HIP_CHECK(hipGetLastError());
   return POD2G_OK;
 }

@@ -92,7 +92,8 @@ class Problem:
 
     # -- preconditioner -----------------------------------------------------------
     def setup(self, sysm: System, P, k=None, precision=L.FP64, omega=None, nu_pre=None,
-              nu_post=None, power_iters=0, key="setup", stream=None) -> L.Prec:
+              nu_post=None, power_iters=0, key="setup", smoother=L.SMOOTHER_JACOBI,
+              stream=None) -> L.Prec:
         w = self.w
         k = (P.shape[0] if P is not None else 0) if k is None else k
         nb = L.pod2g_setup_bytes(self.pat, k, sysm.batch, precision)
@@ -104,6 +105,7 @@ class Problem:
                               w.nu_post if nu_post is None else nu_post,
                               precision, sysm.batch, power_iters, wk, nb, prec, stream),
                 "pod2g_setup")
+        L.check(L.pod2g_set_smoother(prec, smoother), "pod2g_set_smoother")
         prec._keepalive = (wk, P, sysm)
         return prec
 

@@ -41,7 +41,8 @@ def test_binding_loads_and_structs_match():
     assert C.sizeof(capi.Mesh) == 32
     assert C.sizeof(capi.Pattern) == 72
     assert capi.Prec.omega.offset == 96
-    assert C.sizeof(capi.Prec) == 96 + 8 + 13 * 8
+    assert C.sizeof(capi.Prec) == 96 + 8 + 13 * 8 + 8
+    assert capi.Prec.smoother.offset == 96 + 8 + 13 * 8
     assert C.sizeof(capi.SlotInfo) == 24 and C.sizeof(capi.Group) == 56
     assert C.sizeof(capi.Timer) == 40
     assert capi.strerror(capi.ENOTSPD).startswith("coarse matrix")
