@@ -216,6 +216,9 @@ def main(argv=None):
     ap.add_argument("--warm", default="noisy", choices=["noisy", "rom", "zero"],
                     help="initial guess: exact + 1%% noise (surrogate stand-in), the reduced-order "
                          "solution P K_c^-1 P^T f formed inside the step, or zero")
+    ap.add_argument("--smoother", default="jacobi", choices=["jacobi", "sgs"],
+                    help="relaxation of the cycle: damped Jacobi (the configurations') or "
+                         "symmetric Gauss-Seidel in multicolour order")
     ap.add_argument("--solver", default="pcg", choices=["pcg", "stationary"],
                     help="PCG preconditioned by the cycle, or the cycle iterated on its own")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
@@ -269,6 +272,7 @@ def main(argv=None):
     sysm = prob.alloc_system(w.batch, fp32=mixed)
     u = torch.empty(w.batch, w.n, dtype=torch.float64, device=dev)
     precision = L.MIXED if mixed else L.FP64
+    smoother = L.SMOOTHER_SGS if args.smoother == "sgs" else L.SMOOTHER_JACOBI
     timer = L.pod2g_timer_create(KERNELS[args.kernel], 6)
     stats = {"iters": [], "relres": [], "err": []}
     plan = None
@@ -277,7 +281,7 @@ def main(argv=None):
         # capture the PCG iterations once: every step reuses these buffers
         sysm.xi.copy_(xi_d[:w.batch])
         prob.assemble(sysm)
-        prec0 = prob.setup(sysm, P, precision=precision)
+        prec0 = prob.setup(sysm, P, precision=precision, smoother=smoother)
         plan = prob.plan(sysm, prec0, u, chunk=args.chunk, timer=timer)
         if not args.no_tune:
             tuning = plan.tune()
@@ -287,7 +291,7 @@ def main(argv=None):
         idx = [(i * w.batch + b) % Q for b in range(w.batch)]
         sysm.xi.copy_(xi_d[idx])
         prob.assemble(sysm)
-        prec = prob.setup(sysm, P, precision=precision)
+        prec = prob.setup(sysm, P, precision=precision, smoother=smoother)
         if args.warm == "noisy":
             u.copy_(x0[idx])
         elif args.warm == "rom":
@@ -350,7 +354,8 @@ def main(argv=None):
                    "precision": w.precision, "tol": w.tol, "omega": w.omega,
                    "sweeps": [w.nu_pre, w.nu_post], "queries": Q,
                    "graph_chunk": args.chunk if args.solver == "pcg" else 0,
-                   "warm_start": args.warm, "solver": args.solver, "tuning": tuning,
+                   "warm_start": args.warm, "solver": args.solver, "smoother": args.smoother,
+                   "tuning": tuning,
                    "iters_mean": float(np.mean(stats["iters"])),
                    "relres_max": float(np.max(stats["relres"])),
                    "err_vs_fp64_max": float(np.max(stats["err"]))},

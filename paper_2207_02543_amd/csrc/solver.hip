@@ -1252,7 +1252,8 @@ static void gs_sweeps(const Ctx &c, const T *rhs, T *x, int nsweeps, bool backwa
 // from x = 0, restriction, coarse solve and prolongation as in the Jacobi
 // cycle, nu_post backward sweeps, then s = x / scale with r^T s.
 template <int DIM, typename T>
-static void launch_cycle_sgs(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, int want_dot) {
+static void launch_cycle_sgs(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, int want_dot,
+                             Tm *tm) {
   dim3 grid(c.nb, c.batch), gridn(c.nbn, c.batch), blk(NT);
   T *x = (T *)c.xa, *y = (T *)c.xb;
   const bool have = pr->nu_pre >= 1;
@@ -1264,7 +1265,7 @@ static void launch_cycle_sgs(const Ctx &c, const pod2g_prec *pr, hipStream_t str
   if (c.k > 0) {
     if (batched_products<T>(c)) {
       if (have) {
-        hipLaunchKernelGGL(k_resid32<DIM>, gridn, blk, 0, stream, c, (const float *)x);
+        launch(tm, POD2G_TK_RESTRICT, k_resid32<DIM>, gridn, blk, 0, stream, c, (const float *)x);
         hipLaunchKernelGGL(k_ptr_b, dim3(c.bgrid), blk, sizeof(float) * c.k * PW_LD, stream, c,
                            (const float *)c.rbuf);
       } else {
@@ -1273,12 +1274,15 @@ static void launch_cycle_sgs(const Ctx &c, const pod2g_prec *pr, hipStream_t str
       }
       hipLaunchKernelGGL(k_ptr_sum, dim3(ceil_div((long long)c.k * c.batch * PTR_TPO, NT)), blk, 0,
                          stream, c);
-      hipLaunchKernelGGL(k_prolong_b, dim3(c.nb), blk, 0, stream, c, (const float *)cur, (float *)y,
-                         (const float *)nullptr);
+      launch(tm, POD2G_TK_PROLONG, k_prolong_b, dim3(c.nb), blk, 0, stream, c, (const float *)cur,
+             (float *)y, (const float *)nullptr);
     } else {
-      if (have) hipLaunchKernelGGL((k_restrict<DIM, T, false>), grid, blk, 0, stream, c, (const T *)x);
-      else hipLaunchKernelGGL((k_restrict<DIM, T, true>), grid, blk, 0, stream, c, (const T *)nullptr);
-      hipLaunchKernelGGL(k_prolong<T>, grid, blk, 0, stream, c, (const T *)cur, y);
+      if (have)
+        launch(tm, POD2G_TK_RESTRICT, k_restrict<DIM, T, false>, grid, blk, 0, stream, c, (const T *)x);
+      else
+        launch(tm, POD2G_TK_RESTRICT, k_restrict<DIM, T, true>, grid, blk, 0, stream, c,
+               (const T *)nullptr);
+      launch(tm, POD2G_TK_PROLONG, k_prolong<T>, grid, blk, 0, stream, c, (const T *)cur, y);
     }
     cur = y;
   } else if (!have) {
@@ -1293,8 +1297,8 @@ template <int DIM>
 static void launch_cycle_any(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, int want_dot,
                              Tm *tm) {
   if (pr->smoother == POD2G_SMOOTHER_SGS) {
-    if (pr->precision == POD2G_MIXED) launch_cycle_sgs<DIM, float>(c, pr, stream, want_dot);
-    else launch_cycle_sgs<DIM, double>(c, pr, stream, want_dot);
+    if (pr->precision == POD2G_MIXED) launch_cycle_sgs<DIM, float>(c, pr, stream, want_dot, tm);
+    else launch_cycle_sgs<DIM, double>(c, pr, stream, want_dot, tm);
     return;
   }
   if (pr->precision == POD2G_MIXED) launch_cycle<DIM, float>(c, pr, stream, want_dot, tm);
