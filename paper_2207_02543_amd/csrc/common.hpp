@@ -167,6 +167,29 @@ __device__ __forceinline__ double strided_sum(const double *part, int first, int
   return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
+// As strided_sum, but all loads of a share of up to WIDE partials are
+// issued before any is added (one trip to the memory side per WIDE
+// partials instead of per eight), then summed by a fixed pairwise tree.
+constexpr int WIDE = 48;
+__device__ __forceinline__ double strided_sum_wide(const double *part, int first, int m, int step,
+                                                   int stride) {
+  double total = 0.0;
+  for (int base = first; base < m; base += WIDE * step) {
+    double v[WIDE];
+#pragma unroll
+    for (int u = 0; u < WIDE; ++u) {
+      const int i = base + u * step;
+      v[u] = i < m ? part[(size_t)i * stride] : 0.0;
+    }
+#pragma unroll
+    for (int w = 1; w < WIDE; w <<= 1)
+#pragma unroll
+      for (int u = 0; u + w < WIDE; u += 2 * w) v[u] += v[u + w];
+    total += v[0];
+  }
+  return total;
+}
+
 __device__ __forceinline__ double reduce_partials(const double *part, int m, int stride,
                                                   double *lds) {
   return block_sum(strided_sum(part, threadIdx.x, m, NT, stride), lds);

@@ -289,12 +289,18 @@ __global__ void __launch_bounds__(NT) k_restrict(Ctx c, const T *__restrict__ x)
   __syncthreads();
   if (threadIdx.x < c.k) put_partial(slot(c, b, threadIdx.x) + blk, rc[threadIdx.x]);
   if (!arrive_last(site(c, b, CNT_C), blk, c.nb, &flag)) return;
+  const int k = c.k;
+  // the inverse factor into LDS (dynamic, k x k), its loads in flight with
+  // those of the partials
+  extern __shared__ double Ls[];
+  const double *Li = c.Linv + (size_t)b * k * k;
+  for (int t = threadIdx.x; t < k * k; t += NT) Ls[t] = Li[t];
   // r_c: tpc threads per column, each summing a strided share of the
   // column's partials, then the shares in order
-  const int k = c.k;
   const int tpc = NT / k;
   if (threadIdx.x < k * tpc)
-    rsh[threadIdx.x] = strided_sum(slot(c, b, threadIdx.x / tpc), threadIdx.x % tpc, c.nb, tpc, 1);
+    rsh[threadIdx.x] = strided_sum_wide(slot(c, b, threadIdx.x / tpc), threadIdx.x % tpc, c.nb,
+                                        tpc, 1);
   __syncthreads();
   if (threadIdx.x < k) {
     double v = 0.0;
@@ -303,11 +309,10 @@ __global__ void __launch_bounds__(NT) k_restrict(Ctx c, const T *__restrict__ x)
   }
   __syncthreads();
   // coarse solve L L^T e_c = r_c as e_c = Linv^T (Linv r_c)
-  const double *Li = c.Linv + (size_t)b * k * k;
   double y = 0.0;
   if (threadIdx.x < k) {
     const int i = threadIdx.x;
-    for (int j = 0; j <= i; ++j) y += Li[i * k + j] * rc[j];
+    for (int j = 0; j <= i; ++j) y += Ls[i * k + j] * rc[j];
   }
   __syncthreads();
   if (threadIdx.x < k) rsh[threadIdx.x] = y;
@@ -315,7 +320,7 @@ __global__ void __launch_bounds__(NT) k_restrict(Ctx c, const T *__restrict__ x)
   if (threadIdx.x < k) {
     const int i = threadIdx.x;
     double e = 0.0;
-    for (int j = i; j < k; ++j) e += Li[j * k + i] * rsh[j];
+    for (int j = i; j < k; ++j) e += Ls[j * k + i] * rsh[j];
     c.ec[(size_t)b * MAXK + i] = e;
   }
 }
@@ -621,7 +626,7 @@ __global__ void __launch_bounds__(NT) k_ptr_sum(Ctx c) {
   if (threadIdx.x < B) live[threadIdx.x] = !c.st[threadIdx.x].done;
   __syncthreads();
   double v = 0.0;
-  if (o < k * B) v = strided_sum(c.bpart + o, q, c.bgrid, PTR_TPO, k * B);
+  if (o < k * B) v = strided_sum_wide(c.bpart + o, q, c.bgrid, PTR_TPO, k * B);
 #pragma unroll
   for (int d = PTR_TPO / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, PTR_TPO);
   double *rc = c.bpart + (size_t)c.bgrid * k * B;   // k * B sums after the partials
@@ -1149,6 +1154,9 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
   }
 }
 
+// dynamic LDS of the restriction: the k x k inverse factor
+static unsigned lds_kk(const Ctx &c) { return (unsigned)(sizeof(double) * c.k * c.k); }
+
 template <typename T>
 static bool batched_products(const Ctx &c) {
   return sizeof(T) == 4 && c.batch >= BATCH_MFMA_MIN && c.batch <= MAXB;
@@ -1193,9 +1201,11 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
     if (rp) post_done = 1;
   } else if (c.k > 0) {
     if (have)
-      launch(tm, POD2G_TK_RESTRICT, k_restrict<DIM, T, false>, grid, blk, 0, stream, c, (const T *)cur);
+      launch(tm, POD2G_TK_RESTRICT, k_restrict<DIM, T, false>, grid, blk, lds_kk(c), stream, c,
+             (const T *)cur);
     else
-      launch(tm, POD2G_TK_RESTRICT, k_restrict<DIM, T, true>, grid, blk, 0, stream, c, (const T *)nullptr);
+      launch(tm, POD2G_TK_RESTRICT, k_restrict<DIM, T, true>, grid, blk, lds_kk(c), stream, c,
+             (const T *)nullptr);
     launch(tm, POD2G_TK_PROLONG, k_prolong<T>, grid, blk, 0, stream, c,
            have ? (const T *)cur : (const T *)nullptr, oth);
     T *t = cur; cur = oth; oth = t;
@@ -1278,9 +1288,10 @@ static void launch_cycle_sgs(const Ctx &c, const pod2g_prec *pr, hipStream_t str
              (float *)y, (const float *)nullptr);
     } else {
       if (have)
-        launch(tm, POD2G_TK_RESTRICT, k_restrict<DIM, T, false>, grid, blk, 0, stream, c, (const T *)x);
+        launch(tm, POD2G_TK_RESTRICT, k_restrict<DIM, T, false>, grid, blk, lds_kk(c), stream, c,
+               (const T *)x);
       else
-        launch(tm, POD2G_TK_RESTRICT, k_restrict<DIM, T, true>, grid, blk, 0, stream, c,
+        launch(tm, POD2G_TK_RESTRICT, k_restrict<DIM, T, true>, grid, blk, lds_kk(c), stream, c,
                (const T *)nullptr);
       launch(tm, POD2G_TK_PROLONG, k_prolong<T>, grid, blk, 0, stream, c, (const T *)cur, y);
     }
