@@ -60,8 +60,10 @@ def kernel_bytes(w, kernel, mixed):
             return idx + B * (4 * nvals + 12 * n)
         return idx + vb * k * n + B * (vb * nvals + 2 * vb * n)   # + P once
     if kernel == "prolong":
-        if batched and w.dim == 3:   # x + P e + omega D^-1 (r' - K P e): P once, K P per instance
-            return 4 * k * n + B * (4 * k * n + 16 * n)
+        # x + P e + omega D^-1 (r' - K P e) where K P is at hand (FP64 path,
+        # or FP32 in 3D): P once, K P per instance, x, r', D^-1 read, x written
+        if not mixed or w.dim == 3:
+            return vb * k * n + B * (vb * k * n + 4 * vb * n)
         return vb * k * n + B * 2 * vb * n
     if kernel == "update":       # u, p, r, q (, s) read; u, r written; cycle input and first sweep
         return B * (48 * n + (8 * n if mixed else 0) + (12 * n if mixed else 24 * n))

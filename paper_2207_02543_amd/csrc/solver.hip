@@ -32,6 +32,7 @@ struct Ctx {
   const void *sP;                // cycle P (FP64 or FP32)
   const double *Linv;            // [batch][k][k] inverse Cholesky factor
   const float *KP32;             // [batch][k][n] FP32 K P (batched FP32 cycle, 3D) or null
+  const double *KP;              // [batch][k][n] FP64 K P (setup) or null
   double omega;
   const double *f;               // [n]
   double *u, *r, *q, *s;         // [batch][n] FP64
@@ -235,7 +236,8 @@ __global__ void __launch_bounds__(NT) k_sweep(Ctx c, const T *__restrict__ xin, 
 // Residual after pre-relaxation and restriction: r' = b - K x,
 // r_c = P^T r'; the last block solves L L^T e_c = r_c (FP64).
 template <int DIM, typename T, bool XZERO>
-__global__ void __launch_bounds__(NT) k_restrict(Ctx c, const T *__restrict__ x) {
+__global__ void __launch_bounds__(NT) k_restrict(Ctx c, const T *__restrict__ x,
+                                                 T *__restrict__ rsave) {
   __shared__ double lds[2 * NWAVE];
   __shared__ double rsh[NT];
   __shared__ double rc[MAXK];
@@ -255,6 +257,7 @@ __global__ void __launch_bounds__(NT) k_restrict(Ctx c, const T *__restrict__ x)
       const T *vals = (const T *)c.svals + (size_t)b * c.vstride;
       rv = bv - row_dot<DIM>(c.colblk, vals, x + off, row, row / DIM, c.n, c.nn);
     }
+    if (rsave) rsave[off + row] = rv;   // r' for the first post-sweep (see k_prolong)
   }
   rsh[threadIdx.x] = (double)rv;
   __syncthreads();
@@ -345,9 +348,12 @@ __global__ void __launch_bounds__(NT) k_resid32(Ctx c, const float *__restrict__
   for (int r = 0; r < DIM; ++r) c.rbuf[r0 + r] = ((const float *)c.b32)[r0 + r] - kx[r];
 }
 
-// Prolongation and correction: x_out = x_in + P e_c.
+// Prolongation and correction: x_out = x_in + P e_c.  With rp (the
+// restricted residual r') and kp (the instance's K P) it also applies the
+// first post-relaxation sweep from b - K (x + P e_c) = r' - (K P) e_c.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_prolong(Ctx c, const T *__restrict__ xin, T *__restrict__ xout) {
+__global__ void __launch_bounds__(NT) k_prolong(Ctx c, const T *__restrict__ xin, T *__restrict__ xout,
+                                                const T *__restrict__ rp, const T *__restrict__ kp) {
   __shared__ T e[MAXK];
   const int b = inst_id();
   if (c.st[b].done) return;
@@ -359,6 +365,12 @@ __global__ void __launch_bounds__(NT) k_prolong(Ctx c, const T *__restrict__ xin
   const T *P = (const T *)c.sP;
   T acc = xin ? xin[off + row] : T(0);
   for (int j = 0; j < c.k; ++j) acc += P[(size_t)j * c.n + row] * e[j];
+  if (rp) {
+    const T *kpb = kp + (size_t)b * c.k * c.n + row;
+    T d = rp[off + row];
+    for (int j = 0; j < c.k; ++j) d -= kpb[(size_t)j * c.n] * e[j];
+    acc += (T)c.omega * ((const T *)c.sdinv)[off + row] * d;
+  }
   xout[off + row] = acc;
 }
 
@@ -716,9 +728,16 @@ __global__ void __launch_bounds__(NT) k_prolong_b(Ctx c, const float *__restrict
     const size_t off = (size_t)b * n;
     float xv = (xin ? xin[off + row] : 0.f) + Out[b][threadIdx.x];
     if (rp) {
+      // eight loads of K P in flight before their products
       const float *kp = c.KP32 + (size_t)b * k * n + row;
       float d = rp[off + row];
-      for (int j = 0; j < k; ++j) d -= kp[(size_t)j * n] * E[j][b];
+      for (int j0 = 0; j0 < k; j0 += 8) {
+        float kv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) kv[u] = j0 + u < k ? kp[(size_t)(j0 + u) * n] : 0.f;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) d -= kv[u] * E[j0 + u < MAXK ? j0 + u : 0][b];
+      }
       xv += (float)c.omega * ((const float *)c.sdinv)[off + row] * d;
     }
     xout[off + row] = xv;
@@ -1142,6 +1161,7 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
     c.omega = prec->omega;
     c.Linv = prec->Linv;
     c.KP32 = prec->KP32;
+    c.KP = prec->KP;
     if (precision == POD2G_MIXED) {
       c.svals = prec->vals32;
       c.sdinv = prec->dinv32;
@@ -1156,6 +1176,12 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
 
 // dynamic LDS of the restriction: the k x k inverse factor
 static unsigned lds_kk(const Ctx &c) { return (unsigned)(sizeof(double) * c.k * c.k); }
+
+// The cycle's right-hand side as the host sees it (FP64 r or FP32 b32).
+template <typename T>
+static const T *cycle_rhs_host(const Ctx &c) {
+  return sizeof(T) == 8 ? (const T *)c.r : (const T *)c.b32;
+}
 
 template <typename T>
 static bool batched_products(const Ctx &c) {
@@ -1200,16 +1226,27 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
     have = true;
     if (rp) post_done = 1;
   } else if (c.k > 0) {
+    // with K P at hand the first post-sweep comes from r' (saved by the
+    // restriction: q is free during the cycle, rbuf holds FP32)
+    const T *kp = sizeof(T) == 8 ? (const T *)c.KP : (const T *)c.KP32;
+    T *rsave = nullptr;
+    const T *rp = nullptr;
+    if (kp && pr->nu_post >= 1) {
+      rsave = sizeof(T) == 8 ? (T *)c.q : (T *)c.rbuf;
+      rp = have ? (const T *)rsave : cycle_rhs_host<T>(c);
+      if (!have) rsave = nullptr;
+    }
     if (have)
       launch(tm, POD2G_TK_RESTRICT, k_restrict<DIM, T, false>, grid, blk, lds_kk(c), stream, c,
-             (const T *)cur);
+             (const T *)cur, rsave);
     else
       launch(tm, POD2G_TK_RESTRICT, k_restrict<DIM, T, true>, grid, blk, lds_kk(c), stream, c,
-             (const T *)nullptr);
+             (const T *)nullptr, (T *)nullptr);
     launch(tm, POD2G_TK_PROLONG, k_prolong<T>, grid, blk, 0, stream, c,
-           have ? (const T *)cur : (const T *)nullptr, oth);
+           have ? (const T *)cur : (const T *)nullptr, oth, rp, rp ? kp : (const T *)nullptr);
     T *t = cur; cur = oth; oth = t;
     have = true;
+    if (rp) post_done = 1;
   }
   if (pr->nu_post >= 1 && !have) {
     // x = 0 so the first post sweep is omega D^-1 b: reuse the zero-input path
@@ -1289,11 +1326,12 @@ static void launch_cycle_sgs(const Ctx &c, const pod2g_prec *pr, hipStream_t str
     } else {
       if (have)
         launch(tm, POD2G_TK_RESTRICT, k_restrict<DIM, T, false>, grid, blk, lds_kk(c), stream, c,
-               (const T *)x);
+               (const T *)x, (T *)nullptr);
       else
         launch(tm, POD2G_TK_RESTRICT, k_restrict<DIM, T, true>, grid, blk, lds_kk(c), stream, c,
-               (const T *)nullptr);
-      launch(tm, POD2G_TK_PROLONG, k_prolong<T>, grid, blk, 0, stream, c, (const T *)cur, y);
+               (const T *)nullptr, (T *)nullptr);
+      launch(tm, POD2G_TK_PROLONG, k_prolong<T>, grid, blk, 0, stream, c, (const T *)cur, y,
+             (const T *)nullptr, (const T *)nullptr);
     }
     cur = y;
   } else if (!have) {
