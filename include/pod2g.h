@@ -353,6 +353,13 @@ int pod2g_server_create(const pod2g_group *groups, int n_groups, int chunk,
 int pod2g_server_admit(pod2g_server *srv, int group, int slot, double rtol, int maxit,
                        int beta, hipStream_t stream);
 int pod2g_serve_step(pod2g_server *srv, pod2g_slot_info *info_h, hipStream_t stream);
+/* The step of one group alone (its own graph) with the copy of that group's
+ * slot outcomes into its part of info_h: groups stepped on different streams
+ * advance at their own pace, so a small class is not held to the iteration
+ * rate of a large one.  A group must not be stepped on two streams at once.
+ * Asynchronous.                                                            */
+int pod2g_serve_step_group(pod2g_server *srv, int group, pod2g_slot_info *info_h,
+                           hipStream_t stream);
 int pod2g_server_slots(const pod2g_server *srv);   /* total slots, or EINVAL */
 int pod2g_server_destroy(pod2g_server *srv);
 

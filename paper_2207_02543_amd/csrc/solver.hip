@@ -1420,6 +1420,9 @@ struct pod2g_server {
     pod2g::Ctx c;
     pod2g_prec prec;
     int dim;
+    size_t info_off;          // first slot of the group in the info array
+    hipGraph_t graph;         // this group's step alone (pod2g_serve_step_group)
+    hipGraphExec_t exec;
   };
   std::vector<Group> groups;
   int chunk, slots;
@@ -1944,6 +1947,9 @@ int pod2g_server_create(const pod2g_group *groups, int n_groups, int chunk, pod2
     pod2g_server::Group gr;
     gr.prec = *G.prec;
     gr.dim = G.pat->mesh.dim;
+    gr.info_off = (size_t)sv->slots;
+    gr.graph = nullptr;
+    gr.exec = nullptr;
     fill_ctx(gr.c, G.pat, G.vals, batch, G.prec, G.f, G.u, G.work);
     sv->groups.push_back(gr);
     sv->slots += batch;
@@ -1981,6 +1987,16 @@ int pod2g_server_create(const pod2g_group *groups, int n_groups, int chunk, pod2
     ok = cap && ended;
   }
   if (ok && hipGraphInstantiate(&sv->exec, sv->graph, nullptr, nullptr, 0) != hipSuccess) ok = false;
+  // one graph per group as well, for groups stepped at their own pace
+  for (int g = 0; ok && g < G; ++g) {
+    ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+    if (!ok) break;
+    serve_group_step(sv->groups[g], chunk, cs);
+    ok = hipStreamEndCapture(cs, &sv->groups[g].graph) == hipSuccess;
+    if (ok && hipGraphInstantiate(&sv->groups[g].exec, sv->groups[g].graph, nullptr, nullptr, 0) !=
+                  hipSuccess)
+      ok = false;
+  }
   for (int g = 0; g < G; ++g) {
     if (done_ev[g]) (void)hipEventDestroy(done_ev[g]);
     if (bs[g]) (void)hipStreamDestroy(bs[g]);
@@ -1988,8 +2004,7 @@ int pod2g_server_create(const pod2g_group *groups, int n_groups, int chunk, pod2
   if (fork) (void)hipEventDestroy(fork);
   if (cs) (void)hipStreamDestroy(cs);
   if (!ok) {
-    if (sv->graph) (void)hipGraphDestroy(sv->graph);
-    delete sv;
+    pod2g_server_destroy(sv);
     return POD2G_EHIP;
   }
   *out = sv;
@@ -2020,10 +2035,24 @@ int pod2g_serve_step(pod2g_server *sv, pod2g_slot_info *info_h, hipStream_t stre
   return POD2G_OK;
 }
 
+int pod2g_serve_step_group(pod2g_server *sv, int group, pod2g_slot_info *info_h,
+                           hipStream_t stream) {
+  if (!sv || !info_h || group < 0 || group >= (int)sv->groups.size()) return POD2G_EINVAL;
+  const pod2g_server::Group &g = sv->groups[group];
+  POD2G_HIP_CHECK(hipGraphLaunch(g.exec, stream));
+  POD2G_HIP_CHECK(hipMemcpyAsync(info_h + g.info_off, g.c.info,
+                                 sizeof(pod2g_slot_info) * g.c.batch, hipMemcpyDeviceToHost, stream));
+  return POD2G_OK;
+}
+
 int pod2g_server_slots(const pod2g_server *sv) { return sv ? sv->slots : POD2G_EINVAL; }
 
 int pod2g_server_destroy(pod2g_server *sv) {
   if (!sv) return POD2G_EINVAL;
+  for (auto &g : sv->groups) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
   if (sv->exec) (void)hipGraphExecDestroy(sv->exec);
   if (sv->graph) (void)hipGraphDestroy(sv->graph);
   delete sv;

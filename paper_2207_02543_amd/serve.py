@@ -4,11 +4,12 @@ The multi-query setting of Sec. 3 (many parametrised solves K(theta) u = f
 with one offline basis per problem class) as a request loop.  Each problem
 class (mesh size, field terms, basis P) is one slot group of the library's
 server (``pod2g_server_*``): its slots hold one query each -- K(theta),
-D^-1, the coarse factor and the CG state stay resident on the device.  One
-step is one graph launch that advances every live slot of every class by
-a fixed number of PCG iterations (Alg. 3); requests that arrive while
-others run are admitted into free slots between steps, and finished slots
-are retired (result copied to the host) and reused.
+D^-1, the coarse factor and the CG state stay resident on the device.  A
+step is one graph launch that advances every live slot of a class (by
+default each class on its own stream, at its own pace; optionally all
+classes together) by a fixed number of PCG iterations (Alg. 3); requests
+that arrive while others run are admitted into free slots between steps,
+and finished slots are retired (result copied to the host) and reused.
 
 Every numerical step runs in the HIP library; this module only moves
 requests and results and keeps time.
@@ -111,6 +112,9 @@ class Server:
     def step(self, stream=None):
         L.check(L.pod2g_serve_step(self.handle, self.info, stream), "pod2g_serve_step")
 
+    def step_group(self, g: int, stream=None):
+        L.check(L.pod2g_serve_step_group(self.handle, g, self.info, stream), "pod2g_serve_step_group")
+
     def slot_info(self) -> np.ndarray:
         """The info copied by the last step (the caller synchronised)."""
         return np.frombuffer(self.info.numpy().tobytes(), dtype=SLOT_INFO)
@@ -169,12 +173,16 @@ class RunResult:
 
 
 def run_stream(server: Server, pools: list[Pool], times, cls, qidx, rtol, maxit=5000,
-               check_first=0, realtime=True) -> RunResult:
+               check_first=0, realtime=True, independent=True) -> RunResult:
     """Serve the request stream (arrival times in s from the start, class
     and pool index per request).  With realtime, requests become visible at
     their arrival times; otherwise all are queued at t = 0.  The results of
     the first `check_first` requests of every class are compared with u*
-    (relative error); every result is copied to the host."""
+    (relative error); every result is copied to the host.  independent:
+    every class is stepped on its own stream at its own pace (otherwise one
+    step advances all classes together)."""
+    if independent:
+        return _run_groups(server, pools, times, cls, qidx, rtol, maxit, check_first, realtime)
     classes = server.classes
     reqs = [Request(i, int(cls[i]), int(qidx[i]), float(times[i]) if realtime else 0.0)
             for i in range(len(times))]
@@ -248,6 +256,92 @@ def run_stream(server: Server, pools: list[Pool], times, cls, qidx, rtol, maxit=
         if pending:
             ev_ret = torch.cuda.Event()
             ev_ret.record()
+    res.wall = time.perf_counter() - t0
+    return res
+
+
+def _run_groups(server, pools, times, cls, qidx, rtol, maxit, check_first, realtime) -> RunResult:
+    """run_stream with one stream per class: a class is admitted, stepped
+    and retired whenever its previous step has finished."""
+    classes = server.classes
+    G = len(classes)
+    reqs = [Request(i, int(cls[i]), int(qidx[i]), float(times[i]) if realtime else 0.0)
+            for i in range(len(times))]
+    streams = [torch.cuda.Stream() for _ in range(G)]
+    free = [list(range(c.slots))[::-1] for c in classes]
+    live = [dict() for _ in range(G)]           # slot -> request
+    queues = [deque() for _ in range(G)]
+    inflight = [None] * G
+    copies = []                                 # (event, requests whose result is being copied)
+    checked = [0] * G
+    res = RunResult(reqs)
+    nxt = 0
+    t0 = time.perf_counter()
+    while True:
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and reqs[nxt].t_arrive <= now:
+            queues[reqs[nxt].ci].append(reqs[nxt])
+            nxt += 1
+        for g in range(G):
+            c = classes[g]
+            if inflight[g] is not None:
+                if not inflight[g].query():
+                    continue
+                inflight[g] = None
+                info = server.slot_info()[int(server.base[g]):int(server.base[g + 1])]
+                done = []
+                with torch.cuda.stream(streams[g]):
+                    for slot in list(live[g]):
+                        if info[slot]["done"]:
+                            r = live[g].pop(slot)
+                            c.out[slot].copy_(c.u[slot], non_blocking=True)
+                            r.iters, r.status = int(info[slot]["iter"]), int(info[slot]["status"])
+                            r.relres = float(info[slot]["relres"])
+                            free[g].append(slot)
+                            done.append(r)
+                    if done:
+                        ev = torch.cuda.Event()
+                        ev.record(streams[g])
+                        copies.append((ev, done))
+                res.occupancy.append((time.perf_counter() - t0,
+                                      [len(live[i]) for i in range(G)]))
+            with torch.cuda.stream(streams[g]):
+                while queues[g] and free[g]:
+                    r = queues[g].popleft()
+                    slot = free[g].pop()
+                    p = pools[g]
+                    server.admit(g, slot, p.xi[r.q], p.x0[r.q], rtol, maxit)
+                    r.slot, r.t_admit = slot, time.perf_counter() - t0
+                    live[g][slot] = r
+                if live[g]:
+                    server.step_group(g)
+                    ev = torch.cuda.Event()
+                    ev.record(streams[g])
+                    inflight[g] = ev
+                    res.steps += 1
+        for item in list(copies):
+            ev, done = item
+            if ev.query():
+                t = time.perf_counter() - t0
+                for r in done:
+                    r.t_done = t
+                    if checked[r.ci] < check_first:
+                        u = classes[r.ci].out[r.slot].numpy()
+                        us = pools[r.ci].u_star[r.q]
+                        r.err = float(np.linalg.norm(u - us) / np.linalg.norm(us))
+                        checked[r.ci] += 1
+                copies.remove(item)
+        busy = any(e is not None for e in inflight) or copies
+        if not busy:
+            if nxt >= len(reqs) and not any(queues):
+                break
+            if nxt < len(reqs):
+                delay = reqs[nxt].t_arrive - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(min(delay, 0.01))
+        else:
+            time.sleep(5e-5)
+    torch.cuda.synchronize()
     res.wall = time.perf_counter() - t0
     return res
 

@@ -113,7 +113,8 @@ def test_alone_equals_mix_equals_batched_solve(two_classes):
     srv.close()
 
 
-def test_stream_completes_every_request(two_classes):
+@pytest.mark.parametrize("independent", [True, False])
+def test_stream_completes_every_request(two_classes, independent):
     from paper_2207_02543_amd import capi, serve
     (w2, c2, P2, p2, q2), (w3, c3, P3, p3, q3) = two_classes
     srv = serve.Server([c2, c3], chunk=2)
@@ -121,9 +122,10 @@ def test_stream_completes_every_request(two_classes):
     times = np.zeros(n_req)
     cls = np.array([j % 2 for j in range(n_req)])
     qidx = np.array([(j // 2) % 4 for j in range(n_req)])
-    flush(f"serve: stream of {n_req} queued requests over {2 * SLOTS} slots")
+    flush(f"serve: stream of {n_req} queued requests over {2 * SLOTS} slots, "
+          f"{'one stream per class' if independent else 'classes stepped together'}")
     res = serve.run_stream(srv, [p2, p3], times, cls, qidx, rtol=1e-8, check_first=n_req,
-                           realtime=False)
+                           realtime=False, independent=independent)
     s = serve.summarize(res, ["2d", "3d"])
     flush(f"  {s['completed']} done in {res.steps} steps")
     assert s["completed"] == n_req and s["failed"] == 0
