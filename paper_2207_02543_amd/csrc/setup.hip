@@ -13,7 +13,7 @@ constexpr int KP_CH = 8;   // columns of K P per pass over K
 constexpr int KC_TR = 64;  // rows per LDS tile of the coarse-matrix kernel
 
 struct SetupLayout {
-  size_t status, lam, pst, arr, kp, L, Linv, kcpart, ppart, p32, d32, kp32, pw, total;
+  size_t status, lam, pst, arr, kp, L, Linv, kcpart, ppart, p32, d32, kp32, pt, pw, total;
   int nbk, rows_per_wg;
 };
 
@@ -24,6 +24,10 @@ static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 static bool want_kp32(int dim, int k, int precision) {
   return precision == POD2G_MIXED && dim == 3 && k > 0;
 }
+
+// columns of the node-major basis copy: k rounded up to whole passes of
+// K P, zero-padded, so a pass loads whole rows without bounds tests
+static int kp_pad(int k) { return (k + KP_CH - 1) / KP_CH * KP_CH; }
 
 static SetupLayout setup_layout(int n, int k, int batch, int precision, int dim) {
   SetupLayout S;
@@ -45,6 +49,7 @@ static SetupLayout setup_layout(int n, int k, int batch, int precision, int dim)
   S.p32 = o;    if (precision == POD2G_MIXED) o += align256(sizeof(float) * (size_t)k * n);
   S.d32 = o;    if (precision == POD2G_MIXED) o += align256(sizeof(float) * (size_t)batch * n);
   S.kp32 = o;   if (want_kp32(dim, k, precision)) o += align256(sizeof(float) * (size_t)batch * k * n);
+  S.pt = o;     o += align256(sizeof(double) * (size_t)kp_pad(k) * n);   // node-major copy of P
   S.pw = o;     o += 2 * align256(sizeof(double) * (size_t)batch * n);
   S.total = o;
   return S;
@@ -63,14 +68,31 @@ __global__ void k_setup_init(InstState *pst, Arrival *arr, int *status, double *
   lam[b] = 0.0;
 }
 
+// Node-major copy of the basis: Pt[node][j][d] = P[j][node dim + d] for
+// j < k and 0 up to kpad columns, so that the values K P needs at a
+// neighbour node are contiguous.
+template <int DIM>
+__global__ void __launch_bounds__(NT) k_pt(int n, int k, int kpad, const double *__restrict__ P,
+                                           double *__restrict__ Pt) {
+  const size_t total = (size_t)kpad * n;
+  for (size_t t = (size_t)blockIdx.x * NT + threadIdx.x; t < total; t += (size_t)gridDim.x * NT) {
+    const size_t node = t / ((size_t)kpad * DIM);
+    const int rem = (int)(t - node * kpad * DIM);
+    const int j = rem / DIM, d = rem % DIM;
+    Pt[t] = j < k ? P[(size_t)j * n + node * DIM + d] : 0.0;
+  }
+}
+
 // KP[:, j0 .. j0 + KP_CH) = K P[:, j0 ..] for one instance per grid row,
-// one thread per node (its DIM rows): per neighbour slot and component the
-// node's DIM values of K meet KP_CH gathered basis entries.
+// one thread per node (its DIM rows): per neighbour slot the KP_CH x DIM
+// basis entries of the neighbour node (contiguous in Pt) meet the node's
+// DIM x DIM block of K.  Each entry sums over slots and components in the
+// order of a row-wise product.
 template <int DIM>
 __global__ void __launch_bounds__(NT) k_kp(int n, int nn, int k, long long vstride,
                                            const int *__restrict__ colblk,
                                            const double *__restrict__ vals,
-                                           const double *__restrict__ P, double *__restrict__ KP) {
+                                           const double *__restrict__ Pt, double *__restrict__ KP) {
   const int b = blockIdx.y;
   const int node = xcd_block(blockIdx.x, gridDim.x) * NT + threadIdx.x;
   const int j0 = blockIdx.z * KP_CH;
@@ -82,22 +104,25 @@ __global__ void __launch_bounds__(NT) k_kp(int n, int nn, int k, long long vstri
 #pragma unroll
     for (int jj = 0; jj < KP_CH; ++jj) acc[r][jj] = 0.0;
   const int jn = k - j0 < KP_CH ? k - j0 : KP_CH;
+  const int kpad = (k + KP_CH - 1) / KP_CH * KP_CH;
+#pragma unroll 3
   for (int s = 0; s < Stencil<DIM>::S; ++s) {
     const int c = colblk[s * nn + node];
+    const double *pc = Pt + ((size_t)c * kpad + j0) * DIM;
+    double pv[KP_CH][DIM];
+#pragma unroll
+    for (int jj = 0; jj < KP_CH; ++jj)
+#pragma unroll
+      for (int bc = 0; bc < DIM; ++bc) pv[jj][bc] = pc[jj * DIM + bc];
 #pragma unroll
     for (int bc = 0; bc < DIM; ++bc) {
       double a[DIM];
 #pragma unroll
       for (int r = 0; r < DIM; ++r) a[r] = v[(size_t)(s * DIM + bc) * n + r];
-      const double *pc = P + (size_t)j0 * n + (size_t)c * DIM + bc;
 #pragma unroll
-      for (int jj = 0; jj < KP_CH; ++jj) {
-        if (jj < jn) {
-          const double pv = pc[(size_t)jj * n];
+      for (int jj = 0; jj < KP_CH; ++jj)
 #pragma unroll
-          for (int r = 0; r < DIM; ++r) acc[r][jj] += a[r] * pv;
-        }
-      }
+        for (int r = 0; r < DIM; ++r) acc[r][jj] += a[r] * pv[jj][bc];
     }
   }
   double *out = KP + (size_t)b * k * n + (size_t)node * DIM;
@@ -313,13 +338,20 @@ static int setup_run(const pod2g_prec &pr, const SetupLayout &S, char *w, int b0
   hipLaunchKernelGGL(k_setup_init, dim3(ceil_div(cnt, 64)), dim3(64), 0, stream, pst, arr, status, lam,
                      cnt, n);
   if (k > 0) {
+    double *Pt = (double *)(w + S.pt);
+    if (convert_p) {
+      if (dim == 2)
+        hipLaunchKernelGGL(k_pt<2>, dim3(2048), dim3(NT), 0, stream, n, k, kp_pad(k), pr.P, Pt);
+      else
+        hipLaunchKernelGGL(k_pt<3>, dim3(2048), dim3(NT), 0, stream, n, k, kp_pad(k), pr.P, Pt);
+    }
     dim3 gk(ceil_div(pat->n_nodes, NT), cnt, ceil_div(k, KP_CH));
     if (dim == 2)
       hipLaunchKernelGGL(k_kp<2>, gk, dim3(NT), 0, stream, n, pat->n_nodes, k, pat->nvals,
-                         pat->colblk, vals, pr.P, KP);
+                         pat->colblk, vals, (const double *)Pt, KP);
     else
       hipLaunchKernelGGL(k_kp<3>, gk, dim3(NT), 0, stream, n, pat->n_nodes, k, pat->nvals,
-                         pat->colblk, vals, pr.P, KP);
+                         pat->colblk, vals, (const double *)Pt, KP);
     hipLaunchKernelGGL(k_kc, dim3(S.nbk, cnt), dim3(NT), 0, stream, n, k, S.rows_per_wg, S.nbk,
                        pr.P, (const double *)KP, kcpart, L, Linv, status, arr);
     if (convert_p && pr.precision == POD2G_MIXED)
