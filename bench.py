@@ -170,7 +170,12 @@ def serve_bench(args):
                      realtime=False)
     times, cls, qidx = I.arrivals(args.rate, args.serve_seconds, len(ws), args.queries)
     log(f"[serve] {len(times)} requests over {args.serve_seconds:.0f} s at {args.rate:.0f}/s")
+    if args.markers:
+        L.check(L.pod2g_mark(0), "pod2g_mark")
     res = serve.run_stream(srv, pools, times, cls, qidx, rtol=1e-8, check_first=4)
+    if args.markers:
+        L.check(L.pod2g_mark(1), "pod2g_mark")
+        torch.cuda.synchronize()
     s = serve.summarize(res, names)
     srv.close()
     log(f"[serve] {s['completed']} solves in {s['wall_s']:.1f} s; p50 {s['p50_ms']:.1f} ms, "

@@ -90,14 +90,14 @@ CALIB_BYTES = 256 * 2 ** 20   # one calibration copy reads and writes this much
 
 
 def source_digest():
-    """Digest of the library sources (kernels and the C ABI header)."""
-    import glob
+    """Digest of the sources of the iteration kernels (the ones the
+    counters measure: solver.hip, the shared device helpers and the ABI
+    header); assembly, setup and POD sources do not enter it."""
     import hashlib
     import os
     here = os.path.dirname(os.path.abspath(__file__))
-    files = sorted(glob.glob(os.path.join(here, "csrc", "*.hip")) +
-                   glob.glob(os.path.join(here, "csrc", "*.hpp")))
-    files.append(os.path.join(os.path.dirname(here), "include", "pod2g.h"))
+    files = [os.path.join(here, "csrc", "solver.hip"), os.path.join(here, "csrc", "common.hpp"),
+             os.path.join(os.path.dirname(here), "include", "pod2g.h")]
     h = hashlib.sha256()
     for f in files:
         h.update(os.path.basename(f).encode())
@@ -118,7 +118,7 @@ def per_dispatch(path, pattern, counter):
     return (sum(v) / len(v), len(v)) if v else (float("nan"), 0)
 
 
-def run(workload, kernel, out, steps, extra):
+def run(workload, kernel, out, steps, extra, trace_only=False):
     """Profile bench.py on one workload (see the module docstring)."""
     import os
     import subprocess
@@ -141,6 +141,13 @@ def run(workload, kernel, out, steps, extra):
 
     pat = KERNEL_PATTERNS[kernel]
     t = prof(["--kernel-trace"], bench, "trace", 900)
+    if trace_only:
+        lines = [f"# rocprofv3 kernel trace: workload {workload}",
+                 "# commands (run from /tmp with TMPDIR=/tmp, PYTHONPATH=<repo>):"]
+        lines += [f"#   {c}" for c in cmds]
+        lines += ["", "## kernel trace of the timed region (between the markers)",
+                  trace_summary(os.path.join(t, "p_kernel_trace.csv"))]
+        return "\n".join(lines)
     f = prof(["--pmc", "FETCH_SIZE", "--kernel-include-regex", f"{pat}|k_mark"], bench, "fetch", 900)
     w = prof(["--pmc", "WRITE_SIZE", "--kernel-include-regex", f"{pat}|k_mark"], bench, "write", 900)
     cf = prof(["--pmc", "FETCH_SIZE"], calib_cmd, "calib_fetch", 120)
@@ -193,8 +200,9 @@ if __name__ == "__main__":
         ap.add_argument("--kernel", default="sweep")
         ap.add_argument("--out", required=True)
         ap.add_argument("--steps", type=int, default=2)
+        ap.add_argument("--trace-only", action="store_true")
         a, extra = ap.parse_known_args()
-        print(run(a.workload, a.kernel, a.out, a.steps, extra))
+        print(run(a.workload, a.kernel, a.out, a.steps, extra, a.trace_only))
     else:
         path = sys.argv[2]
         print(trace_summary(path) if kind == "trace" else counter_summary(path))
