@@ -357,20 +357,31 @@ __global__ void __launch_bounds__(NT) k_prolong(Ctx c, const T *__restrict__ xin
   __shared__ T e[MAXK];
   const int b = inst_id();
   if (c.st[b].done) return;
-  if (threadIdx.x < c.k) e[threadIdx.x] = (T)c.ec[(size_t)b * MAXK + threadIdx.x];
+  if (threadIdx.x < MAXK) e[threadIdx.x] = threadIdx.x < c.k ? (T)c.ec[(size_t)b * MAXK + threadIdx.x] : T(0);
   __syncthreads();
   const int row = blockIdx.x * NT + threadIdx.x;
   if (row >= c.n) return;
   const size_t off = (size_t)b * c.n;
   const T *P = (const T *)c.sP;
+  // eight basis (and K P) loads in flight before their products
   T acc = xin ? xin[off + row] : T(0);
-  for (int j = 0; j < c.k; ++j) acc += P[(size_t)j * c.n + row] * e[j];
-  if (rp) {
-    const T *kpb = kp + (size_t)b * c.k * c.n + row;
-    T d = rp[off + row];
-    for (int j = 0; j < c.k; ++j) d -= kpb[(size_t)j * c.n] * e[j];
-    acc += (T)c.omega * ((const T *)c.sdinv)[off + row] * d;
+  T d = rp ? rp[off + row] : T(0);
+  const T *kpb = rp ? kp + (size_t)b * c.k * c.n + row : nullptr;
+  for (int j0 = 0; j0 < c.k; j0 += 8) {
+    T pv[8], kv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      pv[u] = j0 + u < c.k ? P[(size_t)(j0 + u) * c.n + row] : T(0);
+      kv[u] = (kpb && j0 + u < c.k) ? kpb[(size_t)(j0 + u) * c.n] : T(0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const T eu = e[j0 + u < MAXK ? j0 + u : 0];
+      acc += pv[u] * eu;
+      d -= kv[u] * eu;
+    }
   }
+  if (rp) acc += (T)c.omega * ((const T *)c.sdinv)[off + row] * d;
   xout[off + row] = acc;
 }
 
@@ -562,9 +573,11 @@ __global__ void __launch_bounds__(NT) k_ptr_b(Ctx c, const float *__restrict__ R
   __shared__ int nlive;
   const int B = c.batch, k = c.k, n = c.n;
   const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+  if (threadIdx.x < B) live[threadIdx.x] = !c.st[threadIdx.x].done;
+  __syncthreads();
   if (threadIdx.x == 0) {
     int m = 0;
-    for (int b = 0; b < B; ++b) { live[b] = !c.st[b].done; m += live[b]; }
+    for (int b = 0; b < B; ++b) m += live[b];
     nlive = m;
   }
   __syncthreads();
@@ -580,9 +593,14 @@ __global__ void __launch_bounds__(NT) k_ptr_b(Ctx c, const float *__restrict__ R
   const float *P = (const float *)c.sP;
   for (int blk = g * per; blk < blk_end; ++blk) {
     const int row = blk * NT + w * WAVE + lane;
-    for (int b = 0; b < B; ++b)
-      Rw[w][b][lane] = (live[b] && row < n) ? R[(size_t)b * n + row] : 0.f;
-    for (int j = 0; j < k; ++j) Pw[j * PW_LD + threadIdx.x] = row < n ? P[(size_t)j * n + row] : 0.f;
+    // every load of the block's residuals and basis rows issued before the
+    // LDS stores (fixed trip counts, guarded)
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b)
+      if (b < B) Rw[w][b][lane] = (live[b] && row < n) ? R[(size_t)b * n + row] : 0.f;
+#pragma unroll
+    for (int j = 0; j < MAXK; ++j)
+      if (j < k) Pw[j * PW_LD + threadIdx.x] = row < n ? P[(size_t)j * n + row] : 0.f;
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
@@ -630,37 +648,38 @@ __global__ void __launch_bounds__(NT) k_ptr_b(Ctx c, const float *__restrict__ R
 constexpr int PTR_TPO = 16;   // threads per output
 
 __global__ void __launch_bounds__(NT) k_ptr_sum(Ctx c) {
-  __shared__ int live[MAXB];
-  __shared__ int flag;
-  __shared__ double ys[MAXK * MAXB];
   const int B = c.batch, k = c.k;
   const int o = (blockIdx.x * NT + threadIdx.x) / PTR_TPO, q = threadIdx.x % PTR_TPO;
-  if (threadIdx.x < B) live[threadIdx.x] = !c.st[threadIdx.x].done;
-  __syncthreads();
   double v = 0.0;
   if (o < k * B) v = strided_sum_wide(c.bpart + o, q, c.bgrid, PTR_TPO, k * B);
 #pragma unroll
   for (int d = PTR_TPO / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, PTR_TPO);
   double *rc = c.bpart + (size_t)c.bgrid * k * B;   // k * B sums after the partials
-  if (q == 0 && o < k * B) put_partial(rc + o, v);
-  if (!arrive_last(site(c, 0, CNT_F), blockIdx.x, gridDim.x, &flag)) return;
-  for (int t = threadIdx.x; t < k * B; t += NT) {
-    const int b = t / k, i = t % k;
-    double y = 0.0;
-    if (live[b]) {
-      const double *Li = c.Linv + (size_t)b * k * k;
-      for (int j = 0; j <= i; ++j) y += Li[i * k + j] * rc[j * B + b];
-    }
-    ys[t] = y;
+  if (q == 0 && o < k * B) rc[o] = v;
+}
+
+// Coarse solves of the batched restriction, one workgroup per live
+// instance: its factor and its r_c in LDS, then e_c = Linv^T (Linv r_c).
+__global__ void __launch_bounds__(NT) k_coarse_b(Ctx c) {
+  __shared__ double Ls[MAXK * MAXK];
+  __shared__ double r[MAXK], y[MAXK];
+  const int b = blockIdx.x, B = c.batch, k = c.k, t = threadIdx.x;
+  if (c.st[b].done) return;
+  const double *Li = c.Linv + (size_t)b * k * k;
+  const double *rc = c.bpart + (size_t)c.bgrid * k * B;
+  for (int i = t; i < k * k; i += NT) Ls[i] = Li[i];
+  if (t < k) r[t] = rc[(size_t)t * B + b];
+  __syncthreads();
+  if (t < k) {
+    double v = 0.0;
+    for (int j = 0; j <= t; ++j) v += Ls[t * k + j] * r[j];
+    y[t] = v;
   }
   __syncthreads();
-  for (int t = threadIdx.x; t < k * B; t += NT) {
-    const int b = t / k, i = t % k;
-    if (!live[b]) continue;
-    const double *Li = c.Linv + (size_t)b * k * k;
+  if (t < k) {
     double e = 0.0;
-    for (int j = i; j < k; ++j) e += Li[j * k + i] * ys[b * k + j];
-    c.ec[(size_t)b * MAXK + i] = e;
+    for (int j = t; j < k; ++j) e += Ls[j * k + t] * y[j];
+    c.ec[(size_t)b * MAXK + t] = e;
   }
 }
 
@@ -680,12 +699,16 @@ __global__ void __launch_bounds__(NT) k_prolong_b(Ctx c, const float *__restrict
   __shared__ int nlive;
   const int B = c.batch, k = c.k, n = c.n;
   const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+  if (threadIdx.x < B) live[threadIdx.x] = !c.st[threadIdx.x].done;
+  __syncthreads();
   if (threadIdx.x == 0) {
     int m = 0;
-    for (int b = 0; b < B; ++b) { live[b] = !c.st[b].done; m += live[b]; }
+    for (int b = 0; b < B; ++b) m += live[b];
     nlive = m;
   }
-  for (int t = threadIdx.x; t < MAXK * MAXB; t += NT) {
+#pragma unroll
+  for (int u = 0; u < MAXK * MAXB / NT; ++u) {
+    const int t = threadIdx.x + u * NT;
     const int j = t / MAXB, b = t % MAXB;
     E[j][b] = (j < k && b < B) ? (float)c.ec[(size_t)b * MAXK + j] : 0.f;
   }
@@ -1217,6 +1240,7 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
     }
     hipLaunchKernelGGL(k_ptr_sum, dim3(ceil_div((long long)c.k * c.batch * PTR_TPO, NT)), blk, 0,
                        stream, c);
+    hipLaunchKernelGGL(k_coarse_b, dim3(c.batch), blk, 0, stream, c);
     // with K P at hand, the first post-sweep comes from the restricted residual
     const float *rp = nullptr;
     if (c.KP32 && pr->nu_post >= 1) rp = have ? (const float *)c.rbuf : (const float *)c.b32;
@@ -1321,6 +1345,7 @@ static void launch_cycle_sgs(const Ctx &c, const pod2g_prec *pr, hipStream_t str
       }
       hipLaunchKernelGGL(k_ptr_sum, dim3(ceil_div((long long)c.k * c.batch * PTR_TPO, NT)), blk, 0,
                          stream, c);
+      hipLaunchKernelGGL(k_coarse_b, dim3(c.batch), blk, 0, stream, c);
       launch(tm, POD2G_TK_PROLONG, k_prolong_b, dim3(c.nb), blk, 0, stream, c, (const float *)cur,
              (float *)y, (const float *)nullptr);
     } else {
