@@ -560,9 +560,8 @@ __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode, const double *__
 // with R the residuals r'_b (FP32, [batch][n]).  Every wave owns 64
 // consecutive rows of the workgroup's row range, stages them for all live
 // instances in LDS and accumulates all 16 x 16 output tiles on MFMA; the
-// waves' tiles are summed per workgroup; the last workgroup sums the
-// workgroups (FP64, fixed order) and applies each live instance's coarse
-// solve.
+// waves' tiles are summed per workgroup into one FP64 partial per output
+// (k_ptr_sum sums the workgroups, k_coarse_b applies the coarse solves).
 constexpr int PW_LD = NT + 1;     // padded LDS strides: no bank conflicts between
 constexpr int RW_LD = WAVE + 1;   // the 16 columns an MFMA operand reads at once
 
@@ -643,8 +642,7 @@ __global__ void __launch_bounds__(NT) k_ptr_b(Ctx c, const float *__restrict__ R
 }
 
 // r_c of every (j, b): the workgroup partials of k_ptr_b summed by 16 threads
-// per output (strided shares, then a fixed 16-lane tree); the last workgroup
-// applies each live instance's coarse solve e_c = Linv^T (Linv r_c).
+// per output (strided shares, then a fixed 16-lane tree).
 constexpr int PTR_TPO = 16;   // threads per output
 
 __global__ void __launch_bounds__(NT) k_ptr_sum(Ctx c) {
