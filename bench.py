@@ -259,7 +259,7 @@ def main(argv=None):
     # ---- offline phase and query inputs (untimed) -----------------------------
     prob = pipeline.Problem(w, dev)
     t0 = time.perf_counter()
-    P, lam, U, train_iters = pipeline.offline_basis(prob)
+    P, lam, U, train_iters = pipeline.offline_basis(prob, progress=lambda m: log(f"[bench] {m}"))
     torch.cuda.synchronize()
     log(f"[bench] offline: {w.n_train} training solves ({sum(train_iters)} iterations) + POD "
         f"in {time.perf_counter() - t0:.1f} s; lambda_k/lambda_1 = "

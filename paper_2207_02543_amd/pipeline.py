@@ -222,7 +222,7 @@ def pod_basis(U: torch.Tensor, k: int):
     return P, lam
 
 
-def offline_basis(prob: Problem, n_train=None, k=None, rtol=1e-12, chunk=32):
+def offline_basis(prob: Problem, n_train=None, k=None, rtol=1e-12, chunk=32, progress=None):
     """Offline phase (Sec. 3.4): training solves, then POD of the snapshots
     (Sec. 3.3).  The training solves are incremental: the first one uses
     the smoother-only cycle; every later group (doubling in size up to
@@ -249,6 +249,8 @@ def offline_basis(prob: Problem, n_train=None, k=None, rtol=1e-12, chunk=32):
         Ub, its = solve_batched(prob, xis[done:b], P_cur, rtol=rtol, chunk=chunk)
         U[done:b] = Ub
         iters += its
+        if progress is not None:
+            progress(f"training solves {done}..{b - 1}: {max(its)} iterations at most")
         done, size = b, min(chunk, 2 * size)
     P, lam = pod_basis(U, k)
     return P, lam, U, iters
