@@ -186,11 +186,23 @@ class Plan:
             pass
 
 
+def fp64_chunk(prob: Problem, k: int, cap: int = 32, share: float = 0.5) -> int:
+    """Instances of one FP64 solve batch that fit `share` of the free HBM:
+    per instance K and D^-1, K P and the solver vectors."""
+    free, _ = torch.cuda.mem_get_info(prob.device)
+    per = 8 * (prob.nvals + prob.n * (k + 12))
+    return int(max(1, min(cap, share * free // per)))
+
+
 def solve_batched(prob: Problem, xis: np.ndarray, P=None, k=0, rtol=1e-12, maxit=20000,
-                  chunk=32, u0=None):
+                  chunk=None, u0=None):
     """Tight solves at the given parameters (FP64 two-grid PCG with the
-    basis P, or the smoother-only cycle for k = 0).  Returns [len(xis), n]."""
+    basis P, or the smoother-only cycle for k = 0), `chunk` instances at a
+    time (default: as many as half the free HBM holds, at most 32).
+    Returns [len(xis), n]."""
     m = len(xis)
+    if chunk is None:
+        chunk = fp64_chunk(prob, P.shape[0] if P is not None else k)
     out = torch.empty(m, prob.n, dtype=torch.float64, device=prob.device)
     iters = []
     for a in range(0, m, chunk):
@@ -208,6 +220,10 @@ def solve_batched(prob: Problem, xis: np.ndarray, P=None, k=0, rtol=1e-12, maxit
             raise L.Pod2gError(ret, f"training solve {a}..{b}: statuses {st}")
         iters += it
         del sysm, prec
+    # the batch workspaces are sized for this call only: hand them back
+    for key in ("setup_train", "pcg_train"):
+        prob._work.pop(key, None)
+    torch.cuda.empty_cache()
     return out, iters
 
 
@@ -222,7 +238,7 @@ def pod_basis(U: torch.Tensor, k: int):
     return P, lam
 
 
-def offline_basis(prob: Problem, n_train=None, k=None, rtol=1e-12, chunk=32, progress=None):
+def offline_basis(prob: Problem, n_train=None, k=None, rtol=1e-12, chunk=None, progress=None):
     """Offline phase (Sec. 3.4): training solves, then POD of the snapshots
     (Sec. 3.3).  The training solves are incremental: the first one uses
     the smoother-only cycle; every later group (doubling in size up to
@@ -232,6 +248,8 @@ def offline_basis(prob: Problem, n_train=None, k=None, rtol=1e-12, chunk=32, pro
     k = w.k if k is None else k
     xis = np.stack([I.train_xi(w, i) for i in range(n_train)])
     U = torch.empty(n_train, prob.n, dtype=torch.float64, device=prob.device)
+    if chunk is None:
+        chunk = fp64_chunk(prob, k)
     iters = []
     done, size = 0, 1
     while done < n_train:
@@ -256,6 +274,6 @@ def offline_basis(prob: Problem, n_train=None, k=None, rtol=1e-12, chunk=32, pro
     return P, lam, U, iters
 
 
-def exact_solutions(prob: Problem, xis, P, rtol=1e-12, chunk=32):
+def exact_solutions(prob: Problem, xis, P, rtol=1e-12, chunk=None):
     u, it = solve_batched(prob, xis, P, rtol=rtol, chunk=chunk)
     return u
