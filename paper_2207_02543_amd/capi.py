@@ -49,7 +49,7 @@ class Prec(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("bgrid", C.c_int), ("fuse_dir", C.c_int), ("igroup", C.c_int),
+    _fields_ = [("bgrid", C.c_int), ("fuse_dir", C.c_int), ("igroup", C.c_int), ("xwin", C.c_int),
                 ("ms_per_iteration", C.c_float)]
 
 

@@ -21,6 +21,7 @@ struct Ctx {
   int n, nn, k, batch, nb, ps;   // ps: partial stride per workgroup (doubles)
   int nbn;                       // workgroups of the node-wise kernels (one thread per node)
   int N;                         // mesh elements per side
+  int xwin;                      // node-wise kernels stage x[block +- xwin nodes] in LDS (0: no)
   int igroup;                    // instances per group in the node-wise block order (divides batch)
   int fuse_dir;                  // direction update folded into the outer SpMV
   int mixed;                     // FP32 cycle: its input is scaled by a power of two
@@ -77,6 +78,23 @@ __device__ __forceinline__ NodeBlk node_block(const Ctx &c) {
 
 __device__ __forceinline__ Arrival *site(const Ctx &c, int b, int s) {
   return c.arr + (size_t)b * NSITE + s;
+}
+
+// Neighbourhood of a node block in LDS: rows of nodes [blk NT - xwin,
+// blk NT + NT + xwin) of x (clamped to the instance), loaded coalesced once
+// so that the block's gathers read LDS instead of cache lines of x.  In 2D
+// the neighbours of node m are m +- 1, m +- N, m +- N +- 1, so xwin = N + 1
+// covers them.  Returns the first staged row; every thread of the block
+// must call it (it synchronises).
+template <int DIM, typename T, typename XV>
+__device__ __forceinline__ long long stage_x(const Ctx &c, int blk, T *xs, XV xv) {
+  long long lo = (long long)blk * NT - c.xwin;
+  long long hi = (long long)blk * NT + NT + c.xwin;
+  lo = (lo < 0 ? 0 : lo) * DIM;
+  hi = (hi > c.nn ? c.nn : hi) * DIM;
+  for (long long i = lo + threadIdx.x; i < hi; i += NT) xs[i - lo] = xv((size_t)i);
+  __syncthreads();
+  return lo;
 }
 
 // Partial sums: slot j of instance b holds one value per workgroup,
@@ -194,12 +212,18 @@ __global__ void __launch_bounds__(NT) k_sweep(Ctx c, const T *__restrict__ xin, 
   if (st && st->done) return;
   const int node = blk * NT + threadIdx.x;
   const size_t off = (size_t)b * c.n;
+  const T *xb = xin + off;
+  extern __shared__ double xlds_dyn[];
+  T *xs = (T *)xlds_dyn;
+  const long long xlo = c.xwin ? stage_x<DIM, T>(c, blk, xs, [xb](size_t i) { return xb[i]; }) : 0;
   double rs = 0.0;
   if (node < c.nn) {
     const T *vals = (const T *)c.svals + (size_t)b * c.vstride;
-    const T *xb = xin + off;
     T kx[DIM];
-    node_dot<DIM>(c.colblk, vals, [xb](size_t i) { return xb[i]; }, node, c.n, c.nn, kx);
+    if (c.xwin)
+      node_dot<DIM>(c.colblk, vals, [xs, xlo](size_t i) { return xs[i - xlo]; }, node, c.n, c.nn, kx);
+    else
+      node_dot<DIM>(c.colblk, vals, [xb](size_t i) { return xb[i]; }, node, c.n, c.nn, kx);
     const size_t r0 = off + (size_t)node * DIM;
     const T *rhs = cycle_rhs<T>(c, off) + (size_t)node * DIM;
     const T *dv = (const T *)c.sdinv + r0;
@@ -337,12 +361,19 @@ __global__ void __launch_bounds__(NT) k_resid32(Ctx c, const float *__restrict__
   const int b = nbk.b;
   if (c.st[b].done) return;
   const int node = nbk.blk * NT + threadIdx.x;
-  if (node >= c.nn) return;
   const size_t off = (size_t)b * c.n;
-  const float *vals = (const float *)c.svals + (size_t)b * c.vstride;
   const float *xb = x + off;
+  extern __shared__ double xlds_dyn[];
+  float *xs = (float *)xlds_dyn;
+  const long long xlo =
+      c.xwin ? stage_x<DIM, float>(c, nbk.blk, xs, [xb](size_t i) { return xb[i]; }) : 0;
+  if (node >= c.nn) return;
+  const float *vals = (const float *)c.svals + (size_t)b * c.vstride;
   float kx[DIM];
-  node_dot<DIM>(c.colblk, vals, [xb](size_t i) { return xb[i]; }, node, c.n, c.nn, kx);
+  if (c.xwin)
+    node_dot<DIM>(c.colblk, vals, [xs, xlo](size_t i) { return xs[i - xlo]; }, node, c.n, c.nn, kx);
+  else
+    node_dot<DIM>(c.colblk, vals, [xb](size_t i) { return xb[i]; }, node, c.n, c.nn, kx);
   const size_t r0 = off + (size_t)node * DIM;
 #pragma unroll
   for (int r = 0; r < DIM; ++r) c.rbuf[r0 + r] = ((const float *)c.b32)[r0 + r] - kx[r];
@@ -438,14 +469,31 @@ __global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c, const double *__restrict_
   if (blk == 0 && threadIdx.x == 0) st->scale = cycle_scale(c, st->rr);
   const int node = blk * NT + threadIdx.x;
   const size_t off = (size_t)b * c.n;
+  const double *sb = s + off, *pb = pold + off;
+  double *pn = pnew + off;
+  // the direction p = s + beta p_old (or the p formed by k_pdir) around the
+  // block, in LDS when staged
+  extern __shared__ double xlds_dyn[];
+  double *xs = (double *)xlds_dyn;
+  long long xlo = 0;
+  if (c.xwin) {
+    if (FUSED) xlo = stage_x<DIM, double>(c, blk, xs, [sb, pb, beta](size_t i) { return pdir(sb[i], pb, i, beta); });
+    else xlo = stage_x<DIM, double>(c, blk, xs, [pn](size_t i) { return pn[i]; });
+  }
   double pq = 0.0;
   if (node < c.nn) {
     const double *vals = c.vals + (size_t)b * c.vstride;
-    const double *sb = s + off, *pb = pold + off;
-    double *pn = pnew + off;
     const size_t r0 = (size_t)node * DIM;
     double kp[DIM], pv[DIM];
-    if (FUSED) {
+    if (c.xwin) {
+      node_dot<DIM>(c.colblk, vals, [xs, xlo](size_t i) { return xs[i - xlo]; }, node, c.n, c.nn, kp);
+#pragma unroll
+      for (int r = 0; r < DIM; ++r) pv[r] = xs[r0 + r - xlo];
+      if (FUSED) {
+#pragma unroll
+        for (int r = 0; r < DIM; ++r) pn[r0 + r] = pv[r];
+      }
+    } else if (FUSED) {
       node_dot<DIM>(c.colblk, vals, [sb, pb, beta](size_t i) { return pdir(sb[i], pb, i, beta); },
                     node, c.n, c.nn, kp);
 #pragma unroll
@@ -867,12 +915,19 @@ __global__ void __launch_bounds__(NT) k_stat_resid(Ctx c) {
   if (st->done) return;
   const int node = blk * NT + threadIdx.x;
   const size_t off = (size_t)b * c.n;
+  const double *ub = c.u + off;
+  extern __shared__ double xlds_dyn[];
+  double *xs = (double *)xlds_dyn;
+  const long long xlo = c.xwin ? stage_x<DIM, double>(c, blk, xs, [ub](size_t i) { return ub[i]; }) : 0;
   double rr = 0.0;
   if (node < c.nn) {
-    const double *ub = c.u + off;
     double kx[DIM];
-    node_dot<DIM>(c.colblk, c.vals + (size_t)b * c.vstride, [ub](size_t i) { return ub[i]; }, node,
-                  c.n, c.nn, kx);
+    if (c.xwin)
+      node_dot<DIM>(c.colblk, c.vals + (size_t)b * c.vstride,
+                    [xs, xlo](size_t i) { return xs[i - xlo]; }, node, c.n, c.nn, kx);
+    else
+      node_dot<DIM>(c.colblk, c.vals + (size_t)b * c.vstride, [ub](size_t i) { return ub[i]; },
+                    node, c.n, c.nn, kx);
     const size_t r0 = (size_t)node * DIM;
 #pragma unroll
     for (int r = 0; r < DIM; ++r) {
@@ -1126,6 +1181,21 @@ static Layout layout(int n, int batch, int k, int precision) {
   return L;
 }
 
+// dynamic LDS of the node-wise kernels: the staged neighbourhood of x
+template <typename T>
+static unsigned xlds(const Ctx &c) {
+  return c.xwin ? (unsigned)(sizeof(T) * (size_t)(NT + 2 * c.xwin) * (c.n / c.nn)) : 0u;
+}
+
+// 2D: stage x around each node block in LDS when the window fits in 48 KB
+// at FP64; 3D neighbourhoods span two node planes, which do not fit.
+constexpr size_t XWIN_LDS_MAX = 48 * 1024;
+static int choose_xwin(const pod2g_pattern *pat) {
+  if (pat->mesh.dim != 2) return 0;
+  const int w = pat->mesh.N + 1;
+  return sizeof(double) * (size_t)(NT + 2 * w) * 2 <= XWIN_LDS_MAX ? w : 0;
+}
+
 // Instances per group of the node-wise block order: the largest divisor of
 // the batch that is at most IGROUP_MAX.
 constexpr int IGROUP_MAX = 1;
@@ -1150,6 +1220,7 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
   c.nb = ceil_div(n, NT);
   c.nbn = ceil_div(pat->n_nodes, NT);
   c.N = pat->mesh.N;
+  c.xwin = choose_xwin(pat);
   c.igroup = default_igroup(batch);
   c.fuse_dir = (long long)n * batch <= FUSE_DIR_MAX;
   c.ps = k > 2 ? k : 2;
@@ -1221,14 +1292,14 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
   const bool have_x = pr->nu_pre >= 1;
   int post_done = 0;   // post-relaxation sweeps already applied
   for (int i = 1; i < pr->nu_pre; ++i) {
-    launch(tm, POD2G_TK_SWEEP, k_sweep<DIM, T, false>, gridn, blk, 0, stream, c, (const T *)cur, oth, 0);
+    launch(tm, POD2G_TK_SWEEP, k_sweep<DIM, T, false>, gridn, blk, xlds<T>(c), stream, c, (const T *)cur, oth, 0);
     T *t = cur; cur = oth; oth = t;
   }
   bool have = have_x;
   if (c.k > 0 && batched_products<T>(c)) {
     // shared basis, many instances: one MFMA contraction over the batch
     if (have) {
-      launch(tm, POD2G_TK_RESTRICT, k_resid32<DIM>, gridn, blk, 0, stream, c, (const float *)cur);
+      launch(tm, POD2G_TK_RESTRICT, k_resid32<DIM>, gridn, blk, xlds<float>(c), stream, c, (const float *)cur);
       hipLaunchKernelGGL(k_ptr_b, dim3(c.bgrid), blk, sizeof(float) * c.k * PW_LD, stream, c,
                          (const float *)c.rbuf);
     } else {
@@ -1278,9 +1349,9 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
     for (int i = 1; i < pr->nu_post; ++i) {
       const bool fin = (i == pr->nu_post - 1);
       if (fin)
-        hipLaunchKernelGGL((k_sweep<DIM, T, true>), gridn, blk, 0, stream, c, cur, oth, want_dot);
+        hipLaunchKernelGGL((k_sweep<DIM, T, true>), gridn, blk, xlds<T>(c), stream, c, cur, oth, want_dot);
       else
-        hipLaunchKernelGGL((k_sweep<DIM, T, false>), gridn, blk, 0, stream, c, cur, oth, 0);
+        hipLaunchKernelGGL((k_sweep<DIM, T, false>), gridn, blk, xlds<T>(c), stream, c, cur, oth, 0);
       T *t = cur; cur = oth; oth = t;
     }
     if (pr->nu_post == 1) hipLaunchKernelGGL((k_finalize<T>), grid, blk, 0, stream, c, cur, want_dot);
@@ -1289,10 +1360,10 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
   for (int i = post_done; i < pr->nu_post; ++i) {
     const bool fin = (i == pr->nu_post - 1);
     if (fin)
-      launch(tm, POD2G_TK_SWEEP_FINAL, k_sweep<DIM, T, true>, gridn, blk, 0, stream, c, (const T *)cur, oth,
+      launch(tm, POD2G_TK_SWEEP_FINAL, k_sweep<DIM, T, true>, gridn, blk, xlds<T>(c), stream, c, (const T *)cur, oth,
              want_dot);
     else
-      launch(tm, POD2G_TK_SWEEP, k_sweep<DIM, T, false>, gridn, blk, 0, stream, c, (const T *)cur, oth, 0);
+      launch(tm, POD2G_TK_SWEEP, k_sweep<DIM, T, false>, gridn, blk, xlds<T>(c), stream, c, (const T *)cur, oth, 0);
     T *t = cur; cur = oth; oth = t;
   }
   if (pr->nu_post == post_done)
@@ -1334,7 +1405,7 @@ static void launch_cycle_sgs(const Ctx &c, const pod2g_prec *pr, hipStream_t str
   if (c.k > 0) {
     if (batched_products<T>(c)) {
       if (have) {
-        launch(tm, POD2G_TK_RESTRICT, k_resid32<DIM>, gridn, blk, 0, stream, c, (const float *)x);
+        launch(tm, POD2G_TK_RESTRICT, k_resid32<DIM>, gridn, blk, xlds<float>(c), stream, c, (const float *)x);
         hipLaunchKernelGGL(k_ptr_b, dim3(c.bgrid), blk, sizeof(float) * c.k * PW_LD, stream, c,
                            (const float *)c.rbuf);
       } else {
@@ -1398,10 +1469,10 @@ static void launch_iteration(const Ctx &c, const pod2g_prec *pr, hipStream_t str
   // SpMV; large ones are bandwidth-bound: a second gathered vector costs
   // more than one elementwise pass
   if (c.fuse_dir) {
-    launch(tm, POD2G_TK_SPMV_PQ, k_spmv_pq<DIM, true>, gridn, blk, 0, stream, c, sdir, pold, pnew);
+    launch(tm, POD2G_TK_SPMV_PQ, k_spmv_pq<DIM, true>, gridn, blk, xlds<double>(c), stream, c, sdir, pold, pnew);
   } else {
     hipLaunchKernelGGL(k_pdir, grid, blk, 0, stream, c, sdir, pold, pnew);
-    launch(tm, POD2G_TK_SPMV_PQ, k_spmv_pq<DIM, false>, gridn, blk, 0, stream, c, sdir, pold, pnew);
+    launch(tm, POD2G_TK_SPMV_PQ, k_spmv_pq<DIM, false>, gridn, blk, xlds<double>(c), stream, c, sdir, pold, pnew);
   }
   if (pr) {
     const int mode = pr->nu_pre >= 1 && pr->smoother == POD2G_SMOOTHER_JACOBI ? 1 : 2;
@@ -1554,7 +1625,7 @@ static int stat_run(Ctx &c, const pod2g_prec *pr, double rtol, int maxit, int *i
       launch_first<DIM>(c, pr, stream);
       launch_cycle_any<DIM>(c, pr, stream, 0, nullptr);
       hipLaunchKernelGGL(k_stat_update, grid, blk, 0, stream, c);
-      hipLaunchKernelGGL(k_stat_resid<DIM>, gridn, blk, 0, stream, c);
+      hipLaunchKernelGGL(k_stat_resid<DIM>, gridn, blk, xlds<double>(c), stream, c);
     }
     POD2G_HIP_CHECK(hipGetLastError());
     int st = read_states(c, h, stream);
@@ -1877,6 +1948,17 @@ int pcg_plan_tune(pod2g_plan *pl, int trials, pod2g_tuning *out, hipStream_t str
     if (ms < best) best = ms;
     else c.fuse_dir = keep;
   }
+  {
+    // the neighbourhood of each node block staged in LDS, or gathers from L2
+    const int keep = c.xwin;
+    c.xwin = keep ? 0 : choose_xwin(&pl->pat);
+    if (c.xwin != keep) {
+      float ms;
+      if ((st = measure(&ms))) return st;
+      if (ms < best) best = ms;
+      else c.xwin = keep;
+    }
+  }
   for (int g : {1, 2, 4, 8}) {
     if (g == c.igroup || c.batch % g) continue;
     const int keep = c.igroup;
@@ -1891,6 +1973,7 @@ int pcg_plan_tune(pod2g_plan *pl, int trials, pod2g_tuning *out, hipStream_t str
     out->bgrid = c.bgrid;
     out->fuse_dir = c.fuse_dir;
     out->igroup = c.igroup;
+    out->xwin = c.xwin;
     out->ms_per_iteration = best;
   }
   return POD2G_OK;
@@ -2208,6 +2291,8 @@ int pod2g_jacobi(const pod2g_pattern *pat, const double *vals, const double *din
   c.batch = batch;
   c.nb = ceil_div(pat->n, NT);
   c.nbn = ceil_div(pat->n_nodes, NT);
+  c.N = pat->mesh.N;
+  c.xwin = choose_xwin(pat);
   c.igroup = default_igroup(batch);
   c.vstride = pat->nvals;
   c.colblk = pat->colblk;
@@ -2219,9 +2304,9 @@ int pod2g_jacobi(const pod2g_pattern *pat, const double *vals, const double *din
   double *cur = x, *oth = tmp;
   for (int i = 0; i < nsweeps; ++i) {
     if (pat->mesh.dim == 2)
-      hipLaunchKernelGGL((k_sweep<2, double, false>), grid, dim3(NT), 0, stream, c, cur, oth, 0);
+      hipLaunchKernelGGL((k_sweep<2, double, false>), grid, dim3(NT), xlds<double>(c), stream, c, cur, oth, 0);
     else
-      hipLaunchKernelGGL((k_sweep<3, double, false>), grid, dim3(NT), 0, stream, c, cur, oth, 0);
+      hipLaunchKernelGGL((k_sweep<3, double, false>), grid, dim3(NT), xlds<double>(c), stream, c, cur, oth, 0);
     double *t = cur; cur = oth; oth = t;
   }
   if (cur != x)

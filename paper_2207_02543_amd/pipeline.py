@@ -171,7 +171,7 @@ class Plan:
         """Pick the launch parameters by timing (overwrites u: call before
         loading the initial guess)."""
         t = L.pcg_plan_tune(self.handle, trials, stream)
-        return {"bgrid": t.bgrid, "fuse_dir": t.fuse_dir, "igroup": t.igroup,
+        return {"bgrid": t.bgrid, "fuse_dir": t.fuse_dir, "igroup": t.igroup, "xwin": t.xwin,
                 "ms_per_iteration": t.ms_per_iteration}
 
     def close(self):
