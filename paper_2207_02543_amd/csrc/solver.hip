@@ -209,7 +209,9 @@ __global__ void __launch_bounds__(NT) k_sweep(Ctx c, const T *__restrict__ xin, 
   const NodeBlk nbk = node_block(c);
   const int b = nbk.b, blk = nbk.blk;
   InstState *st = c.st ? c.st + b : nullptr;   // null: standalone sweeps
-  if (st && st->done) return;
+  // a finished instance is skipped at its first store: its state load is
+  // in flight with the gathers instead of ahead of them
+  const int done = st ? st->done : 0;
   const int node = blk * NT + threadIdx.x;
   const size_t off = (size_t)b * c.n;
   const T *xb = xin + off;
@@ -227,6 +229,7 @@ __global__ void __launch_bounds__(NT) k_sweep(Ctx c, const T *__restrict__ xin, 
     const size_t r0 = off + (size_t)node * DIM;
     const T *rhs = cycle_rhs<T>(c, off) + (size_t)node * DIM;
     const T *dv = (const T *)c.sdinv + r0;
+    if (done) return;
 #pragma unroll
     for (int r = 0; r < DIM; ++r) {
       const T xv = xin[r0 + r] + (T)c.omega * dv[r] * (rhs[r] - kx[r]);
@@ -239,7 +242,7 @@ __global__ void __launch_bounds__(NT) k_sweep(Ctx c, const T *__restrict__ xin, 
       }
     }
   }
-  if (!FINAL || !want_dot) return;
+  if (!FINAL || !want_dot || done) return;
   double dummy = 0.0;
   block_sum2(rs, dummy, lds);
   if (threadIdx.x == 0) put_partial(slot(c, b, 0) + blk, rs);
@@ -268,7 +271,7 @@ __global__ void __launch_bounds__(NT) k_restrict(Ctx c, const T *__restrict__ x,
   __shared__ int flag;
   const int b = inst_id();
   InstState *st = c.st + b;
-  if (st->done) return;
+  const int done = st->done;   // checked at the first store (see k_sweep)
   const int blk = xcd_block(blockIdx.x, c.nb);
   const int row = blk * NT + threadIdx.x;
   const size_t off = (size_t)b * c.n;
@@ -281,8 +284,9 @@ __global__ void __launch_bounds__(NT) k_restrict(Ctx c, const T *__restrict__ x,
       const T *vals = (const T *)c.svals + (size_t)b * c.vstride;
       rv = bv - row_dot<DIM>(c.colblk, vals, x + off, row, row / DIM, c.n, c.nn);
     }
-    if (rsave) rsave[off + row] = rv;   // r' for the first post-sweep (see k_prolong)
   }
+  if (done) return;
+  if (row < c.n && rsave) rsave[off + row] = rv;   // r' for the first post-sweep (see k_prolong)
   rsh[threadIdx.x] = (double)rv;
   __syncthreads();
   // wave w reduces columns j = w, w + 4, ...; lane l covers rows l + 64 m
@@ -385,33 +389,32 @@ __global__ void __launch_bounds__(NT) k_resid32(Ctx c, const float *__restrict__
 template <typename T>
 __global__ void __launch_bounds__(NT) k_prolong(Ctx c, const T *__restrict__ xin, T *__restrict__ xout,
                                                 const T *__restrict__ rp, const T *__restrict__ kp) {
-  __shared__ T e[MAXK];
+  constexpr int PC = 16;   // basis (and K P) loads in flight together
   const int b = inst_id();
-  if (c.st[b].done) return;
-  if (threadIdx.x < MAXK) e[threadIdx.x] = threadIdx.x < c.k ? (T)c.ec[(size_t)b * MAXK + threadIdx.x] : T(0);
-  __syncthreads();
+  const int done = c.st[b].done;   // checked at the store (see k_sweep)
   const int row = blockIdx.x * NT + threadIdx.x;
   if (row >= c.n) return;
   const size_t off = (size_t)b * c.n;
   const T *P = (const T *)c.sP;
-  // eight basis (and K P) loads in flight before their products
+  const double *ec = c.ec + (size_t)b * MAXK;   // the same for every lane
   T acc = xin ? xin[off + row] : T(0);
   T d = rp ? rp[off + row] : T(0);
   const T *kpb = rp ? kp + (size_t)b * c.k * c.n + row : nullptr;
-  for (int j0 = 0; j0 < c.k; j0 += 8) {
-    T pv[8], kv[8];
+  for (int j0 = 0; j0 < c.k; j0 += PC) {
+    T pv[PC], kv[PC];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < PC; ++u) {
       pv[u] = j0 + u < c.k ? P[(size_t)(j0 + u) * c.n + row] : T(0);
       kv[u] = (kpb && j0 + u < c.k) ? kpb[(size_t)(j0 + u) * c.n] : T(0);
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const T eu = e[j0 + u < MAXK ? j0 + u : 0];
+    for (int u = 0; u < PC; ++u) {
+      const T eu = j0 + u < c.k ? (T)ec[j0 + u] : T(0);
       acc += pv[u] * eu;
       d -= kv[u] * eu;
     }
   }
+  if (done) return;
   if (rp) acc += (T)c.omega * ((const T *)c.sdinv)[off + row] * d;
   xout[off + row] = acc;
 }
@@ -464,9 +467,9 @@ __global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c, const double *__restrict_
   const NodeBlk nbk = node_block(c);
   const int b = nbk.b, blk = nbk.blk;
   InstState *st = c.st + b;
-  if (st->done || st->pending) return;
+  // finished or pending instances are skipped at the first store (see k_sweep)
+  const int skip = st->done | st->pending;
   const double beta = st->beta;
-  if (blk == 0 && threadIdx.x == 0) st->scale = cycle_scale(c, st->rr);
   const int node = blk * NT + threadIdx.x;
   const size_t off = (size_t)b * c.n;
   const double *sb = s + off, *pb = pold + off;
@@ -481,33 +484,31 @@ __global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c, const double *__restrict_
     else xlo = stage_x<DIM, double>(c, blk, xs, [pn](size_t i) { return pn[i]; });
   }
   double pq = 0.0;
+  const size_t r0 = (size_t)node * DIM;
+  double kp[DIM], pv[DIM];
   if (node < c.nn) {
     const double *vals = c.vals + (size_t)b * c.vstride;
-    const size_t r0 = (size_t)node * DIM;
-    double kp[DIM], pv[DIM];
     if (c.xwin) {
       node_dot<DIM>(c.colblk, vals, [xs, xlo](size_t i) { return xs[i - xlo]; }, node, c.n, c.nn, kp);
 #pragma unroll
       for (int r = 0; r < DIM; ++r) pv[r] = xs[r0 + r - xlo];
-      if (FUSED) {
-#pragma unroll
-        for (int r = 0; r < DIM; ++r) pn[r0 + r] = pv[r];
-      }
     } else if (FUSED) {
       node_dot<DIM>(c.colblk, vals, [sb, pb, beta](size_t i) { return pdir(sb[i], pb, i, beta); },
                     node, c.n, c.nn, kp);
 #pragma unroll
-      for (int r = 0; r < DIM; ++r) {
-        pv[r] = pdir(sb[r0 + r], pb, r0 + r, beta);
-        pn[r0 + r] = pv[r];
-      }
+      for (int r = 0; r < DIM; ++r) pv[r] = pdir(sb[r0 + r], pb, r0 + r, beta);
     } else {
       node_dot<DIM>(c.colblk, vals, [pn](size_t i) { return pn[i]; }, node, c.n, c.nn, kp);
 #pragma unroll
       for (int r = 0; r < DIM; ++r) pv[r] = pn[r0 + r];
     }
+  }
+  if (skip) return;
+  if (blk == 0 && threadIdx.x == 0) st->scale = cycle_scale(c, st->rr);
+  if (node < c.nn) {
 #pragma unroll
     for (int r = 0; r < DIM; ++r) {
+      if (FUSED) pn[r0 + r] = pv[r];
       c.q[off + r0 + r] = kp[r];
       pq += pv[r] * kp[r];
     }
@@ -552,7 +553,7 @@ __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode, const double *__
   __shared__ int flag;
   const int b = inst_id();
   InstState *st = c.st + b;
-  if (st->done) return;
+  const int done = st->done;   // checked at the first store (see k_sweep)
   const bool pend = st->pending != 0;
   const int blk = blockIdx.x;
   const int row = blk * NT + threadIdx.x;
@@ -560,13 +561,21 @@ __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode, const double *__
   const double alpha = st->alpha;
   const bool pr = have_prec && st->beta_kind == POD2G_BETA_PR && !pend;
   double rr = 0.0, rs = 0.0;
+  double uv = 0.0, pv = 0.0, rv0 = 0.0, qv = 0.0;
+  if (row < c.n) {
+    uv = c.u[off + row];
+    pv = p[off + row];
+    rv0 = c.r[off + row];
+    qv = c.q[off + row];
+  }
+  if (done) return;
   if (row < c.n) {
     double rv;
     if (pend) {
-      rv = c.q[off + row];
+      rv = qv;
     } else {
-      c.u[off + row] += alpha * p[off + row];
-      rv = c.r[off + row] - alpha * c.q[off + row];
+      c.u[off + row] = uv + alpha * pv;
+      rv = rv0 - alpha * qv;
     }
     c.r[off + row] = rv;
     rr = rv * rv;
