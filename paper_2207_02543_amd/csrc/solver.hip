@@ -24,6 +24,8 @@ struct Ctx {
   int xwin;                      // node-wise kernels stage x[block +- xwin nodes] in LDS (0: no)
   int igroup;                    // instances per group in the node-wise block order (divides batch)
   int fuse_dir;                  // direction update folded into the outer SpMV
+  int cons;                      // r^T s and p^T q finished by their consumers (else by
+                                 // the producer's last workgroup)
   int mixed;                     // FP32 cycle: its input is scaled by a power of two
   long long vstride;
   const int *colblk;
@@ -101,6 +103,57 @@ __device__ __forceinline__ long long stage_x(const Ctx &c, int blk, T *xs, XV xv
 // contiguous over workgroups.
 __device__ __forceinline__ double *slot(const Ctx &c, int b, int j) {
   return c.part + ((size_t)b * c.ps + j) * c.nb;
+}
+
+// Slots of the two sums that their consumers finish themselves: r^T s from
+// the end of the cycle (read by the direction update and by the vector
+// update) and p^T q from the outer SpMV (read by the vector update).  The
+// other reductions use slots 0 and 1 (and the restriction slots 0..k-1)
+// only while these two are not live.
+constexpr int SLOT_RHO = 2, SLOT_GAMMA = 3;
+
+// Sum of m partials by every workgroup of a consumer kernel: the order of
+// reduce_partials in every workgroup, so each obtains the same bits (and the
+// bits the producer's last workgroup would have formed).  Every thread of
+// the workgroup calls it and gets the total.
+__device__ __forceinline__ double consume_partials(const double *part, int m, double *lds) {
+  const double v = wave_sum(strided_sum(part, threadIdx.x, m, NT, 1));
+  if ((threadIdx.x & (WAVE - 1)) == 0) lds[threadIdx.x / WAVE] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int i = 0; i < NWAVE; ++i) t += lds[i];
+  __syncthreads();
+  return t;
+}
+
+// beta of the direction update from rho_new = r^T s (Fletcher-Reeves, or
+// the flexible Polak-Ribiere form with r_{k+1}^T s_k); 0 after a restart.
+__device__ __forceinline__ double beta_of(const InstState *st, double trs) {
+  if (st->restart) return 0.0;
+  return st->beta_kind == POD2G_BETA_PR ? (trs - st->rs_prev) / st->rho : trs / st->rho;
+}
+
+// A non-positive (or non-finite) r^T s or p^T q ends the instance: every
+// workgroup of the consumer skips it and one thread records it.
+__device__ __forceinline__ void breakdown(InstState *st, double v) {
+  st->done = 1;
+  st->status = finite(v) ? POD2G_EBREAKDOWN : POD2G_ENAN;
+}
+
+// Producer side of r^T s (large grids, where every consumer workgroup
+// re-reading the partials costs more than the arrival): the last workgroup
+// of the cycle's final kernel forms rho and beta.
+__device__ __forceinline__ void rho_tail(const Ctx &c, InstState *st, int b, int blk, double *lds,
+                                         int *flag) {
+  if (!arrive_last(site(c, b, CNT_B), blk, c.nbn, flag)) return;
+  const double trs = reduce_partials(slot(c, b, SLOT_RHO), c.nbn, 1, lds);
+  if (threadIdx.x == 0) {
+    st->beta = beta_of(st, trs);
+    st->restart = 0;
+    st->rho = trs;
+    if (!(trs > 0.0)) breakdown(st, trs);
+  }
 }
 
 // The search direction p = s + beta p_old (beta = 0 on a restart: p = s,
@@ -199,8 +252,9 @@ __device__ __forceinline__ const T *cycle_rhs(const Ctx &c, size_t off) {
 
 // x_out = x_in + omega D^-1 (b - K x_in), one thread per node (its DIM
 // rows).  With FINAL the result is the preconditioned residual
-// s = x_out / scale (FP64) and the block also reduces r^T s; the last block
-// forms rho and beta.
+// s = x_out / scale (FP64) and the block also writes its partial of r^T s
+// (finished by the consumers: k_pdir or k_spmv_pq, and k_update; or, with
+// c.cons unset, by the last workgroup here, which forms rho and beta).
 template <int DIM, typename T, bool FINAL>
 __global__ void __launch_bounds__(NT) k_sweep(Ctx c, const T *__restrict__ xin, T *__restrict__ xout,
                                               int want_dot) {
@@ -245,19 +299,8 @@ __global__ void __launch_bounds__(NT) k_sweep(Ctx c, const T *__restrict__ xin, 
   if (!FINAL || !want_dot || done) return;
   double dummy = 0.0;
   block_sum2(rs, dummy, lds);
-  if (threadIdx.x == 0) put_partial(slot(c, b, 0) + blk, rs);
-  if (!arrive_last(site(c, b, CNT_B), blk, c.nbn, &flag)) return;
-  const double trs = reduce_partials(slot(c, b, 0), c.nbn, 1, lds);
-  if (threadIdx.x == 0) {
-    double beta = 0.0;
-    if (!st->restart) {
-      beta = st->beta_kind == POD2G_BETA_PR ? (trs - st->rs_prev) / st->rho : trs / st->rho;
-    }
-    st->restart = 0;
-    st->beta = beta;
-    st->rho = trs;
-    if (!(trs > 0.0)) { st->done = 1; st->status = finite(trs) ? POD2G_EBREAKDOWN : POD2G_ENAN; }
-  }
+  if (threadIdx.x == 0) put_partial(slot(c, b, SLOT_RHO) + blk, rs);
+  if (!c.cons) rho_tail(c, st, b, blk, lds, &flag);
 }
 
 // Residual after pre-relaxation and restriction: r' = b - K x,
@@ -419,49 +462,46 @@ __global__ void __launch_bounds__(NT) k_prolong(Ctx c, const T *__restrict__ xin
   xout[off + row] = acc;
 }
 
-// s = x / scale with r^T s (used when the cycle ends without a sweep).
-template <typename T>
+// s = x / scale with r^T s (used when the cycle ends without a sweep),
+// one thread per node; the partials of r^T s go where k_sweep puts them.
+template <int DIM, typename T>
 __global__ void __launch_bounds__(NT) k_finalize(Ctx c, const T *__restrict__ x, int want_dot) {
   __shared__ double lds[2 * NWAVE];
   __shared__ int flag;
-  const int b = inst_id();
+  const NodeBlk nbk = node_block(c);
+  const int b = nbk.b, blk = nbk.blk;
   InstState *st = c.st + b;
   if (st->done) return;
-  const int blk = blockIdx.x;
-  const int row = blk * NT + threadIdx.x;
+  const int node = blk * NT + threadIdx.x;
   const size_t off = (size_t)b * c.n;
   double rs = 0.0;
-  if (row < c.n) {
-    const double sv = x ? (double)x[off + row] / st->scale : 0.0;
-    c.s[off + row] = sv;
-    rs = c.r[off + row] * sv;
+  if (node < c.nn) {
+#pragma unroll
+    for (int r = 0; r < DIM; ++r) {
+      const size_t row = off + (size_t)node * DIM + r;
+      const double sv = x ? (double)x[row] / st->scale : 0.0;
+      c.s[row] = sv;
+      rs += c.r[row] * sv;
+    }
   }
   if (!want_dot) return;
   double dummy = 0.0;
   block_sum2(rs, dummy, lds);
-  if (threadIdx.x == 0) put_partial(slot(c, b, 0) + blk, rs);
-  if (!arrive_last(site(c, b, CNT_B), blk, c.nb, &flag)) return;
-  const double trs = reduce_partials(slot(c, b, 0), c.nb, 1, lds);
-  if (threadIdx.x == 0) {
-    double beta = 0.0;
-    if (!st->restart)
-      beta = st->beta_kind == POD2G_BETA_PR ? (trs - st->rs_prev) / st->rho : trs / st->rho;
-    st->restart = 0;
-    st->beta = beta;
-    st->rho = trs;
-    if (!(trs > 0.0)) { st->done = 1; st->status = finite(trs) ? POD2G_EBREAKDOWN : POD2G_ENAN; }
-  }
+  if (threadIdx.x == 0) put_partial(slot(c, b, SLOT_RHO) + blk, rs);
+  if (!c.cons) rho_tail(c, st, b, blk, lds, &flag);
 }
 
-// q = K p and p^T q, one thread per node; the last block forms
-// alpha = rho / p^T q.  With FUSED the direction p = s + beta p_old is
-// formed here (gathered where K needs it, the owned rows written to pnew);
+// q = K p and the partials of p^T q, one thread per node; k_update
+// finishes the sum (c.cons) or the last workgroup here forms alpha.  With
+// FUSED the direction p = s + beta p_old is formed here (gathered where K
+// needs it, the owned rows written to pnew), beta from the cycle's r^T s
+// partials when cons and c.cons are set (else the beta in the state);
 // otherwise k_pdir formed it already.  Workgroup 0 sets the input scale of
 // the next cycle from the current ||r||.
 template <int DIM, bool FUSED>
 __global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c, const double *__restrict__ s,
                                                 const double *__restrict__ pold,
-                                                double *__restrict__ pnew) {
+                                                double *__restrict__ pnew, int cons) {
   __shared__ double lds[2 * NWAVE];
   __shared__ int flag;
   const NodeBlk nbk = node_block(c);
@@ -469,7 +509,16 @@ __global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c, const double *__restrict_
   InstState *st = c.st + b;
   // finished or pending instances are skipped at the first store (see k_sweep)
   const int skip = st->done | st->pending;
-  const double beta = st->beta;
+  double beta = st->beta;
+  if (FUSED && cons && c.cons) {
+    if (skip) return;
+    const double trs = consume_partials(slot(c, b, SLOT_RHO), c.nbn, lds);
+    if (!(trs > 0.0)) {
+      if (blk == 0 && threadIdx.x == 0) breakdown(st, trs);
+      return;
+    }
+    beta = beta_of(st, trs);
+  }
   const int node = blk * NT + threadIdx.x;
   const size_t off = (size_t)b * c.n;
   const double *sb = s + off, *pb = pold + off;
@@ -515,34 +564,49 @@ __global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c, const double *__restrict_
   }
   double dummy = 0.0;
   block_sum2(pq, dummy, lds);
-  if (threadIdx.x == 0) put_partial(slot(c, b, 0) + blk, pq);
-  if (!arrive_last(site(c, b, CNT_D), blk, c.nbn, &flag)) return;
-  const double g = reduce_partials(slot(c, b, 0), c.nbn, 1, lds);
+  if (threadIdx.x == 0) put_partial(slot(c, b, SLOT_GAMMA) + blk, pq);
+  if (c.cons || !arrive_last(site(c, b, CNT_D), blk, c.nbn, &flag)) return;
+  // producer side (large grids): alpha here
+  const double g = reduce_partials(slot(c, b, SLOT_GAMMA), c.nbn, 1, lds);
   if (threadIdx.x == 0) {
     st->gamma = g;
-    if (!(g > 0.0)) { st->done = 1; st->status = finite(g) ? POD2G_EBREAKDOWN : POD2G_ENAN; }
+    if (!(g > 0.0)) breakdown(st, g);
     st->alpha = st->rho / g;
   }
 }
 
-// p = s + beta p_old (the unfused form of the direction update).
+// p = s + beta p_old (the unfused form of the direction update); beta as in
+// k_spmv_pq.
 __global__ void __launch_bounds__(NT) k_pdir(Ctx c, const double *__restrict__ s,
                                              const double *__restrict__ pold,
-                                             double *__restrict__ pnew) {
+                                             double *__restrict__ pnew, int cons) {
+  __shared__ double lds[NWAVE];
   const int b = inst_id();
-  const InstState *st = c.st + b;
+  InstState *st = c.st + b;
   if (st->done || st->pending) return;
+  double beta = st->beta;
+  if (cons && c.cons) {
+    const double trs = consume_partials(slot(c, b, SLOT_RHO), c.nbn, lds);
+    if (!(trs > 0.0)) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) breakdown(st, trs);
+      return;
+    }
+    beta = beta_of(st, trs);
+  }
   const int row = blockIdx.x * NT + threadIdx.x;
   if (row >= c.n) return;
   const size_t off = (size_t)b * c.n;
-  pnew[off + row] = pdir(s[off + row], pold + off, row, st->beta);
+  pnew[off + row] = pdir(s[off + row], pold + off, row, beta);
 }
 
-// u += alpha p, r -= alpha q, ||r||^2 (and r^T s_old for the flexible
-// beta); with a preconditioner also the next cycle's input and, for
-// mode 1, its first pre-relaxation sweep.  Last block: convergence,
-// iteration limit, non-finite checks; without a preconditioner (mode 0)
-// s = r, so rho and beta are formed here.  A pending instance (served
+// alpha = rho / p^T q from the partials of the outer SpMV (and, with a
+// preconditioner, rho = r^T s from the cycle's), then u += alpha p,
+// r -= alpha q, ||r||^2 (and r^T s_old for the flexible beta); with a
+// preconditioner also the next cycle's input and, for mode 1, its first
+// pre-relaxation sweep.  Last block: convergence, iteration limit,
+// non-finite checks, and the state the next direction update reads (rho,
+// the restart flag cleared); without a preconditioner (mode 0) s = r, so
+// rho and beta are formed here.  A pending instance (served
 // solve whose true residual f - K u sits in q) takes r = q instead, leaves
 // u and the iteration count alone, and restarts from there: this is the
 // first step of a newly admitted solve and of a residual replacement.
@@ -558,7 +622,6 @@ __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode, const double *__
   const int blk = blockIdx.x;
   const int row = blk * NT + threadIdx.x;
   const size_t off = (size_t)b * c.n;
-  const double alpha = st->alpha;
   const bool pr = have_prec && st->beta_kind == POD2G_BETA_PR && !pend;
   double rr = 0.0, rs = 0.0;
   double uv = 0.0, pv = 0.0, rv0 = 0.0, qv = 0.0;
@@ -569,6 +632,16 @@ __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode, const double *__
     qv = c.q[off + row];
   }
   if (done) return;
+  double alpha = st->alpha, g = 0.0, rho = 0.0;
+  if (!pend && c.cons) {
+    g = consume_partials(slot(c, b, SLOT_GAMMA), c.nbn, lds);
+    rho = have_prec ? consume_partials(slot(c, b, SLOT_RHO), c.nbn, lds) : st->rho;
+    if (!(g > 0.0)) {
+      if (blk == 0 && threadIdx.x == 0) { st->gamma = g; breakdown(st, g); }
+      return;
+    }
+    alpha = rho / g;
+  }
   if (row < c.n) {
     double rv;
     if (pend) {
@@ -592,8 +665,19 @@ __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode, const double *__
   const double trr = reduce_partials(slot(c, b, 0), c.nb, 1, lds);
   const double trs = pr ? reduce_partials(slot(c, b, 1), c.nb, 1, lds) : 0.0;
   if (threadIdx.x == 0) {
-    if (pend) st->pending = 0;
-    else st->iter += 1;
+    if (pend) {
+      st->pending = 0;
+    } else {
+      st->iter += 1;
+      if (c.cons) {
+        st->gamma = g;
+        st->alpha = alpha;
+        if (have_prec) {
+          st->rho = rho;
+          st->restart = 0;
+        }
+      }
+    }
     st->rr = trr;
     st->rs_prev = trs;
     if (!finite(trr)) { st->done = 1; st->status = POD2G_ENAN; }
@@ -1162,6 +1246,9 @@ struct Layout {
 constexpr int BGRID_DEFAULT = 512;    // workgroups of the batched restriction
 constexpr int BGRID_MAX = 1024;       // largest the tuner tries (workspace is sized for it)
 constexpr long long FUSE_DIR_MAX = 1ll << 20;   // rows x instances with the fused update
+// consumer-side sums while (row workgroups x instances) x partials stays
+// below this (the partial loads every consumer workgroup repeats)
+constexpr long long CONS_MAX = 1ll << 21;
 
 static int batched_grid(int n, int cap) {
   const int nb = ceil_div(n, NT);
@@ -1170,7 +1257,7 @@ static int batched_grid(int n, int cap) {
 
 static Layout layout(int n, int batch, int k, int precision) {
   const int nb = ceil_div(n, NT);
-  const int ps = k > 2 ? k : 2;
+  const int ps = k > 4 ? k : 4;   // slots 0..3 at least (SLOT_RHO, SLOT_GAMMA)
   Layout L;
   size_t o = 0;
   L.st = o;    o += align256(sizeof(InstState) * (size_t)batch);
@@ -1232,7 +1319,8 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
   c.xwin = choose_xwin(pat);
   c.igroup = default_igroup(batch);
   c.fuse_dir = (long long)n * batch <= FUSE_DIR_MAX;
-  c.ps = k > 2 ? k : 2;
+  c.cons = (long long)c.nb * batch * c.nbn <= CONS_MAX;
+  c.ps = k > 4 ? k : 4;   // as in layout()
   c.vstride = pat->nvals;
   c.colblk = pat->colblk;
   c.vals = vals;
@@ -1363,7 +1451,7 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
         hipLaunchKernelGGL((k_sweep<DIM, T, false>), gridn, blk, xlds<T>(c), stream, c, cur, oth, 0);
       T *t = cur; cur = oth; oth = t;
     }
-    if (pr->nu_post == 1) hipLaunchKernelGGL((k_finalize<T>), grid, blk, 0, stream, c, cur, want_dot);
+    if (pr->nu_post == 1) hipLaunchKernelGGL((k_finalize<DIM, T>), gridn, blk, 0, stream, c, cur, want_dot);
     return;
   }
   for (int i = post_done; i < pr->nu_post; ++i) {
@@ -1376,7 +1464,7 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
     T *t = cur; cur = oth; oth = t;
   }
   if (pr->nu_post == post_done)
-    hipLaunchKernelGGL((k_finalize<T>), grid, blk, 0, stream, c, have ? (const T *)cur : (const T *)nullptr, want_dot);
+    hipLaunchKernelGGL((k_finalize<DIM, T>), gridn, blk, 0, stream, c, have ? (const T *)cur : (const T *)nullptr, want_dot);
 }
 
 // nsweeps Gauss-Seidel sweeps in place on x: colours in turn (reversed
@@ -1442,7 +1530,7 @@ static void launch_cycle_sgs(const Ctx &c, const pod2g_prec *pr, hipStream_t str
     cur = x;
   }
   if (pr->nu_post >= 1) gs_sweeps<DIM, T>(c, nullptr, cur, pr->nu_post, true, stream);
-  hipLaunchKernelGGL((k_finalize<T>), grid, blk, 0, stream, c, (const T *)cur, want_dot);
+  hipLaunchKernelGGL((k_finalize<DIM, T>), gridn, blk, 0, stream, c, (const T *)cur, want_dot);
 }
 
 template <int DIM>
@@ -1477,11 +1565,15 @@ static void launch_iteration(const Ctx &c, const pod2g_prec *pr, hipStream_t str
   // small problems are launch-bound: fold the direction update into the
   // SpMV; large ones are bandwidth-bound: a second gathered vector costs
   // more than one elementwise pass
+  // with a preconditioner, rho = r^T s is finished from the cycle's partials
+  const int cons = pr ? 1 : 0;
   if (c.fuse_dir) {
-    launch(tm, POD2G_TK_SPMV_PQ, k_spmv_pq<DIM, true>, gridn, blk, xlds<double>(c), stream, c, sdir, pold, pnew);
+    launch(tm, POD2G_TK_SPMV_PQ, k_spmv_pq<DIM, true>, gridn, blk, xlds<double>(c), stream, c, sdir, pold,
+           pnew, cons);
   } else {
-    hipLaunchKernelGGL(k_pdir, grid, blk, 0, stream, c, sdir, pold, pnew);
-    launch(tm, POD2G_TK_SPMV_PQ, k_spmv_pq<DIM, false>, gridn, blk, xlds<double>(c), stream, c, sdir, pold, pnew);
+    hipLaunchKernelGGL(k_pdir, grid, blk, 0, stream, c, sdir, pold, pnew, cons);
+    launch(tm, POD2G_TK_SPMV_PQ, k_spmv_pq<DIM, false>, gridn, blk, xlds<double>(c), stream, c, sdir, pold,
+           pnew, cons);
   }
   if (pr) {
     const int mode = pr->nu_pre >= 1 && pr->smoother == POD2G_SMOOTHER_JACOBI ? 1 : 2;
@@ -1958,6 +2050,15 @@ int pcg_plan_tune(pod2g_plan *pl, int trials, pod2g_tuning *out, hipStream_t str
     else c.fuse_dir = keep;
   }
   {
+    // the scalar sums finished by their consumers, or by the producers
+    const int keep = c.cons;
+    c.cons = !keep;
+    float ms;
+    if ((st = measure(&ms))) return st;
+    if (ms < best) best = ms;
+    else c.cons = keep;
+  }
+  {
     // the neighbourhood of each node block staged in LDS, or gathers from L2
     const int keep = c.xwin;
     c.xwin = keep ? 0 : choose_xwin(&pl->pat);
@@ -1983,6 +2084,7 @@ int pcg_plan_tune(pod2g_plan *pl, int trials, pod2g_tuning *out, hipStream_t str
     out->fuse_dir = c.fuse_dir;
     out->igroup = c.igroup;
     out->xwin = c.xwin;
+    out->cons = c.cons;
     out->ms_per_iteration = best;
   }
   return POD2G_OK;
