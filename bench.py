@@ -38,10 +38,12 @@ DOMINANT = {"c1": "restrict", "c2": "restrict", "c4a": "restrict", "c4b": "restr
             "c3": "spmv_pq", "c4c": "spmv_pq", "c5": "spmv_pq"}
 
 
-def kernel_bytes(w, kernel, mixed):
+def kernel_bytes(w, kernel, mixed, fuse_upd=False):
     """Algorithmic HBM bytes of one launch of `kernel` over the batch: each
     stored matrix value, index and vector entry moved once; what all
-    instances share (indices, basis) counted once."""
+    instances share (indices, basis) counted once.  fuse_upd: the update
+    kernel also applies the second pre-relaxation sweep (K, D^-1 read, x2
+    written, no stored first sweep)."""
     S = 3 ** w.dim
     n, nn, k, B = w.n, w.n_nodes_free, w.k, w.batch
     nvals = n * S * w.dim
@@ -65,6 +67,9 @@ def kernel_bytes(w, kernel, mixed):
         if not mixed or w.dim == 3:
             return vb * k * n + B * (vb * k * n + 4 * vb * n)
         return vb * k * n + B * 2 * vb * n
+    if kernel == "update" and fuse_upd:
+        return idx + B * (vb * nvals + 48 * n + (8 * n if mixed else 0) + (4 * n if mixed else 0)
+                          + 2 * vb * n)
     if kernel == "update":       # u, p, r, q (, s) read; u, r written; cycle input and first sweep
         return B * (48 * n + (8 * n if mixed else 0) + (12 * n if mixed else 24 * n))
     raise ValueError(kernel)
@@ -342,7 +347,10 @@ def main(argv=None):
     solves = args.steps * w.batch
     value = solves / dt
     avg_s = (ms_k / cnt) / 1e3 if cnt else float("nan")
-    nbytes = kernel_bytes(w, args.kernel, mixed)
+    # the update fused with the second pre-sweep: as tuned, else the library's
+    # default (small problems, Jacobi relaxation)
+    fuse_upd = (tuning["fuse_upd"] if tuning else w.n * w.batch <= (1 << 20)) and args.smoother == "jacobi"
+    nbytes = kernel_bytes(w, args.kernel, mixed, bool(fuse_upd))
     achieved = nbytes / avg_s / 1e9 if cnt else None
     log(f"[bench] {solves} solves in {dt:.3f} s; mean iterations "
         f"{np.mean(stats['iters']):.1f}; {args.kernel}: {cnt} timed launches, "

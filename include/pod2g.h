@@ -290,7 +290,8 @@ int pcg_plan_destroy(pod2g_plan *plan);
  * one parameter at a time and keeps the fastest, then recaptures the plan:
  * the workgroups of the batched restriction (128..1024, batched FP32 cycle
  * only), the direction update folded into the outer SpMV or run as its own
- * pass, the scalar sums r^T s and p^T q finished by the kernels that read
+ * pass, the vector update fused with the second Jacobi pre-relaxation
+ * sweep or not, the scalar sums r^T s and p^T q finished by the kernels that read
  * them (each workgroup re-reads the partials) or by the producer's last
  * workgroup, the neighbourhood of each 2D node block staged in LDS or
  * gathered from the caches, and the instance grouping of the node-wise block order
@@ -302,6 +303,7 @@ typedef struct pod2g_tuning {
   int igroup;              /* instances per group in the node-wise block order */
   int xwin;                /* > 0: 2D node blocks gather x from LDS (+- xwin nodes staged) */
   int cons;                /* 1: r^T s and p^T q summed by every workgroup of their consumers */
+  int fuse_upd;            /* 1: vector update fused with the second pre-relaxation sweep */
   float ms_per_iteration;  /* time of one iteration with the chosen values */
 } pod2g_tuning;
 int pcg_plan_tune(pod2g_plan *plan, int trials, pod2g_tuning *out, hipStream_t stream);

@@ -26,6 +26,7 @@ struct Ctx {
   int fuse_dir;                  // direction update folded into the outer SpMV
   int cons;                      // r^T s and p^T q finished by their consumers (else by
                                  // the producer's last workgroup)
+  int fuse_upd;                  // vector update fused with the second pre-relaxation sweep
   int mixed;                     // FP32 cycle: its input is scaled by a power of two
   long long vstride;
   const int *colblk;
@@ -39,6 +40,8 @@ struct Ctx {
   double omega;
   const double *f;               // [n]
   double *u, *r, *q, *s;         // [batch][n] FP64
+  double *r_alt;                 // [batch][n] second residual buffer (fused update, see
+                                 // k_update_sweep: the two alternate by iteration parity)
   double *p0, *p1;               // [batch][n] search directions (ping-pong)
   void *xa, *xb;                 // [batch][n] cycle vectors (smoother type)
   void *b32;                     // [batch][n] FP32 scaled residual (mixed only)
@@ -155,6 +158,11 @@ __device__ __forceinline__ void rho_tail(const Ctx &c, InstState *st, int b, int
     if (!(trs > 0.0)) breakdown(st, trs);
   }
 }
+
+// a b + c with one rounding, spelled out where two kernels must agree bit
+// for bit (the compiler may otherwise contract either product of a sum)
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // The search direction p = s + beta p_old (beta = 0 on a restart: p = s,
 // p_old not read).  One expression for the owned and the gathered entries.
@@ -286,7 +294,7 @@ __global__ void __launch_bounds__(NT) k_sweep(Ctx c, const T *__restrict__ xin, 
     if (done) return;
 #pragma unroll
     for (int r = 0; r < DIM; ++r) {
-      const T xv = xin[r0 + r] + (T)c.omega * dv[r] * (rhs[r] - kx[r]);
+      const T xv = fma_t((T)c.omega * dv[r], rhs[r] - kx[r], xin[r0 + r]);
       if (FINAL) {
         const double sv = (double)xv / st->scale;
         c.s[r0 + r] = sv;
@@ -687,6 +695,111 @@ __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode, const double *__
       st->beta = pend ? 0.0 : trr / st->rho;
       st->rho = trr;
     }
+  }
+}
+
+// k_update (mode 1) fused with the second pre-relaxation sweep, one thread
+// per node.  The first sweep starts from x = 0 and is pointwise,
+// x1 = omega D^-1 b with b = scale (r - alpha q) (b = scale q for a pending
+// instance), so the second sweep x2 = x1 + omega D^-1 (b - K x1) forms x1
+// at the neighbours from r, q and D^-1 there, with the expressions of the
+// owned rows, instead of reading a stored x1.  The neighbours' r must be
+// the old one, so the new residual goes to the other buffer (rin and rout
+// swap roles every iteration).  Writes u, rout, (FP32 b) and x2 to xout;
+// the ||r||^2 (and r^T s_old) reduction and its last workgroup are those
+// of k_update, over node blocks.
+template <int DIM, typename T>
+__global__ void __launch_bounds__(NT) k_update_sweep(Ctx c, const double *__restrict__ p,
+                                                     const double *__restrict__ rin,
+                                                     double *__restrict__ rout, T *__restrict__ xout) {
+  __shared__ double lds[2 * NWAVE];
+  __shared__ int flag;
+  const NodeBlk nbk = node_block(c);
+  const int b = nbk.b, blk = nbk.blk;
+  InstState *st = c.st + b;
+  const int done = st->done;   // checked at the first store (see k_sweep)
+  const bool pend = st->pending != 0;
+  const bool pr = st->beta_kind == POD2G_BETA_PR && !pend;
+  const int node = blk * NT + threadIdx.x;
+  const bool own = node < c.nn;
+  const size_t off = (size_t)b * c.n;
+  const size_t r0 = off + (size_t)node * DIM;
+  double uv[DIM], pv[DIM], rv0[DIM], qv[DIM];
+#pragma unroll
+  for (int r = 0; r < DIM; ++r) {
+    uv[r] = own ? c.u[r0 + r] : 0.0;
+    pv[r] = own ? p[r0 + r] : 0.0;
+    rv0[r] = own ? rin[r0 + r] : 0.0;
+    qv[r] = own ? c.q[r0 + r] : 0.0;
+  }
+  if (done) return;
+  double alpha = st->alpha, g = 0.0, rho = 0.0;
+  if (!pend && c.cons) {
+    g = consume_partials(slot(c, b, SLOT_GAMMA), c.nbn, lds);
+    rho = consume_partials(slot(c, b, SLOT_RHO), c.nbn, lds);
+    if (!(g > 0.0)) {
+      if (blk == 0 && threadIdx.x == 0) { st->gamma = g; breakdown(st, g); }
+      return;
+    }
+    alpha = rho / g;
+  }
+  const double scale = st->scale;
+  const T om = (T)c.omega;
+  const double *rb = rin + off, *qb = c.q + off;
+  const T *db = (const T *)c.sdinv + off;
+  double rr = 0.0, rs = 0.0;
+  if (own) {
+    T kx[DIM];
+    const T *vals = (const T *)c.svals + (size_t)b * c.vstride;
+    node_dot<DIM>(c.colblk, vals,
+                  [=](size_t i) {
+                    const double rvi = pend ? qb[i] : rb[i] - alpha * qb[i];
+                    return om * db[i] * (T)(rvi * scale);
+                  },
+                  node, c.n, c.nn, kx);
+#pragma unroll
+    for (int r = 0; r < DIM; ++r) {
+      const size_t row = r0 + r;
+      double rv;
+      if (pend) {
+        rv = qv[r];
+      } else {
+        c.u[row] = uv[r] + alpha * pv[r];
+        rv = rv0[r] - alpha * qv[r];
+      }
+      rout[row] = rv;
+      rr += rv * rv;
+      if (pr) rs += rv * c.s[row];
+      const T bv = (T)(rv * scale);
+      if (sizeof(T) == 4) ((float *)c.b32)[row] = (float)bv;
+      const T dv = ((const T *)c.sdinv)[row];
+      const T rhs = sizeof(T) == 8 ? (T)rv : bv;   // the cycle's right-hand side (see cycle_rhs)
+      const T x1 = om * dv * bv;
+      xout[row] = fma_t(om * dv, rhs - kx[r], x1);   // as in k_sweep, bit for bit
+    }
+  }
+  block_sum2(rr, rs, lds);
+  if (threadIdx.x == 0) { put_partial(slot(c, b, 0) + blk, rr); put_partial(slot(c, b, 1) + blk, rs); }
+  if (!arrive_last(site(c, b, CNT_E), blk, c.nbn, &flag)) return;
+  const double trr = reduce_partials(slot(c, b, 0), c.nbn, 1, lds);
+  const double trs = pr ? reduce_partials(slot(c, b, 1), c.nbn, 1, lds) : 0.0;
+  if (threadIdx.x == 0) {
+    if (pend) {
+      st->pending = 0;
+    } else {
+      st->iter += 1;
+      if (c.cons) {
+        st->gamma = g;
+        st->alpha = alpha;
+        st->rho = rho;
+        st->restart = 0;
+      }
+    }
+    st->rr = trr;
+    st->rs_prev = trs;
+    if (!finite(trr)) { st->done = 1; st->status = POD2G_ENAN; }
+    else if (trr <= st->tol2) { st->done = 1; st->status = POD2G_OK; }
+    else if (st->iter >= st->maxit) { st->done = 1; st->status = POD2G_EMAXIT; }
   }
 }
 
@@ -1270,7 +1383,7 @@ static Layout layout(int n, int batch, int k, int precision) {
   L.flags = o; o += align256(sizeof(int) * (size_t)batch);
   L.info = o;  o += align256(sizeof(pod2g_slot_info) * (size_t)batch);
   L.arr = o;   o += sizeof(Arrival) * NSITE * (size_t)batch;
-  L.vec = o;   o += 7 * align256(sizeof(double) * (size_t)n * batch);   // r p0 p1 q s xa xb
+  L.vec = o;   o += 8 * align256(sizeof(double) * (size_t)n * batch);   // r p0 p1 q s xa xb r_alt
   L.vec32 = o;
   if (precision == POD2G_MIXED) o += 2 * align256(sizeof(float) * (size_t)n * batch);  // b32, rbuf
   L.total = o;
@@ -1320,6 +1433,7 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
   c.igroup = default_igroup(batch);
   c.fuse_dir = (long long)n * batch <= FUSE_DIR_MAX;
   c.cons = (long long)c.nb * batch * c.nbn <= CONS_MAX;
+  c.fuse_upd = (long long)n * batch <= FUSE_DIR_MAX;
   c.ps = k > 4 ? k : 4;   // as in layout()
   c.vstride = pat->nvals;
   c.colblk = pat->colblk;
@@ -1341,6 +1455,7 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
   c.s = (double *)(w + Lo.vec + 4 * vb);
   c.xa = (void *)(w + Lo.vec + 5 * vb);
   c.xb = (void *)(w + Lo.vec + 6 * vb);
+  c.r_alt = (double *)(w + Lo.vec + 7 * vb);
   c.b32 = precision == POD2G_MIXED ? (void *)(w + Lo.vec32) : nullptr;
   c.rbuf = precision == POD2G_MIXED
                ? (float *)(w + Lo.vec32 + align256(sizeof(float) * (size_t)n * batch))
@@ -1382,13 +1497,14 @@ static bool batched_products(const Ctx &c) {
 // r).  With want_dot the last kernel also forms rho and beta.
 template <int DIM, typename T>
 static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, int want_dot,
-                         Tm *tm) {
+                         Tm *tm, int pre2_done) {
   dim3 grid(c.nb, c.batch), gridn(c.nbn, c.batch), blk(NT);
   T *xa = (T *)c.xa, *xb = (T *)c.xb;
-  T *cur = xa, *oth = xb;
+  // pre2_done: the first two pre-relaxation sweeps are done, x2 in xb
+  T *cur = pre2_done ? xb : xa, *oth = pre2_done ? xa : xb;
   const bool have_x = pr->nu_pre >= 1;
   int post_done = 0;   // post-relaxation sweeps already applied
-  for (int i = 1; i < pr->nu_pre; ++i) {
+  for (int i = pre2_done ? 2 : 1; i < pr->nu_pre; ++i) {
     launch(tm, POD2G_TK_SWEEP, k_sweep<DIM, T, false>, gridn, blk, xlds<T>(c), stream, c, (const T *)cur, oth, 0);
     T *t = cur; cur = oth; oth = t;
   }
@@ -1535,14 +1651,14 @@ static void launch_cycle_sgs(const Ctx &c, const pod2g_prec *pr, hipStream_t str
 
 template <int DIM>
 static void launch_cycle_any(const Ctx &c, const pod2g_prec *pr, hipStream_t stream, int want_dot,
-                             Tm *tm) {
+                             Tm *tm, int pre2_done = 0) {
   if (pr->smoother == POD2G_SMOOTHER_SGS) {
     if (pr->precision == POD2G_MIXED) launch_cycle_sgs<DIM, float>(c, pr, stream, want_dot, tm);
     else launch_cycle_sgs<DIM, double>(c, pr, stream, want_dot, tm);
     return;
   }
-  if (pr->precision == POD2G_MIXED) launch_cycle<DIM, float>(c, pr, stream, want_dot, tm);
-  else launch_cycle<DIM, double>(c, pr, stream, want_dot, tm);
+  if (pr->precision == POD2G_MIXED) launch_cycle<DIM, float>(c, pr, stream, want_dot, tm, pre2_done);
+  else launch_cycle<DIM, double>(c, pr, stream, want_dot, tm, pre2_done);
 }
 
 template <int DIM>
@@ -1577,11 +1693,29 @@ static void launch_iteration(const Ctx &c, const pod2g_prec *pr, hipStream_t str
   }
   if (pr) {
     const int mode = pr->nu_pre >= 1 && pr->smoother == POD2G_SMOOTHER_JACOBI ? 1 : 2;
-    if (pr->precision == POD2G_MIXED)
-      launch(tm, POD2G_TK_UPDATE, k_update<float>, grid, blk, 0, stream, c, mode, (const double *)pnew);
-    else
-      launch(tm, POD2G_TK_UPDATE, k_update<double>, grid, blk, 0, stream, c, mode, (const double *)pnew);
-    launch_cycle_any<DIM>(c, pr, stream, 1, tm);
+    const int fuse = mode == 1 && pr->nu_pre >= 2 && c.fuse_upd;
+    if (fuse) {
+      // the residual alternates between r (even iterations read it) and
+      // r_alt; chunks have an even number of iterations, so it is back in
+      // r at the end of each, as every other kernel expects
+      const double *rin = parity ? c.r_alt : c.r;
+      double *rout = parity ? c.r : c.r_alt;
+      if (pr->precision == POD2G_MIXED)
+        launch(tm, POD2G_TK_UPDATE, k_update_sweep<DIM, float>, gridn, blk, 0, stream, c,
+               (const double *)pnew, rin, rout, (float *)c.xb);
+      else
+        launch(tm, POD2G_TK_UPDATE, k_update_sweep<DIM, double>, gridn, blk, 0, stream, c,
+               (const double *)pnew, rin, rout, (double *)c.xb);
+      Ctx cc = c;
+      cc.r = rout;
+      launch_cycle_any<DIM>(cc, pr, stream, 1, tm, 1);
+    } else {
+      if (pr->precision == POD2G_MIXED)
+        launch(tm, POD2G_TK_UPDATE, k_update<float>, grid, blk, 0, stream, c, mode, (const double *)pnew);
+      else
+        launch(tm, POD2G_TK_UPDATE, k_update<double>, grid, blk, 0, stream, c, mode, (const double *)pnew);
+      launch_cycle_any<DIM>(c, pr, stream, 1, tm);
+    }
   } else {
     launch(tm, POD2G_TK_UPDATE, k_update<double>, grid, blk, 0, stream, c, 0, (const double *)pnew);
   }
@@ -2049,6 +2183,15 @@ int pcg_plan_tune(pod2g_plan *pl, int trials, pod2g_tuning *out, hipStream_t str
     if (ms < best) best = ms;
     else c.fuse_dir = keep;
   }
+  if (pr && pr->nu_pre >= 2 && pr->smoother == POD2G_SMOOTHER_JACOBI) {
+    // the vector update fused with the second pre-relaxation sweep, or not
+    const int keep = c.fuse_upd;
+    c.fuse_upd = !keep;
+    float ms;
+    if ((st = measure(&ms))) return st;
+    if (ms < best) best = ms;
+    else c.fuse_upd = keep;
+  }
   {
     // the scalar sums finished by their consumers, or by the producers
     const int keep = c.cons;
@@ -2085,6 +2228,7 @@ int pcg_plan_tune(pod2g_plan *pl, int trials, pod2g_tuning *out, hipStream_t str
     out->igroup = c.igroup;
     out->xwin = c.xwin;
     out->cons = c.cons;
+    out->fuse_upd = c.fuse_upd;
     out->ms_per_iteration = best;
   }
   return POD2G_OK;

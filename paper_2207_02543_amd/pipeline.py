@@ -172,7 +172,7 @@ class Plan:
         loading the initial guess)."""
         t = L.pcg_plan_tune(self.handle, trials, stream)
         return {"bgrid": t.bgrid, "fuse_dir": t.fuse_dir, "igroup": t.igroup, "xwin": t.xwin,
-                "cons": t.cons, "ms_per_iteration": t.ms_per_iteration}
+                "cons": t.cons, "fuse_upd": t.fuse_upd, "ms_per_iteration": t.ms_per_iteration}
 
     def close(self):
         if self.handle:

@@ -40,7 +40,7 @@ def test_plan_replays_match_eager(dim, N, prec, chunk, batch):
         ret, it, rr, st = prob.solve(sysm, pr, u)
         assert ret == capi.OK
         eager.append((it, u.cpu().numpy().copy()))
-    timer = capi.pod2g_timer_create(capi.TK_SWEEP, 4)
+    timer = capi.pod2g_timer_create(capi.TK_UPDATE, 4)
     pr = load(0)
     plan = prob.plan(sysm, pr, u, chunk=chunk, timer=timer)
     for rep in range(2):
