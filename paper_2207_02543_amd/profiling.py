@@ -128,6 +128,7 @@ def run(workload, kernel, out, steps, extra, trace_only=False):
              "--kernel", kernel] + extra
     calib_cmd = [sys.executable, "-m", "paper_2207_02543_amd.profiling", "calib"]
     env = dict(os.environ, TMPDIR="/tmp", PYTHONPATH=root)
+    out = os.path.abspath(out)   # the profiler runs from /tmp
     os.makedirs(out, exist_ok=True)
     cmds = []
 
