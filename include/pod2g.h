@@ -308,6 +308,19 @@ typedef struct pod2g_tuning {
 } pod2g_tuning;
 int pcg_plan_tune(pod2g_plan *plan, int trials, pod2g_tuning *out, hipStream_t stream);
 
+/* Set a plan's launch parameters explicitly (for instance values an earlier
+ * pcg_plan_tune chose) and recapture it; pcg_plan_config reads them
+ * (ms_per_iteration = 0).  bgrid in 1..min(workgroups of n rows, 1024);
+ * fuse_dir, cons and fuse_upd 0 or 1; igroup a divisor of the batch up to
+ * 8; xwin 0, or positive for LDS staging (2D only: the library sets the
+ * window); ms_per_iteration is ignored.  Anything else: POD2G_EINVAL and
+ * the plan is unchanged.  Only bgrid (the partition of the batched
+ * restriction's sums) and fuse_upd (the grouping of the ||r||^2 and
+ * r^T s_old partials) change rounding; the other parameters give the same
+ * bits.  Not thread-safe with a solve on the same plan.                   */
+int pcg_plan_configure(pod2g_plan *plan, const pod2g_tuning *cfg);
+int pcg_plan_config(const pod2g_plan *plan, pod2g_tuning *out);
+
 /* ---- served solves (continuous batching over slot groups) -----------------
  * Many independent queries theta (Sec. 3, the multi-query setting) arrive
  * over time.  A server owns n_groups slot groups; group g is one problem

@@ -126,6 +126,8 @@ _f = {
                                                   C.POINTER(_i), _vp]),
     "pcg_plan_destroy": _sig("pcg_plan_destroy", _i, [_vp]),
     "pcg_plan_tune": _sig("pcg_plan_tune", _i, [_vp, _i, C.POINTER(Tuning), _vp]),
+    "pcg_plan_configure": _sig("pcg_plan_configure", _i, [_vp, C.POINTER(Tuning)]),
+    "pcg_plan_config": _sig("pcg_plan_config", _i, [_vp, C.POINTER(Tuning)]),
     "pod2g_mark": _sig("pod2g_mark", _i, [_i, _vp]),
     "pod2g_spmv": _sig("pod2g_spmv", _i, [_PP, _vp, _i, _vp, _vp, _vp]),
     "pod2g_jacobi": _sig("pod2g_jacobi", _i, [_PP, _vp, _vp, _i, _d, _i, _vp, _vp, _vp, _vp]),
@@ -311,6 +313,16 @@ def pcg_plan_solve(plan, rtol, maxit, beta, batch, stream=None):
 def pcg_plan_tune(plan, trials, stream=None) -> Tuning:
     t = Tuning()
     check(_f["pcg_plan_tune"](plan, trials, C.byref(t), _stream(stream)), "pcg_plan_tune")
+    return t
+
+
+def pcg_plan_configure(plan, t: Tuning) -> int:
+    return _f["pcg_plan_configure"](plan, C.byref(t))
+
+
+def pcg_plan_config(plan) -> Tuning:
+    t = Tuning()
+    check(_f["pcg_plan_config"](plan, C.byref(t)), "pcg_plan_config")
     return t
 
 

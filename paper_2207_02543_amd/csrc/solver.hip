@@ -2234,6 +2234,39 @@ int pcg_plan_tune(pod2g_plan *pl, int trials, pod2g_tuning *out, hipStream_t str
   return POD2G_OK;
 }
 
+int pcg_plan_configure(pod2g_plan *pl, const pod2g_tuning *cfg) {
+  if (!pl || !cfg) return POD2G_EINVAL;
+  Ctx &c = pl->c;
+  const int gmax = batched_grid(c.n, BGRID_MAX);
+  if (cfg->bgrid < 1 || cfg->bgrid > gmax) return POD2G_EINVAL;
+  if ((cfg->fuse_dir | cfg->cons | cfg->fuse_upd) & ~1) return POD2G_EINVAL;
+  if (cfg->igroup < 1 || cfg->igroup > 8 || c.batch % cfg->igroup) return POD2G_EINVAL;
+  const int xw = cfg->xwin > 0 ? choose_xwin(&pl->pat) : 0;
+  if (cfg->xwin < 0 || (cfg->xwin > 0 && xw == 0)) return POD2G_EINVAL;
+  const Ctx keep = c;
+  c.bgrid = cfg->bgrid;
+  c.fuse_dir = cfg->fuse_dir;
+  c.igroup = cfg->igroup;
+  c.xwin = xw;
+  c.cons = cfg->cons;
+  c.fuse_upd = cfg->fuse_upd;
+  const int st = capture_plan(pl);
+  if (st) c = keep;
+  return st;
+}
+
+int pcg_plan_config(const pod2g_plan *pl, pod2g_tuning *out) {
+  if (!pl || !out) return POD2G_EINVAL;
+  out->bgrid = pl->c.bgrid;
+  out->fuse_dir = pl->c.fuse_dir;
+  out->igroup = pl->c.igroup;
+  out->xwin = pl->c.xwin;
+  out->cons = pl->c.cons;
+  out->fuse_upd = pl->c.fuse_upd;
+  out->ms_per_iteration = 0.f;
+  return POD2G_OK;
+}
+
 int pcg_plan_create(const pod2g_pattern *pat, const double *vals, int batch, const pod2g_prec *prec,
                     const double *f, double *u, int chunk, void *work, size_t bytes,
                     pod2g_timer *timer, pod2g_plan **out) {

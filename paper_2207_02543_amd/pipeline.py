@@ -174,6 +174,21 @@ class Plan:
         return {"bgrid": t.bgrid, "fuse_dir": t.fuse_dir, "igroup": t.igroup, "xwin": t.xwin,
                 "cons": t.cons, "fuse_upd": t.fuse_upd, "ms_per_iteration": t.ms_per_iteration}
 
+    def config(self) -> dict:
+        t = L.pcg_plan_config(self.handle)
+        return {f: getattr(t, f) for f in ("bgrid", "fuse_dir", "igroup", "xwin", "cons", "fuse_upd")}
+
+    def configure(self, **params):
+        """Set launch parameters (names as in config()); the rest keep their
+        values.  Raises on values the plan cannot take."""
+        cur = self.config()
+        unknown = set(params) - set(cur)
+        if unknown:
+            raise ValueError(f"unknown launch parameters {sorted(unknown)}")
+        cur.update(params)
+        t = L.Tuning(**cur)
+        L.check(L.pcg_plan_configure(self.handle, t), "pcg_plan_configure")
+
     def close(self):
         if self.handle:
             L.pcg_plan_destroy(self.handle)

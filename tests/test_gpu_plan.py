@@ -92,3 +92,75 @@ def test_tuned_plan_solves_like_eager(dim, N, prec, batch):
         assert abs(it[b] - it_e[b]) <= 2 and rr[b] <= w.tol
         assert np.linalg.norm(u[b].cpu().numpy() - u_e[b]) <= 1e-6 * np.linalg.norm(u_e[b])
     plan.close()
+
+
+@pytest.mark.parametrize("dim,N,prec,batch", [
+    (2, 24, "fp64", 1), (2, 24, "fp64", 4), (2, 24, "mixed", 4), (3, 6, "fp64", 2), (3, 6, "mixed", 4)])
+def test_launch_parameters_keep_the_result(dim, N, prec, batch):
+    """Each launch parameter set explicitly, one at a time, on the same plan:
+    the direction update fused or not, sums finished by consumers or
+    producers, the LDS-staged neighbourhood (2D), the instance grouping give
+    the same bits; the fused vector update (other grouping of the ||r||^2
+    and r^T s_old partials) and the batched restriction's grid (other
+    partition of its sums) change rounding only.  Invalid values are
+    rejected and leave the plan as it was."""
+    import torch
+    from paper_2207_02543_amd import capi, pipeline
+    flush(f"launch parameters dim={dim} N={N} {prec} batch={batch}")
+    w = I.small(dim, N, k=6, n_train=12)
+    P, lam, U = oprob.basis(w, I.train_xis(w))
+    Pd = torch.tensor(np.ascontiguousarray(P.T), device="cuda")
+    precision = capi.MIXED if prec == "mixed" else capi.FP64
+    queries = [oprob.query(w, I.query_xi(w, j), I.noise(w, j)) for j in range(batch)]
+    prob = pipeline.Problem(w)
+    sysm = prob.alloc_system(batch, fp32=(prec == "mixed"))
+    prob.assemble(sysm, np.stack([q.xi for q in queries]))
+    pr = prob.setup(sysm, Pd, precision=precision)
+    x0 = torch.tensor(np.stack([q.x0 for q in queries]), device="cuda")
+    u = x0.clone()
+    plan = prob.plan(sysm, pr, u, chunk=8)
+    base = plan.config()
+    flush(f"  default {base}")
+
+    def run():
+        u.copy_(x0)
+        ret, it, rr, st = plan.solve(w.tol)
+        assert ret == capi.OK, st
+        return list(it), u.cpu().numpy().copy()
+
+    it0, u0 = run()
+    variants = [dict(fuse_dir=1 - base["fuse_dir"]), dict(cons=1 - base["cons"])]
+    if dim == 2:
+        variants.append(dict(xwin=0 if base["xwin"] else 1))
+    if batch % 2 == 0:
+        variants.append(dict(igroup=2))
+    if batch % 4 == 0:
+        variants.append(dict(igroup=4))
+    for v in variants:
+        plan.configure(**{**base, **v})
+        it, uv = run()
+        flush(f"  {v}: iterations {it}")
+        assert it == it0
+        np.testing.assert_array_equal(uv, u0)
+    # rounding-only changes
+    rounding = [dict(fuse_upd=1 - base["fuse_upd"])]
+    if base["bgrid"] > 1:
+        rounding.append(dict(bgrid=1))
+    for v in rounding:
+        plan.configure(**{**base, **v})
+        it, uv = run()
+        flush(f"  {v}: iterations {it}")
+        for b in range(batch):
+            assert abs(it[b] - it0[b]) <= 1
+            assert np.linalg.norm(uv[b] - u0[b]) <= 1e-7 * np.linalg.norm(u0[b])
+    # invalid values: rejected, plan unchanged
+    plan.configure(**base)
+    for bad in [dict(bgrid=0), dict(cons=2), dict(fuse_upd=-1), dict(igroup=3), dict(igroup=16)] + \
+            ([dict(xwin=1)] if dim == 3 else []):
+        t = capi.Tuning(**{**base, **bad})
+        assert capi.pcg_plan_configure(plan.handle, t) == capi.EINVAL, bad
+        assert plan.config() == base
+    it, uv = run()
+    assert it == it0
+    np.testing.assert_array_equal(uv, u0)
+    plan.close()
