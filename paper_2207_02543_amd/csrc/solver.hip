@@ -550,8 +550,8 @@ __global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c, const double *__restrict_
 #pragma unroll
       for (int r = 0; r < DIM; ++r) pv[r] = xs[r0 + r - xlo];
     } else if (FUSED) {
-      node_dot<DIM>(c.colblk, vals, [sb, pb, beta](size_t i) { return pdir(sb[i], pb, i, beta); },
-                    node, c.n, c.nn, kp);
+      const auto pdir_at = [sb, pb, beta](size_t i) { return pdir(sb[i], pb, i, beta); };
+      node_dot<DIM, double, decltype(pdir_at), DIM == 3 ? 3 : 9>(c.colblk, vals, pdir_at, node, c.n, c.nn, kp);
 #pragma unroll
       for (int r = 0; r < DIM; ++r) pv[r] = pdir(sb[r0 + r], pb, r0 + r, beta);
     } else {
@@ -751,12 +751,12 @@ __global__ void __launch_bounds__(NT) k_update_sweep(Ctx c, const double *__rest
   if (own) {
     T kx[DIM];
     const T *vals = (const T *)c.svals + (size_t)b * c.vstride;
-    node_dot<DIM>(c.colblk, vals,
-                  [=](size_t i) {
-                    const double rvi = pend ? qb[i] : rb[i] - alpha * qb[i];
-                    return om * db[i] * (T)(rvi * scale);
-                  },
-                  node, c.n, c.nn, kx);
+    // x1 at any row i, from r, q and D^-1 there
+    const auto x1_at = [=](size_t i) {
+      const double rvi = pend ? qb[i] : rb[i] - alpha * qb[i];
+      return om * db[i] * (T)(rvi * scale);
+    };
+    node_dot<DIM, T, decltype(x1_at), DIM == 3 ? 3 : 9>(c.colblk, vals, x1_at, node, c.n, c.nn, kx);
 #pragma unroll
     for (int r = 0; r < DIM; ++r) {
       const size_t row = r0 + r;
