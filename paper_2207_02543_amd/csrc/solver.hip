@@ -1003,15 +1003,17 @@ __global__ void __launch_bounds__(NT) k_prolong_b(Ctx c, const float *__restrict
     const size_t off = (size_t)b * n;
     float xv = (xin ? xin[off + row] : 0.f) + Out[b][threadIdx.x];
     if (rp) {
-      // eight loads of K P in flight before their products
+      // up to 32 loads of K P in flight before their products (one round
+      // for k <= 32)
+      constexpr int KC = 32;
       const float *kp = c.KP32 + (size_t)b * k * n + row;
       float d = rp[off + row];
-      for (int j0 = 0; j0 < k; j0 += 8) {
-        float kv[8];
+      for (int j0 = 0; j0 < k; j0 += KC) {
+        float kv[KC];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) kv[u] = j0 + u < k ? kp[(size_t)(j0 + u) * n] : 0.f;
+        for (int u = 0; u < KC; ++u) kv[u] = j0 + u < k ? kp[(size_t)(j0 + u) * n] : 0.f;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) d -= kv[u] * E[j0 + u < MAXK ? j0 + u : 0][b];
+        for (int u = 0; u < KC; ++u) d -= kv[u] * E[j0 + u < MAXK ? j0 + u : 0][b];
       }
       xv += (float)c.omega * ((const float *)c.sdinv)[off + row] * d;
     }
