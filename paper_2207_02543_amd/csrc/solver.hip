@@ -271,8 +271,11 @@ __global__ void __launch_bounds__(NT) k_sweep(Ctx c, const T *__restrict__ xin, 
   const NodeBlk nbk = node_block(c);
   const int b = nbk.b, blk = nbk.blk;
   InstState *st = c.st ? c.st + b : nullptr;   // null: standalone sweeps
-  // a finished instance is skipped at its first store: its state load is
-  // in flight with the gathers instead of ahead of them
+  // One instance: a finished instance is skipped at its first store, so the
+  // state load is in flight with the gathers instead of ahead of them (the
+  // few launches after convergence cost little).  Several instances (a batch,
+  // served slots, most of them possibly finished or free): skip at once.
+  if (c.batch > 1 && st && st->done) return;
   const int done = st ? st->done : 0;
   const int node = blk * NT + threadIdx.x;
   const size_t off = (size_t)b * c.n;
@@ -322,7 +325,8 @@ __global__ void __launch_bounds__(NT) k_restrict(Ctx c, const T *__restrict__ x,
   __shared__ int flag;
   const int b = inst_id();
   InstState *st = c.st + b;
-  const int done = st->done;   // checked at the first store (see k_sweep)
+  if (c.batch > 1 && st->done) return;
+  const int done = st->done;   // one instance: checked at the first store (see k_sweep)
   const int blk = xcd_block(blockIdx.x, c.nb);
   const int row = blk * NT + threadIdx.x;
   const size_t off = (size_t)b * c.n;
@@ -442,7 +446,8 @@ __global__ void __launch_bounds__(NT) k_prolong(Ctx c, const T *__restrict__ xin
                                                 const T *__restrict__ rp, const T *__restrict__ kp) {
   constexpr int PC = 16;   // basis (and K P) loads in flight together
   const int b = inst_id();
-  const int done = c.st[b].done;   // checked at the store (see k_sweep)
+  if (c.batch > 1 && c.st[b].done) return;
+  const int done = c.st[b].done;   // one instance: checked at the store (see k_sweep)
   const int row = blockIdx.x * NT + threadIdx.x;
   if (row >= c.n) return;
   const size_t off = (size_t)b * c.n;
@@ -516,6 +521,7 @@ __global__ void __launch_bounds__(NT) k_spmv_pq(Ctx c, const double *__restrict_
   const int b = nbk.b, blk = nbk.blk;
   InstState *st = c.st + b;
   // finished or pending instances are skipped at the first store (see k_sweep)
+  if (c.batch > 1 && (st->done | st->pending)) return;
   const int skip = st->done | st->pending;
   double beta = st->beta;
   if (FUSED && cons && c.cons) {
@@ -625,7 +631,8 @@ __global__ void __launch_bounds__(NT) k_update(Ctx c, int mode, const double *__
   __shared__ int flag;
   const int b = inst_id();
   InstState *st = c.st + b;
-  const int done = st->done;   // checked at the first store (see k_sweep)
+  if (c.batch > 1 && st->done) return;
+  const int done = st->done;   // one instance: checked at the first store (see k_sweep)
   const bool pend = st->pending != 0;
   const int blk = blockIdx.x;
   const int row = blk * NT + threadIdx.x;
@@ -717,7 +724,8 @@ __global__ void __launch_bounds__(NT) k_update_sweep(Ctx c, const double *__rest
   const NodeBlk nbk = node_block(c);
   const int b = nbk.b, blk = nbk.blk;
   InstState *st = c.st + b;
-  const int done = st->done;   // checked at the first store (see k_sweep)
+  if (c.batch > 1 && st->done) return;
+  const int done = st->done;   // one instance: checked at the first store (see k_sweep)
   const bool pend = st->pending != 0;
   const bool pr = st->beta_kind == POD2G_BETA_PR && !pend;
   const int node = blk * NT + threadIdx.x;
