@@ -60,7 +60,10 @@ def kernel_bytes(w, kernel, mixed, fuse_upd=False):
     if kernel == "restrict":
         if batched:              # r' = b - K x in FP32: K, x, b read; r' written
             return idx + B * (4 * nvals + 12 * n)
-        return idx + vb * k * n + B * (vb * nvals + 2 * vb * n)   # + P once
+        # K, x, b read, P once; r' also written where the first post-sweep
+        # uses it with K P (FP64 path, or FP32 in 3D)
+        saved = vb * n if (not mixed or w.dim == 3) else 0
+        return idx + vb * k * n + B * (vb * nvals + 2 * vb * n + saved)
     if kernel == "prolong":
         # x + P e + omega D^-1 (r' - K P e) where K P is at hand (FP64 path,
         # or FP32 in 3D): P once, K P per instance, x, r', D^-1 read, x written

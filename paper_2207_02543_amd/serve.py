@@ -40,7 +40,7 @@ def slot_bytes(w: I.Workload, k: int, precision: str) -> int:
     b = nvals * 8 + (nvals * 4 if mixed else 0)        # K
     b += n * 8 + (n * 4 if mixed else 0)               # D^-1
     b += k * n * 8 + 2 * k * k * 8                     # K P, L, L^-1
-    b += 8 * n * 8 + (2 * n * 4 if mixed else 0)       # u and the solver vectors
+    b += 9 * n * 8 + (2 * n * 4 if mixed else 0)       # u and the eight solver vectors
     return b
 
 
