@@ -1006,26 +1006,50 @@ __global__ void __launch_bounds__(NT) k_prolong_b(Ctx c, const float *__restrict
   __syncthreads();
   const int row = blk * NT + threadIdx.x;
   if (row >= n) return;
-  for (int b = 0; b < B; ++b) {
-    if (!live[b]) continue;
-    const size_t off = (size_t)b * n;
-    float xv = (xin ? xin[off + row] : 0.f) + Out[b][threadIdx.x];
-    if (rp) {
-      // up to 32 loads of K P in flight before their products (one round
-      // for k <= 32)
-      constexpr int KC = 32;
-      const float *kp = c.KP32 + (size_t)b * k * n + row;
-      float d = rp[off + row];
-      for (int j0 = 0; j0 < k; j0 += KC) {
-        float kv[KC];
-#pragma unroll
-        for (int u = 0; u < KC; ++u) kv[u] = j0 + u < k ? kp[(size_t)(j0 + u) * n] : 0.f;
-#pragma unroll
-        for (int u = 0; u < KC; ++u) d -= kv[u] * E[j0 + u < MAXK ? j0 + u : 0][b];
-      }
-      xv += (float)c.omega * ((const float *)c.sdinv)[off + row] * d;
+  const float *dinv = (const float *)c.sdinv;
+  // two instances at a time, so that both instances' loads are in flight
+  // together (each instance's arithmetic does not depend on its partner)
+  for (int b0 = 0; b0 < B; b0 += 2) {
+    const int b1 = b0 + 1;   // < MAXB: E and Out hold zeros past the batch
+    const bool l0 = live[b0] != 0, l1 = b1 < B && live[b1] != 0;
+    if (!l0 && !l1) continue;
+    const size_t o0 = (size_t)b0 * n, o1 = (size_t)b1 * n;
+    float xv0 = 0.f, xv1 = 0.f, d0 = 0.f, d1 = 0.f, dv0 = 0.f, dv1 = 0.f;
+    if (l0) {
+      xv0 = xin ? xin[o0 + row] : 0.f;
+      if (rp) { d0 = rp[o0 + row]; dv0 = dinv[o0 + row]; }
     }
-    xout[off + row] = xv;
+    if (l1) {
+      xv1 = xin ? xin[o1 + row] : 0.f;
+      if (rp) { d1 = rp[o1 + row]; dv1 = dinv[o1 + row]; }
+    }
+    xv0 += Out[b0][threadIdx.x];
+    xv1 += Out[b1][threadIdx.x];
+    if (rp) {
+      // up to 32 loads of K P per instance in flight before their products
+      // (one round for k <= 32)
+      constexpr int KC = 32;
+      const float *kp0 = c.KP32 + (size_t)b0 * k * n + row;
+      const float *kp1 = c.KP32 + (size_t)b1 * k * n + row;
+      for (int j0 = 0; j0 < k; j0 += KC) {
+        float kv0[KC], kv1[KC];
+#pragma unroll
+        for (int u = 0; u < KC; ++u) {
+          kv0[u] = (l0 && j0 + u < k) ? kp0[(size_t)(j0 + u) * n] : 0.f;
+          kv1[u] = (l1 && j0 + u < k) ? kp1[(size_t)(j0 + u) * n] : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < KC; ++u) {
+          const int j = j0 + u < MAXK ? j0 + u : 0;
+          d0 -= kv0[u] * E[j][b0];
+          d1 -= kv1[u] * E[j][b1];
+        }
+      }
+      xv0 += (float)c.omega * dv0 * d0;
+      xv1 += (float)c.omega * dv1 * d1;
+    }
+    if (l0) xout[o0 + row] = xv0;
+    if (l1) xout[o1 + row] = xv1;
   }
 }
 
