@@ -854,14 +854,29 @@ __global__ void __launch_bounds__(NT) k_ptr_b(Ctx c, const float *__restrict__ R
   const float *P = (const float *)c.sP;
   for (int blk = g * per; blk < blk_end; ++blk) {
     const int row = blk * NT + w * WAVE + lane;
-    // every load of the block's residuals and basis rows issued before the
-    // LDS stores (fixed trip counts, guarded)
+    // the block's residuals and basis rows, sixteen loads in flight at a
+    // time: the addresses are clamped into range so that every load is
+    // unconditional (a guarded load becomes a branch, and the compiler then
+    // waits for each load before the next), and entries past the batch, k
+    // or n are zeroed afterwards
+    constexpr int LG = 16;
+    const int rowc = row < n ? row : n - 1;
+    for (int b0 = 0; b0 < B; b0 += LG) {
+      float v[LG];
 #pragma unroll
-    for (int b = 0; b < MAXB; ++b)
-      if (b < B) Rw[w][b][lane] = (live[b] && row < n) ? R[(size_t)b * n + row] : 0.f;
+      for (int u = 0; u < LG; ++u) v[u] = R[(size_t)(b0 + u < B ? b0 + u : B - 1) * n + rowc];
 #pragma unroll
-    for (int j = 0; j < MAXK; ++j)
-      if (j < k) Pw[j * PW_LD + threadIdx.x] = row < n ? P[(size_t)j * n + row] : 0.f;
+      for (int u = 0; u < LG; ++u)
+        if (b0 + u < B) Rw[w][b0 + u][lane] = (live[b0 + u] && row < n) ? v[u] : 0.f;
+    }
+    for (int j0 = 0; j0 < k; j0 += LG) {
+      float v[LG];
+#pragma unroll
+      for (int u = 0; u < LG; ++u) v[u] = P[(size_t)(j0 + u < k ? j0 + u : k - 1) * n + rowc];
+#pragma unroll
+      for (int u = 0; u < LG; ++u)
+        if (j0 + u < k) Pw[(j0 + u) * PW_LD + threadIdx.x] = row < n ? v[u] : 0.f;
+    }
     __syncthreads();
 #pragma unroll
     for (int m = 0; m < MT; ++m) {
@@ -966,11 +981,23 @@ __global__ void __launch_bounds__(NT) k_prolong_b(Ctx c, const float *__restrict
     for (int b = 0; b < B; ++b) m += live[b];
     nlive = m;
   }
+  {
+    // coarse corrections into LDS: all loads first (addresses clamped into
+    // range, so none is guarded), then the stores with the padding zeroed
+    constexpr int EU = MAXK * MAXB / NT;
+    float ev[EU];
 #pragma unroll
-  for (int u = 0; u < MAXK * MAXB / NT; ++u) {
-    const int t = threadIdx.x + u * NT;
-    const int j = t / MAXB, b = t % MAXB;
-    E[j][b] = (j < k && b < B) ? (float)c.ec[(size_t)b * MAXK + j] : 0.f;
+    for (int u = 0; u < EU; ++u) {
+      const int t = threadIdx.x + u * NT;
+      const int j = t / MAXB, b = t % MAXB;
+      ev[u] = (float)c.ec[(size_t)(b < B ? b : B - 1) * MAXK + (j < k ? j : k - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < EU; ++u) {
+      const int t = threadIdx.x + u * NT;
+      const int j = t / MAXB, b = t % MAXB;
+      E[j][b] = (j < k && b < B) ? ev[u] : 0.f;
+    }
   }
   __syncthreads();
   if (nlive == 0) return;
@@ -1011,7 +1038,10 @@ __global__ void __launch_bounds__(NT) k_prolong_b(Ctx c, const float *__restrict
   // together (each instance's arithmetic does not depend on its partner)
   for (int b0 = 0; b0 < B; b0 += 2) {
     const int b1 = b0 + 1;   // < MAXB: E and Out hold zeros past the batch
-    const bool l0 = live[b0] != 0, l1 = b1 < B && live[b1] != 0;
+    // the same for the whole workgroup: scalar branches, so that the loads
+    // inside are not guarded one by one
+    const bool l0 = __builtin_amdgcn_readfirstlane(live[b0]) != 0;
+    const bool l1 = b1 < B && __builtin_amdgcn_readfirstlane(live[b1]) != 0;
     if (!l0 && !l1) continue;
     const size_t o0 = (size_t)b0 * n, o1 = (size_t)b1 * n;
     float xv0 = 0.f, xv1 = 0.f, d0 = 0.f, d1 = 0.f, dv0 = 0.f, dv1 = 0.f;
@@ -1030,13 +1060,23 @@ __global__ void __launch_bounds__(NT) k_prolong_b(Ctx c, const float *__restrict
       // (one round for k <= 32)
       constexpr int KC = 32;
       const float *kp0 = c.KP32 + (size_t)b0 * k * n + row;
-      const float *kp1 = c.KP32 + (size_t)b1 * k * n + row;
+      const float *kp1 = c.KP32 + (size_t)(l1 ? b1 : b0) * k * n + row;
       for (int j0 = 0; j0 < k; j0 += KC) {
+        // K P rows past k are read at k - 1 (in range) and meet zeros in E
         float kv0[KC], kv1[KC];
+        if (l0) {
 #pragma unroll
-        for (int u = 0; u < KC; ++u) {
-          kv0[u] = (l0 && j0 + u < k) ? kp0[(size_t)(j0 + u) * n] : 0.f;
-          kv1[u] = (l1 && j0 + u < k) ? kp1[(size_t)(j0 + u) * n] : 0.f;
+          for (int u = 0; u < KC; ++u) kv0[u] = kp0[(size_t)(j0 + u < k ? j0 + u : k - 1) * n];
+        } else {
+#pragma unroll
+          for (int u = 0; u < KC; ++u) kv0[u] = 0.f;
+        }
+        if (l1) {
+#pragma unroll
+          for (int u = 0; u < KC; ++u) kv1[u] = kp1[(size_t)(j0 + u < k ? j0 + u : k - 1) * n];
+        } else {
+#pragma unroll
+          for (int u = 0; u < KC; ++u) kv1[u] = 0.f;
         }
 #pragma unroll
         for (int u = 0; u < KC; ++u) {
