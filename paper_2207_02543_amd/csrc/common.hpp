@@ -156,14 +156,24 @@ __device__ __forceinline__ bool arrive_last(Arrival *a, int blk, unsigned total,
 __device__ __forceinline__ double strided_sum(const double *part, int first, int m, int step,
                                               int stride) {
   double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (m <= 0) return 0.0;
   int i = first;
   for (; i + 7 * step < m; i += 8 * step) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) a[u] += part[(size_t)(i + u * step) * stride];
   }
+  // the remainder: indices clamped into range so that no load is guarded
+  // (a guarded load is a branch, and the compiler then waits for each
+  // before the next), the surplus discarded afterwards
+  double v[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int iu = i + u * step;
+    v[u] = part[(size_t)(iu < m ? iu : m - 1) * stride];
+  }
 #pragma unroll
   for (int u = 0; u < 8; ++u)
-    if (i + u * step < m) a[u] += part[(size_t)(i + u * step) * stride];
+    if (i + u * step < m) a[u] += v[u];
   return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
@@ -176,11 +186,15 @@ __device__ __forceinline__ double strided_sum_wide(const double *part, int first
   double total = 0.0;
   for (int base = first; base < m; base += WIDE * step) {
     double v[WIDE];
+    // unguarded loads (clamped into range, zeroed afterwards), all in flight
 #pragma unroll
     for (int u = 0; u < WIDE; ++u) {
       const int i = base + u * step;
-      v[u] = i < m ? part[(size_t)i * stride] : 0.0;
+      v[u] = part[(size_t)(i < m ? i : m - 1) * stride];
     }
+#pragma unroll
+    for (int u = 0; u < WIDE; ++u)
+      if (base + u * step >= m) v[u] = 0.0;
 #pragma unroll
     for (int w = 1; w < WIDE; w <<= 1)
 #pragma unroll

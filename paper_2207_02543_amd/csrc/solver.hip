@@ -353,15 +353,18 @@ __global__ void __launch_bounds__(NT) k_restrict(Ctx c, const T *__restrict__ x,
   const int ncol = (c.k - w + NWAVE - 1) / NWAVE;
   for (int q0 = 0; q0 < ncol; q0 += 4) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    // unguarded loads (a guarded load is a branch, and the compiler then
+    // waits for each before the next): rows past n read row n - 1 and meet
+    // r' = 0, columns past this wave's share read column k - 1 and are
+    // discarded
 #pragma unroll
     for (int cc = 0; cc < 4; ++cc) {
-      if (q0 + cc < ncol) {
-        const T *Pj = P + (size_t)(w + (q0 + cc) * NWAVE) * c.n;
+      const int j = w + (q0 + cc) * NWAVE;
+      const T *Pj = P + (size_t)(j < c.k ? j : c.k - 1) * c.n;
 #pragma unroll
-        for (int m = 0; m < NT / WAVE; ++m) {
-          const int rr = row0 + lane + m * WAVE;
-          if (rr < c.n) acc[cc] += (double)Pj[rr] * rsh[lane + m * WAVE];
-        }
+      for (int m = 0; m < NT / WAVE; ++m) {
+        const int rr = row0 + lane + m * WAVE;
+        acc[cc] += (double)Pj[rr < c.n ? rr : c.n - 1] * rsh[lane + m * WAVE];
       }
     }
 #pragma unroll
@@ -380,7 +383,19 @@ __global__ void __launch_bounds__(NT) k_restrict(Ctx c, const T *__restrict__ x,
   // those of the partials
   extern __shared__ double Ls[];
   const double *Li = c.Linv + (size_t)b * k * k;
-  for (int t = threadIdx.x; t < k * k; t += NT) Ls[t] = Li[t];
+  for (int t0 = 0; t0 < k * k; t0 += 4 * NT) {
+    double lv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u * NT + threadIdx.x;
+      lv[u] = Li[t < k * k ? t : k * k - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u * NT + threadIdx.x;
+      if (t < k * k) Ls[t] = lv[u];
+    }
+  }
   // r_c: tpc threads per column, each summing a strided share of the
   // column's partials, then the shares in order
   const int tpc = NT / k;
