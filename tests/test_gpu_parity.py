@@ -300,3 +300,38 @@ def test_offline_pipeline_matches_direct_solves(env):
     P, lam = opod.pod_basis(U, 5)
     Pg = Pg.cpu().numpy().T
     np.testing.assert_allclose(Pg @ Pg.T, P @ P.T, atol=1e-7)
+
+
+@pytest.mark.parametrize("dim,N,nu,prec,batch", [
+    (2, 24, 1, "fp64", 2), (2, 24, 3, "fp64", 2), (2, 24, 1, "mixed", 4),
+    (3, 6, 1, "mixed", 4), (3, 6, 3, "mixed", 4), (3, 6, 3, "fp64", 2)])
+def test_pcg_other_sweep_counts_match_oracle(env, dim, N, nu, prec, batch):
+    """PCG with nu pre- and nu post-relaxation sweeps (one: the cycle ends in
+    the pass that forms s, after the K P form of the first post-sweep; three:
+    a plain pre-sweep after the fused update and two post-sweeps), one
+    instance at a time (FP64) and batched (FP32 cycle, MFMA products),
+    against the oracle with the same sweep counts."""
+    torch, capi, pipeline = env
+    flush(f"pcg sweeps nu={nu} dim={dim} N={N} {prec} batch={batch}")
+    w = I.with_(I.small(dim, N, k=6, n_train=12), nu_pre=nu, nu_post=nu)
+    P, lam, U = _basis(w)
+    queries = [oprob.query(w, I.query_xi(w, j), I.noise(w, j)) for j in range(batch)]
+    precision = capi.MIXED if prec == "mixed" else capi.FP64
+    prob = pipeline.Problem(w)
+    sysm = prob.alloc_system(batch, fp32=(prec == "mixed"))
+    prob.assemble(sysm, np.stack([q.xi for q in queries]))
+    pr = prob.setup(sysm, torch.tensor(np.ascontiguousarray(P.T), device="cuda"), precision=precision,
+                    nu_pre=nu, nu_post=nu)
+    u = torch.tensor(np.stack([q.x0 for q in queries]), device="cuda")
+    beta = capi.BETA_PR if prec == "mixed" else capi.BETA_FR
+    ret, it, rr, st = prob.solve(sysm, pr, u, beta=beta)
+    assert ret == capi.OK, st
+    uh = u.cpu().numpy()
+    for j, q in enumerate(queries):
+        ref = oprob.solve_query(w, q, P, precision="fp32" if prec == "mixed" else "fp64",
+                                beta="pr" if prec == "mixed" else "fr")
+        assert ref.status == opcg.OK
+        flush(f"  query {j}: gpu iters {it[j]}; oracle iters {ref.iters}")
+        assert abs(it[j] - ref.iters) <= 2
+        assert rr[j] <= w.tol
+        assert relerr(uh[j], ref.u) <= 1e-6
