@@ -82,11 +82,15 @@ def test_cycle_error_operator(dim, N, k, omega, nu1, nu2):
     np.testing.assert_allclose(np.eye(n) - B @ Kd, E, atol=1e-11)
 
 
-@pytest.mark.parametrize("dim,N,k,omega", [(2, 4, 4, 2 / 3), (2, 6, 3, 2 / 3), (3, 2, 4, 0.5), (3, 3, 5, 0.5)])
-def test_preconditioner_spd_and_unit_eigenvalues(dim, N, k, omega):
+@pytest.mark.parametrize("dim,N,k,omega,nu", [
+    (2, 4, 4, 2 / 3, 2), (2, 6, 3, 2 / 3, 2), (3, 2, 4, 0.5, 2), (3, 3, 5, 0.5, 2),
+    (2, 4, 4, 2 / 3, 1), (2, 4, 4, 2 / 3, 3), (3, 2, 4, 0.5, 1), (3, 2, 4, 0.5, 3)])
+def test_preconditioner_spd_and_unit_eigenvalues(dim, N, k, omega, nu):
+    """Equal pre- and post-relaxation counts give a symmetric positive
+    definite B with BK's spectrum in (0, 1] and at least k unit eigenvalues."""
     w, K, P, U = _tiny(dim, N, k, omega)
     n = K.shape[0]
-    B = _dense_B(twogrid.TwoGrid(K, P, omega), n)
+    B = _dense_B(twogrid.TwoGrid(K, P, omega, nu, nu), n)
     assert np.abs(B - B.T).max() <= 1e-12 * np.abs(B).max()
     assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0.0
     ev = np.sort(np.linalg.eigvals(B @ K.toarray()).real)
