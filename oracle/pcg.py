@@ -39,6 +39,8 @@ class Result:
     status: int
     directions: list = field(default_factory=list)   # p_k (when recorded)
     rnorms: list = field(default_factory=list)       # recursive ||r_k||
+    replacements: list = field(default_factory=list)  # iterations at which the
+                                                      # true residual replaced r
 
 
 def pcg(K, f, u0, precond=None, tol=1e-8, maxit=5000, beta="fr",
@@ -96,6 +98,7 @@ def pcg(K, f, u0, precond=None, tol=1e-8, maxit=5000, beta="fr",
                 return finish(OK)
             r = rt                       # residual replacement
             restart = True
+            res.replacements.append(k)
         s_prev = s
         s = apply(r)
         rho_new = float(r @ s)

@@ -84,6 +84,21 @@ def gauss_seidel_sweeps(K, b, x, order, nsweeps, backward=False):
     return x
 
 
+def residual(K, b, x):
+    """r' = b - K x, recomputed after pre-relaxation (Alg. 2)."""
+    return b - K @ x
+
+
+def restrict(P, rr):
+    """r_c = P^T r' (Alg. 2 restriction with P = Phi_r, Sec. 3.3 Eq. 30)."""
+    return P.T @ rr
+
+
+def prolong(x, P, ec):
+    """x + P e_c (Alg. 2 prolongation and correction)."""
+    return x + P @ ec
+
+
 def coarse_matrix(K, P):
     """K_c = P^T K P (Alg. 2, restrict-and-solve step; Sec. 3.3 Eq. 28)."""
     return P.T @ (K @ P)
@@ -142,25 +157,29 @@ class TwoGrid:
         x = np.zeros_like(r)
         x = self._relax(K, dinv, r, x, w, self.nu_pre, False)
         if self.L is not None:
-            rr = r - K @ x
-            rc = P.T @ rr
+            rr = residual(K, r, x)
+            rc = restrict(P, rr)
             ec = coarse_solve(self.L, rc)
-            x = x + P @ ec
+            x = prolong(x, P, ec)
         x = self._relax(K, dinv, r, x, w, self.nu_post, True)
         return x
 
     # -- FP32-emulated cycle (coarse solve in FP64) --------------------------
     def _cycle32(self, r, scale):
+        # every operand of the relaxation, residual, restriction and
+        # prolongation is binary32, so numpy and scipy compute each of these
+        # steps in binary32 (no rounding of a wider result afterwards); only
+        # the coarse solve widens its input to FP64 and rounds its output
         K, dinv, P, w = self.K32, self.dinv32, self.P32, self.omega32
         b = (r * scale).astype(np.float32)
         x = np.zeros_like(b)
-        x = self._relax(K, dinv, b, x, w, self.nu_pre, False).astype(np.float32)
+        x = self._relax(K, dinv, b, x, w, self.nu_pre, False)
         if self.L is not None:
-            rr = (b - K @ x).astype(np.float32)
-            rc = (P.T @ rr).astype(np.float32)
+            rr = residual(K, b, x)
+            rc = restrict(P, rr)
             ec = coarse_solve(self.L, rc.astype(np.float64)).astype(np.float32)
-            x = (x + P @ ec).astype(np.float32)
-        x = self._relax(K, dinv, b, x, w, self.nu_post, True).astype(np.float32)
+            x = prolong(x, P, ec)
+        x = self._relax(K, dinv, b, x, w, self.nu_post, True)
         return x.astype(np.float64) / scale
 
     def apply(self, r, scale=None):

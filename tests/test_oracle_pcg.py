@@ -171,3 +171,53 @@ def test_standalone_twogrid_one_cycle_with_full_basis():
     M = twogrid.TwoGrid(q.K, np.eye(n), w.omega)
     res = pcg.twogrid_solve(q.K, q.f, q.x0, M, tol=1e-10, maxit=5)
     assert res.status == pcg.OK and res.iters == 1
+
+
+# -- residual replacement (the exit check on the true residual) ------------------
+def _replacement_case(precision):
+    w = I.small(2, 16, k=6, n_train=12)
+    P, lam, U = problem.basis(w, I.train_xis(w))
+    q = problem.query(w, I.query_xi(w, 0), I.noise(w, 0))
+    M = twogrid.TwoGrid(q.K, P, w.omega, 2, 2, precision=precision)
+    return w, q, M, ("pr" if precision == "fp32" else "fr")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_replacement_is_a_restart_from_the_true_residual(precision):
+    """At 1e-14 the recursive residual passes the test one iteration before
+    the true residual does, so the exit check replaces r by f - K u.  The
+    replacement must act as a CG restart: the iterates after it are exactly
+    those of a fresh PCG started from the iterate where it happened (r_0 =
+    f - K u, s_0 = B r_0, p_0 = s_0, rho = r_0^T s_0), and the solve ends
+    when the true residual passes."""
+    w, q, M, beta = _replacement_case(precision)
+    tol = 1e-14
+    full = pcg.pcg(q.K, q.f, q.x0, M, tol=tol, maxit=500, beta=beta, record=True)
+    assert full.status == pcg.OK and full.relres <= tol
+    assert len(full.replacements) >= 1
+    k0 = full.replacements[0]
+    thresh = tol * np.linalg.norm(q.f)
+    # at k0 the recursive residual had passed, the true one had not
+    assert full.rnorms[k0 - 1] <= thresh
+    head = pcg.pcg(q.K, q.f, q.x0, M, tol=tol, maxit=k0, beta=beta)
+    assert head.iters == k0 and head.status == pcg.EMAXIT
+    assert np.linalg.norm(q.f - q.K @ head.u) > thresh
+    tail = pcg.pcg(q.K, q.f, head.u, M, tol=tol, maxit=500, beta=beta)
+    assert tail.status == pcg.OK
+    assert k0 + tail.iters == full.iters
+    assert np.array_equal(tail.u, full.u)
+    assert tail.relres == full.relres
+
+
+def test_replacement_below_attainable_accuracy_ends_at_the_limit():
+    """A tolerance below what FP64 residuals can show (1e-16): the recursive
+    residual keeps passing, every exit check fails, the true residual keeps
+    replacing it, and the solve ends with EMAXIT at maxit, reporting the true
+    residual of the final iterate (which is near FP64 rounding)."""
+    w, q, M, beta = _replacement_case("fp32")
+    res = pcg.pcg(q.K, q.f, q.x0, M, tol=1e-16, maxit=120, beta=beta)
+    assert res.status == pcg.EMAXIT and res.iters == 120
+    assert len(res.replacements) >= 3
+    true = np.linalg.norm(q.f - q.K @ res.u) / np.linalg.norm(q.f)
+    assert res.relres == true
+    assert 1e-16 < true < 1e-13

@@ -231,3 +231,107 @@ def test_sgs_cycle_symmetric_pd_and_error_operator():
     e = rng.standard_normal(n)
     for S in (Sf, Sb):
         assert (S @ e) @ Kd @ (S @ e) < e @ Kd @ e
+
+
+# -- FP32 mode: every step of the cycle runs in binary32 --------------------------
+def test_fp32_cycle_steps_run_in_binary32(monkeypatch):
+    """Each relaxation, residual, restriction and prolongation of the FP32
+    cycle receives only binary32 operands and returns binary32 (so it is
+    computed in binary32, not computed wider and rounded afterwards); the
+    coarse solve gets an input that round-trips binary32 and its output is
+    rounded to binary32.  A step left in FP64 (an FP64 P, K, D^-1, omega or
+    vector) fails here."""
+    w, K, P, U = _tiny(2, 8, 4, 2 / 3)
+    M32 = twogrid.TwoGrid(K, P, 2 / 3, 2, 2, precision="fp32")
+    calls = []
+
+    def spy(name, fn):
+        def wrapped(*args, **kw):
+            out = fn(*args, **kw)
+            calls.append((name, args, out))
+            return out
+        return wrapped
+
+    for name in ("jacobi_sweeps", "residual", "restrict", "prolong", "coarse_solve"):
+        monkeypatch.setattr(twogrid, name, spy(name, getattr(twogrid, name)))
+    r = np.random.default_rng(5).standard_normal(K.shape[0])
+    M32(r)
+    names = [c[0] for c in calls]
+    assert names == ["jacobi_sweeps", "residual", "restrict", "coarse_solve", "prolong",
+                     "jacobi_sweeps"]
+    for name, args, out in calls:
+        if name == "coarse_solve":
+            rc = args[1]
+            assert rc.dtype == np.float64
+            assert np.array_equal(rc.astype(np.float32).astype(np.float64), rc)
+            continue
+        for a in args:
+            if isinstance(a, (int,)) and not isinstance(a, np.generic):
+                continue                                   # sweep count
+            dt = a.dtype
+            assert dt == np.float32, (name, dt)
+        assert out.dtype == np.float32, name
+    # the coarse correction reaches prolong as binary32 values
+    ec = [c for c in calls if c[0] == "prolong"][0][1][2]
+    assert ec.dtype == np.float32
+
+
+def _f32_row_loop(K32, x32):
+    """(K x)_i as a plain binary32 loop: each product rounded, then added to
+    the running sum in column order and rounded."""
+    K32 = K32.tocsr()
+    K32.sort_indices()
+    y = np.zeros(K32.shape[0], dtype=np.float32)
+    for i in range(K32.shape[0]):
+        acc = np.float32(0.0)
+        for jj in range(K32.indptr[i], K32.indptr[i + 1]):
+            acc = np.float32(acc + np.float32(K32.data[jj] * x32[K32.indices[jj]]))
+        y[i] = acc
+    return y
+
+
+def test_fp32_jacobi_sweep_and_restriction_elementwise():
+    """One binary32 damped-Jacobi sweep and the binary32 restriction against
+    plain binary32 loops in a fixed summation order, element by element, to
+    the rounding bound of binary32 sums (u = 2^-24 per operation)."""
+    w, K, P, U = _tiny(2, 6, 4, 2 / 3)
+    M32 = twogrid.TwoGrid(K, P, 2 / 3, 1, 1, precision="fp32")
+    rng = np.random.default_rng(9)
+    n = K.shape[0]
+    b = rng.standard_normal(n).astype(np.float32)
+    x = rng.standard_normal(n).astype(np.float32)
+    u = 2.0 ** -24
+    got = twogrid.jacobi_sweeps(M32.K32, M32.dinv32, b, x, M32.omega32, 1)
+    assert got.dtype == np.float32
+    kx = _f32_row_loop(M32.K32, x)
+    wd = (M32.omega32 * M32.dinv32).astype(np.float32)
+    ref = np.empty(n, dtype=np.float32)
+    for i in range(n):
+        ri = np.float32(b[i] - kx[i])
+        ref[i] = np.float32(x[i] + np.float32(wd[i] * ri))
+    absK = abs(M32.K32).astype(np.float64)
+    bound = 8 * u * (np.abs(x) + np.abs(wd) * (np.abs(b) + absK @ np.abs(x).astype(np.float64)))
+    assert np.all(np.abs(got.astype(np.float64) - ref) <= bound)
+    # restriction r_c = P^T r' with every product and sum rounded to binary32
+    rr = twogrid.residual(M32.K32, b, got)
+    assert rr.dtype == np.float32
+    rc = twogrid.restrict(M32.P32, rr)
+    assert rc.dtype == np.float32
+    for j in range(P.shape[1]):
+        acc = np.float32(0.0)
+        for i in range(n):
+            acc = np.float32(acc + np.float32(M32.P32[i, j] * rr[i]))
+        s_abs = float(np.abs(M32.P32[:, j].astype(np.float64)) @ np.abs(rr.astype(np.float64)))
+        assert abs(float(rc[j]) - float(acc)) <= 2 * n * u * s_abs
+
+
+def test_fp32_cycle_differs_from_fp64_at_binary32_level():
+    """The FP32 cycle's departure from the FP64 cycle is of binary32 size:
+    above FP64 rounding (so the mode is not secretly FP64) and below a
+    binary32 bound."""
+    w, K, P, U = _tiny(2, 8, 4, 2 / 3)
+    r = np.random.default_rng(6).standard_normal(K.shape[0])
+    s64 = twogrid.TwoGrid(K, P, 2 / 3)(r)
+    s32 = twogrid.TwoGrid(K, P, 2 / 3, precision="fp32")(r)
+    d = np.linalg.norm(s32 - s64) / np.linalg.norm(s64)
+    assert 1e-9 < d < 1e-5
