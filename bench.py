@@ -28,8 +28,11 @@ HBM_PEAK_GBS = 8000.0
 KERNELS = {"spmv_pq": 1, "sweep": 2, "sweep_final": 3, "restrict": 4, "prolong": 5, "update": 6}
 
 
+T_START = time.perf_counter()
+
+
 def log(msg):
-    print(msg, file=sys.stderr, flush=True)
+    print(f"{msg}  (+{time.perf_counter() - T_START:.0f} s)", file=sys.stderr, flush=True)
 
 
 # the kernel with the largest share of a step's time on each workload
@@ -118,39 +121,186 @@ def plain_baseline(prob, P, xi_d, x0, ustar, count, chunk):
             "path": "FP64 cycle and PCG, one query per solve (batch 1), captured chunks"}
 
 
-# above this many unknowns one oracle solve (a scipy assembly of the whole
-# matrix, then PCG) alone takes minutes, beyond any bounded sample
-CPU_BASELINE_MAX_N = 1_000_000
+# ---- CPU baseline: the oracle on the host's cores ------------------------------
+# The oracle runs in a child process started before this process touches the
+# GPU.  It assembles the first query's K while the GPU runs the offline phase,
+# then receives the basis and warm starts, and finishes before the timed GPU
+# steps begin, so the two never run at the same time.
+
+def host_cpu():
+    """(model name, usable cores) of the host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    # a host shared by several GPUs gives each a share of its cores, stated
+    # in OMP_NUM_THREADS
+    share = os.environ.get("OMP_NUM_THREADS", "")
+    if share.isdigit() and int(share) > 0:
+        cores = min(cores, int(share))
+    return model, cores
 
 
-def cpu_baseline(w, xis, x0s, P, seconds):
-    """Time the oracle's online phase (assembly, two-grid setup, PCG) on the
-    host for a bounded sample of the same queries."""
-    if w.n > CPU_BASELINE_MAX_N:
-        return {"value": None, "unit": "solves/s", "cores": 1, "kind": "oracle",
-                "sample": f"skipped: one oracle solve of workload {w.name} (n = {w.n}) exceeds the "
-                          f"bounded sample; the c3 line times the oracle at n = 811,200"}
+def _oracle_leg(conn, wname, overrides, nq, seconds, full_max_n, sample_iters):
+    """Child process: times the oracle's online phase for the queries of
+    workload `wname` on 1 host thread and on every usable core.  Queries are
+    solved in full while the time bound allows (n <= full_max_n); larger
+    workloads time assembly, setup and `sample_iters` PCG iterations of one
+    query, from which the parent extrapolates."""
     import numpy as np
     from threadpoolctl import threadpool_limits
-    from oracle import fem, problem as oprob, pcg as opcg, twogrid
+    from oracle import fem, pcg as opcg, problem as oprob, twogrid
+    from paper_2207_02543_amd import inputs as I
 
-    done, t_total, iters = 0, 0.0, []
+    w = I.with_(I.WORKLOADS[wname], **overrides)
+    _, cores = host_cpu()
+    xis = I.query_xis(w, nq)
+    mixed = w.precision == "mixed"
+    t = time.perf_counter()
     with threadpool_limits(limits=1):
-        while done < len(xis) and (t_total < seconds or done == 0):
-            t = time.perf_counter()
-            K = oprob.stiffness(w, xis[done])
-            f = fem.traction_load(w.dim, w.N)
-            M = twogrid.TwoGrid(K, P, w.omega, w.nu_pre, w.nu_post,
-                                precision="fp32" if w.precision == "mixed" else "fp64")
-            r = opcg.pcg(K, f, x0s[done], M, tol=w.tol, maxit=5000,
-                         beta="pr" if w.precision == "mixed" else "fr")
-            t_total += time.perf_counter() - t
-            iters.append(r.iters)
-            done += 1
-            log(f"[bench] oracle solve {done}: {r.iters} iterations, {t_total:.1f} s so far")
-    return {"value": done / t_total, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} query solve(s) of workload {w.name} (assembly + two-grid setup + "
-                      f"PCG, oracle iterations {iters}) in {t_total:.1f} s on 1 host thread"}
+        K0 = oprob.stiffness(w, xis[0])
+    t_asm0 = time.perf_counter() - t
+    f = fem.traction_load(w.dim, w.N)
+    msg = conn.recv()
+    if msg is None:
+        return
+    P, x0s = msg["P"], msg["x0"]
+    out = {"t_assembly": t_asm0, "cores": cores, "runs": {}}
+
+    def setup(K):
+        return twogrid.TwoGrid(K, P, w.omega, w.nu_pre, w.nu_post,
+                               precision="fp32" if mixed else "fp64")
+
+    beta = "pr" if mixed else "fr"
+    for threads in sorted({1, cores}):
+        run = {"threads": threads}
+        with threadpool_limits(limits=threads):
+            if w.n <= full_max_n:
+                sols, iters, t_total, j = [], [], 0.0, 0
+                while j < len(x0s) and (t_total < seconds or j == 0):
+                    t = time.perf_counter()
+                    K = K0 if (j == 0 and threads == 1) else oprob.stiffness(w, xis[j])
+                    M = setup(K)
+                    r = opcg.pcg(K, f, x0s[j], M, tol=w.tol, maxit=5000, beta=beta)
+                    dt = time.perf_counter() - t + (t_asm0 if (j == 0 and threads == 1) else 0.0)
+                    t_total += dt
+                    iters.append(r.iters)
+                    if threads == 1:
+                        sols.append(r.u)
+                    j += 1
+                    print(f"[bench] oracle ({threads} thread{'s' * (threads > 1)}) solve {j}: "
+                          f"{r.iters} iterations, {t_total:.1f} s so far", file=sys.stderr, flush=True)
+                run.update(kind="full", solves=j, seconds=t_total, iters=iters)
+                if threads == 1:
+                    out["solutions"] = np.stack(sols)
+            else:
+                t = time.perf_counter()
+                K = K0 if threads == 1 else oprob.stiffness(w, xis[0])
+                t_asm = time.perf_counter() - t + (t_asm0 if threads == 1 else 0.0)
+                t = time.perf_counter()
+                M = setup(K)
+                t_setup = time.perf_counter() - t
+                t = time.perf_counter()
+                r = opcg.pcg(K, f, x0s[0], M, tol=w.tol, maxit=sample_iters, beta=beta)
+                t_iter = (time.perf_counter() - t) / max(1, r.iters)
+                run.update(kind="sampled", t_assembly=t_asm, t_setup=t_setup, t_iter=t_iter,
+                           iters=r.iters)
+                print(f"[bench] oracle ({threads} thread{'s' * (threads > 1)}): assembly "
+                      f"{t_asm:.1f} s, setup {t_setup:.1f} s, {t_iter:.2f} s per PCG iteration "
+                      f"({r.iters} timed)", file=sys.stderr, flush=True)
+        out["runs"][threads] = run
+    conn.send(out)
+
+
+class OracleLeg:
+    """Parent side of the CPU baseline (see _oracle_leg)."""
+
+    FULL_MAX_N = 1_000_000   # above this one oracle solve takes minutes: sample it
+
+    def __init__(self, w, nq, seconds, sample_iters=4):
+        import multiprocessing as mp
+        ctx = mp.get_context("spawn")
+        self.w = w
+        self.conn, child = ctx.Pipe()
+        overrides = {f: getattr(w, f) for f in ("batch", "precision", "tol")}
+        self.proc = ctx.Process(target=_oracle_leg, daemon=True,
+                                args=(child, w.name, overrides, nq, seconds, self.FULL_MAX_N,
+                                      sample_iters))
+        self.proc.start()
+        self.sender = None
+        self.result = None
+
+    def send(self, P_kn, x0s):
+        """Hand the basis ([k, n] device) and warm starts ([Q, n]) to the
+        child; a helper thread writes them, since the child reads them only
+        once its first assembly is done."""
+        import threading
+        import numpy as np
+        msg = {"P": np.ascontiguousarray(P_kn.cpu().numpy().T), "x0": x0s.cpu().numpy()}
+        self.sender = threading.Thread(target=self.conn.send, args=(msg,), daemon=True)
+        self.sender.start()
+
+    def wait(self, timeout=1800):
+        t = time.perf_counter()
+        if self.conn.poll(timeout):
+            self.result = self.conn.recv()
+        self.proc.join(10)
+        self.close()
+        return time.perf_counter() - t
+
+    def close(self):
+        if self.proc.is_alive():
+            if self.sender is None:
+                try:
+                    self.conn.send(None)
+                except OSError:
+                    pass
+            self.proc.join(5)
+            if self.proc.is_alive():
+                self.proc.kill()
+
+    def summary(self, gpu_iters_mean):
+        """The cpu_baseline entry: solves/s on every usable core, with the
+        one-thread figure beside it; sampled runs are extrapolated to the
+        GPU's mean iteration count (labelled as such)."""
+        res = self.result
+        if res is None:
+            return {"value": None, "unit": "solves/s", "cores": None, "kind": "oracle",
+                    "sample": "oracle leg did not finish"}
+        model, _ = host_cpu()
+        vals, desc = {}, []
+        for threads, run in sorted(res["runs"].items()):
+            if run["kind"] == "full":
+                vals[threads] = run["solves"] / run["seconds"]
+                desc.append(f"{run['solves']} query solve(s) on {threads} thread(s) in "
+                            f"{run['seconds']:.1f} s (oracle iterations {run['iters']})")
+            else:
+                per = run["t_assembly"] + run["t_setup"] + gpu_iters_mean * run["t_iter"]
+                vals[threads] = 1.0 / per
+                desc.append(f"{threads} thread(s): assembly {run['t_assembly']:.1f} s + setup "
+                            f"{run['t_setup']:.1f} s + {run['t_iter']:.2f} s per PCG iteration "
+                            f"(over {run['iters']} iterations) x {gpu_iters_mean:.0f} iterations")
+        cores = max(vals)
+        sampled = any(r["kind"] == "sampled" for r in res["runs"].values())
+        return {"value": vals[cores], "unit": "solves/s", "cores": cores, "kind": "oracle",
+                "sample": (f"workload {self.w.name}, assembly + two-grid setup + PCG per query: "
+                           + "; ".join(desc)
+                           + ("; extrapolated from the timed phases to the GPU's mean iteration "
+                              "count (one full oracle solve exceeds the bounded sample)"
+                              if sampled else "")),
+                "value_1thread": vals.get(1), "threads": cores, "cpu_model": model,
+                "extrapolated": sampled}
+
+    def solutions(self):
+        return None if self.result is None else self.result.get("solutions")
 
 
 def serve_bench(args):
@@ -236,6 +386,10 @@ def main(argv=None):
     ap.add_argument("--markers", action="store_true",
                     help="launch the k_mark_begin / k_mark_end kernels around the timed steps "
                          "(for cutting a rocprofv3 trace to them)")
+    ap.add_argument("--basis-file", default=None,
+                    help="load the offline basis from this file if it exists, else compute it "
+                         "and save it there (for repeated runs of one workload, e.g. profiling "
+                         "passes)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch parameters (no timing of candidates)")
     ap.add_argument("--warm", default="noisy", choices=["noisy", "rom", "zero"],
@@ -261,11 +415,16 @@ def main(argv=None):
     if args.workload == "c4":
         return serve_bench(args)
 
+    from paper_2207_02543_amd import inputs as I
+    w = I.WORKLOADS[args.workload]
+    # the oracle leg starts before this process touches the GPU
+    leg = None if args.no_cpu_baseline else OracleLeg(w, max(args.queries, w.batch),
+                                                      args.cpu_seconds)
+
     import numpy as np
     import torch
-    from paper_2207_02543_amd import capi as L, inputs as I, pipeline, profiling
+    from paper_2207_02543_amd import capi as L, pipeline, profiling
 
-    w = I.WORKLOADS[args.workload]
     mixed = w.precision == "mixed"
     if args.kernel is None:
         args.kernel = DOMINANT.get(w.name, "sweep")
@@ -277,12 +436,22 @@ def main(argv=None):
     # ---- offline phase and query inputs (untimed) -----------------------------
     prob = pipeline.Problem(w, dev)
     t0 = time.perf_counter()
-    P, lam, U, train_iters = pipeline.offline_basis(prob, progress=lambda m: log(f"[bench] {m}"))
-    torch.cuda.synchronize()
-    log(f"[bench] offline: {w.n_train} training solves ({sum(train_iters)} iterations) + POD "
-        f"in {time.perf_counter() - t0:.1f} s; lambda_k/lambda_1 = "
-        f"{float(lam[w.k - 1] / lam[0]):.2e}")
-    del U
+    if args.basis_file and os.path.exists(args.basis_file):
+        P = torch.load(args.basis_file, weights_only=True).to(dev)
+        if tuple(P.shape) != (w.k, w.n):
+            raise ValueError(f"{args.basis_file}: basis of shape {tuple(P.shape)}, "
+                             f"expected {(w.k, w.n)}")
+        log(f"[bench] offline basis loaded from {args.basis_file}")
+    else:
+        P, lam, U, train_iters = pipeline.offline_basis(prob,
+                                                        progress=lambda m: log(f"[bench] {m}"))
+        torch.cuda.synchronize()
+        log(f"[bench] offline: {w.n_train} training solves ({sum(train_iters)} iterations) + POD "
+            f"in {time.perf_counter() - t0:.1f} s; lambda_k/lambda_1 = "
+            f"{float(lam[w.k - 1] / lam[0]):.2e}")
+        del U
+        if args.basis_file:
+            torch.save(P.cpu(), args.basis_file)
     Q = max(args.queries, w.batch)
     xis = I.query_xis(w, Q)
     t0 = time.perf_counter()
@@ -292,6 +461,8 @@ def main(argv=None):
     xi_d = torch.tensor(xis, device=dev)
     torch.cuda.synchronize()
     log(f"[bench] {Q} query warm starts in {time.perf_counter() - t0:.1f} s")
+    if leg is not None:
+        leg.send(P, x0)
 
     # ---- timed steps ------------------------------------------------------------
     sysm = prob.alloc_system(w.batch, fp32=mixed)
@@ -336,6 +507,10 @@ def main(argv=None):
     for i in range(args.warmup):
         step(i, False)
     torch.cuda.synchronize()
+    if leg is not None:
+        # the oracle leg finishes before the timed region: they never overlap
+        waited = leg.wait()
+        log(f"[bench] oracle leg done ({waited:.1f} s waited for it)")
     L.pod2g_timer_reset(timer)
     if args.markers:
         L.check(L.pod2g_mark(0), "pod2g_mark")
@@ -353,6 +528,31 @@ def main(argv=None):
     for b, j in enumerate(idx):
         stats["err"].append(float(torch.linalg.norm(u[b] - ustar[j]) / torch.linalg.norm(ustar[j])))
     ms_k, cnt = timer.total_ms, timer.launches
+    # the oracle's solutions of the queries it solved in full, against the
+    # GPU's for the same queries (solved again after the timed region)
+    oracle_check = None
+    usol = leg.solutions() if leg is not None else None
+    if usol is not None and args.solver == "pcg":
+        m = len(usol)
+        errs, gpu_its = [], []
+        for a in range(0, m, w.batch):
+            ids = [(a + b) % Q for b in range(w.batch)]
+            sysm.xi.copy_(xi_d[ids])
+            prob.assemble(sysm)
+            prec = prob.setup(sysm, P, precision=precision, smoother=smoother)
+            u.copy_(x0[ids])
+            ret, its, rr, st = plan.solve(w.tol) if plan is not None else prob.solve(sysm, prec, u)
+            uh = u.cpu().numpy()
+            for b in range(min(w.batch, m - a)):
+                ref = usol[a + b]
+                errs.append(float(np.linalg.norm(uh[b] - ref) / np.linalg.norm(ref)))
+                gpu_its.append(its[b])
+        o_its = leg.result["runs"][1]["iters"]
+        oracle_check = {"queries": m, "err_vs_oracle_max": max(errs),
+                        "iters_gpu": gpu_its, "iters_oracle": o_its,
+                        "iters_diff_max": int(max(abs(g - o) for g, o in zip(gpu_its, o_its)))}
+        log(f"[bench] against the oracle on {m} queries: rel. error <= {max(errs):.2e}, "
+            f"iterations GPU {gpu_its} oracle {o_its}")
     if plan is not None:
         plan.close()
     L.pod2g_timer_destroy(timer)
@@ -386,7 +586,8 @@ def main(argv=None):
                    "tuning": tuning,
                    "iters_mean": float(np.mean(stats["iters"])),
                    "relres_max": float(np.max(stats["relres"])),
-                   "err_vs_fp64_max": float(np.max(stats["err"]))},
+                   "err_vs_exact_max": float(np.max(stats["err"])),
+                   "oracle_check": oracle_check},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS if achieved else None,
                      "traffic": profiling.traffic_lookup(os.path.join(ROOT, "profiles"), w.name,
@@ -402,11 +603,8 @@ def main(argv=None):
         result["plain_fp64"] = pl
         log(f"[bench] plain FP64: {pl['value']:.2f} solves/s ({pl['iters_mean']:.1f} iterations); "
             f"batched {w.precision}: x{pl['speedup_batched']:.2f}")
-    if not args.no_cpu_baseline:
-        log("[bench] timing the oracle on the host ...")
-        x0h = x0.cpu().numpy()
-        Ph = np.ascontiguousarray(P.cpu().numpy().T)
-        result["cpu_baseline"] = cpu_baseline(w, xis, x0h, Ph, args.cpu_seconds)
+    if leg is not None:
+        result["cpu_baseline"] = leg.summary(float(np.mean(stats["iters"])))
     print(json.dumps(result), flush=True)
     return 0
 

@@ -39,6 +39,7 @@ class Workload:
     nu_pre: int = 2     # pre-smoothing sweeps
     nu_post: int = 2    # post-smoothing sweeps
     tol: float = 1e-8   # relative residual ||f - K u|| / ||f||
+    train_tol: float = 1e-12  # relative residual of the training (snapshot) solves
     kl_scale: float = 0.3
     noise: float = 0.01  # warm start = exact + noise * ||exact|| * g / ||g||
 
@@ -68,7 +69,7 @@ WORKLOADS = {
     "c4b": Workload("c4b", dim=2, N=256, n_terms=12, k=20, n_train=100),
     "c4c": Workload("c4c", dim=3, N=48, n_terms=16, k=20, n_train=100, omega=0.5),
     "c5": Workload("c5", dim=3, N=128, n_terms=16, k=50, n_train=200, batch=8,
-                   precision="mixed", omega=0.5),
+                   precision="mixed", omega=0.5, train_tol=1e-8),
 }
 
 

@@ -201,42 +201,56 @@ class Plan:
             pass
 
 
-def fp64_chunk(prob: Problem, k: int, cap: int = 32, share: float = 0.5) -> int:
-    """Instances of one FP64 solve batch that fit `share` of the free HBM:
-    per instance K and D^-1, K P and the solver vectors."""
+def batch_chunk(prob: Problem, k: int, precision=L.FP64, cap: int = 32, share: float = 0.5) -> int:
+    """Instances of one solve batch that fit `share` of the free HBM: per
+    instance K and D^-1, K P and the solver vectors (the FP32 cycle adds the
+    FP32 copy of K and, in 3D, of K P)."""
     free, _ = torch.cuda.mem_get_info(prob.device)
     per = 8 * (prob.nvals + prob.n * (k + 12))
+    if precision == L.MIXED:
+        per += 4 * (prob.nvals + prob.n * (k + 2))
     return int(max(1, min(cap, share * free // per)))
 
 
+fp64_chunk = batch_chunk
+
+
 def solve_batched(prob: Problem, xis: np.ndarray, P=None, k=0, rtol=1e-12, maxit=20000,
-                  chunk=None, u0=None):
-    """Tight solves at the given parameters (FP64 two-grid PCG with the
-    basis P, or the smoother-only cycle for k = 0), `chunk` instances at a
-    time (default: as many as half the free HBM holds, at most 32).
-    Returns [len(xis), n]."""
+                  chunk=None, u0=None, precision=L.FP64, rom=False):
+    """Tight solves at the given parameters (two-grid PCG with the basis P,
+    or the smoother-only cycle for k = 0), `chunk` instances at a time
+    (default: as many as half the free HBM holds, at most 32).  precision:
+    FP64 cycle (Fletcher-Reeves beta) or the FP32 cycle under the FP64 outer
+    loop (flexible Polak-Ribiere beta); both stop on the true FP64 residual.
+    Initial guess: u0 if given, else the reduced-order solution
+    P K_c^-1 P^T f (rom=True, needs P), else zero.  Returns ([len(xis), n],
+    iterations)."""
     m = len(xis)
+    kk = P.shape[0] if P is not None else k
     if chunk is None:
-        chunk = fp64_chunk(prob, P.shape[0] if P is not None else k)
+        chunk = batch_chunk(prob, kk, precision)
+    mixed = precision == L.MIXED
     out = torch.empty(m, prob.n, dtype=torch.float64, device=prob.device)
     iters = []
     for a in range(0, m, chunk):
         b = min(m, a + chunk)
-        sysm = prob.alloc_system(b - a)
+        sysm = prob.alloc_system(b - a, fp32=mixed)
         prob.assemble(sysm, xis[a:b])
-        prec = prob.setup(sysm, P, k=k if P is None else P.shape[0], key="setup_train")
+        prec = prob.setup(sysm, P, k=kk, precision=precision, key="setup_train")
         u = out[a:b]
-        if u0 is None:
-            u.zero_()
-        else:
+        if u0 is not None:
             u.copy_(u0[a:b])
+        elif rom and P is not None:
+            prob.rom_start(sysm, prec, u)
+        else:
+            u.zero_()
         ret, it, rr, st = prob.solve(sysm, prec, u, rtol=rtol, maxit=maxit, key="pcg_train")
         if ret != L.OK:
             raise L.Pod2gError(ret, f"training solve {a}..{b}: statuses {st}")
         iters += it
         del sysm, prec
     # the batch workspaces are sized for this call only: hand them back
-    for key in ("setup_train", "pcg_train"):
+    for key in ("setup_train", "pcg_train", "rom"):
         prob._work.pop(key, None)
     torch.cuda.empty_cache()
     return out, iters
@@ -253,18 +267,25 @@ def pod_basis(U: torch.Tensor, k: int):
     return P, lam
 
 
-def offline_basis(prob: Problem, n_train=None, k=None, rtol=1e-12, chunk=None, progress=None):
+def offline_basis(prob: Problem, n_train=None, k=None, rtol=None, chunk=None, progress=None,
+                  precision=None):
     """Offline phase (Sec. 3.4): training solves, then POD of the snapshots
     (Sec. 3.3).  The training solves are incremental: the first one uses
     the smoother-only cycle; every later group (doubling in size up to
-    `chunk`) is preconditioned by the POD basis of all snapshots so far."""
+    `chunk`) is preconditioned by the POD basis of all snapshots so far and
+    starts from that basis's reduced-order solution.  rtol: the workload's
+    training tolerance unless given; precision: the workload's cycle
+    precision unless given."""
     w = prob.w
     n_train = w.n_train if n_train is None else n_train
     k = w.k if k is None else k
+    rtol = w.train_tol if rtol is None else rtol
+    if precision is None:
+        precision = L.MIXED if w.precision == "mixed" else L.FP64
     xis = np.stack([I.train_xi(w, i) for i in range(n_train)])
     U = torch.empty(n_train, prob.n, dtype=torch.float64, device=prob.device)
     if chunk is None:
-        chunk = fp64_chunk(prob, k)
+        chunk = batch_chunk(prob, k, precision)
     iters = []
     done, size = 0, 1
     while done < n_train:
@@ -279,7 +300,8 @@ def offline_basis(prob: Problem, n_train=None, k=None, rtol=1e-12, chunk=None, p
                     if kk == 1:
                         raise
                     kk -= 1
-        Ub, its = solve_batched(prob, xis[done:b], P_cur, rtol=rtol, chunk=chunk)
+        Ub, its = solve_batched(prob, xis[done:b], P_cur, rtol=rtol, chunk=chunk,
+                                precision=precision, rom=True)
         U[done:b] = Ub
         iters += its
         if progress is not None:
@@ -289,6 +311,10 @@ def offline_basis(prob: Problem, n_train=None, k=None, rtol=1e-12, chunk=None, p
     return P, lam, U, iters
 
 
-def exact_solutions(prob: Problem, xis, P, rtol=1e-12, chunk=None):
-    u, it = solve_batched(prob, xis, P, rtol=rtol, chunk=chunk)
+def exact_solutions(prob: Problem, xis, P, rtol=1e-12, chunk=None, precision=None):
+    """Tight solves (default 1e-12) at the query parameters, from the
+    reduced-order start; precision as the workload's cycle."""
+    if precision is None:
+        precision = L.MIXED if prob.w.precision == "mixed" else L.FP64
+    u, it = solve_batched(prob, xis, P, rtol=rtol, chunk=chunk, precision=precision, rom=True)
     return u
