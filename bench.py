@@ -24,7 +24,7 @@ if ROOT not in sys.path:
 
 METRIC = ("POD-2G-PCG solves/sec at rel-residual 1e-8 (batched/mixed vs plain); "
           "SpMV HBM GB/s")
-HBM_PEAK_GBS = 8000.0
+# kernels the library can time live (pod2g_timer)
 KERNELS = {"spmv_pq": 1, "sweep": 2, "sweep_final": 3, "restrict": 4, "prolong": 5, "update": 6}
 
 
@@ -39,46 +39,6 @@ def log(msg):
 # (rocprofv3 kernel traces of the timed steps)
 DOMINANT = {"c1": "restrict", "c2": "restrict", "c4a": "restrict", "c4b": "restrict",
             "c3": "spmv_pq", "c4c": "spmv_pq", "c5": "spmv_pq"}
-
-
-def kernel_bytes(w, kernel, mixed, fuse_upd=False):
-    """Algorithmic HBM bytes of one launch of `kernel` over the batch: each
-    stored matrix value, index and vector entry moved once; what all
-    instances share (indices, basis) counted once.  fuse_upd: the update
-    kernel also applies the second pre-relaxation sweep (K, D^-1 read, x2
-    written, no stored first sweep)."""
-    S = 3 ** w.dim
-    n, nn, k, B = w.n, w.n_nodes_free, w.k, w.batch
-    nvals = n * S * w.dim
-    batched = mixed and 4 <= B <= 32 and k > 0        # MFMA products over the batch
-    fused = n * B <= (1 << 20)                          # direction update inside the SpMV
-    vb = 4 if mixed else 8                              # cycle precision
-    idx = 4 * S * nn                                    # block-column indices
-    if kernel == "sweep":        # K, x (gathered), b, D^-1 read; x_out written
-        return idx + B * (vb * nvals + 4 * vb * n)
-    if kernel == "sweep_final":  # + r (FP64) read, s (FP64) written instead of x_out
-        return idx + B * (vb * nvals + 3 * vb * n + 16 * n)
-    if kernel == "spmv_pq":      # K, p read (fused: s, p_old read, p written); q written
-        return idx + B * (8 * nvals + (32 if fused else 16) * n)
-    if kernel == "restrict":
-        if batched:              # r' = b - K x in FP32: K, x, b read; r' written
-            return idx + B * (4 * nvals + 12 * n)
-        # K, x, b read, P once; r' also written where the first post-sweep
-        # uses it with K P (FP64 path, or FP32 in 3D)
-        saved = vb * n if (not mixed or w.dim == 3) else 0
-        return idx + vb * k * n + B * (vb * nvals + 2 * vb * n + saved)
-    if kernel == "prolong":
-        # x + P e + omega D^-1 (r' - K P e) where K P is at hand (FP64 path,
-        # or FP32 in 3D): P once, K P per instance, x, r', D^-1 read, x written
-        if not mixed or w.dim == 3:
-            return vb * k * n + B * (vb * k * n + 4 * vb * n)
-        return vb * k * n + B * 2 * vb * n
-    if kernel == "update" and fuse_upd:
-        return idx + B * (vb * nvals + 48 * n + (8 * n if mixed else 0) + (4 * n if mixed else 0)
-                          + 2 * vb * n)
-    if kernel == "update":       # u, p, r, q (, s) read; u, r written; cycle input and first sweep
-        return B * (48 * n + (8 * n if mixed else 0) + (12 * n if mixed else 24 * n))
-    raise ValueError(kernel)
 
 
 def plain_baseline(prob, P, xi_d, x0, ustar, count, chunk):
@@ -164,16 +124,20 @@ def _oracle_leg(conn, wname, overrides, nq, seconds, full_max_n, sample_iters):
     _, cores = host_cpu()
     xis = I.query_xis(w, nq)
     mixed = w.precision == "mixed"
-    t = time.perf_counter()
-    with threadpool_limits(limits=1):
-        K0 = oprob.stiffness(w, xis[0])
-    t_asm0 = time.perf_counter() - t
+    # assembly of the first query on 1 thread and on every core, before the
+    # basis arrives (the GPU's offline phase runs meanwhile)
+    t_asm0 = {}
+    for threads in sorted({1, cores}):
+        t = time.perf_counter()
+        with threadpool_limits(limits=threads):
+            K0 = oprob.stiffness(w, xis[0])
+        t_asm0[threads] = time.perf_counter() - t
     f = fem.traction_load(w.dim, w.N)
     msg = conn.recv()
     if msg is None:
         return
     P, x0s = msg["P"], msg["x0"]
-    out = {"t_assembly": t_asm0, "cores": cores, "runs": {}}
+    out = {"cores": cores, "runs": {}}
 
     def setup(K):
         return twogrid.TwoGrid(K, P, w.omega, w.nu_pre, w.nu_post,
@@ -187,10 +151,10 @@ def _oracle_leg(conn, wname, overrides, nq, seconds, full_max_n, sample_iters):
                 sols, iters, t_total, j = [], [], 0.0, 0
                 while j < len(x0s) and (t_total < seconds or j == 0):
                     t = time.perf_counter()
-                    K = K0 if (j == 0 and threads == 1) else oprob.stiffness(w, xis[j])
+                    K = K0 if j == 0 else oprob.stiffness(w, xis[j])
                     M = setup(K)
                     r = opcg.pcg(K, f, x0s[j], M, tol=w.tol, maxit=5000, beta=beta)
-                    dt = time.perf_counter() - t + (t_asm0 if (j == 0 and threads == 1) else 0.0)
+                    dt = time.perf_counter() - t + (t_asm0[threads] if j == 0 else 0.0)
                     t_total += dt
                     iters.append(r.iters)
                     if threads == 1:
@@ -202,9 +166,7 @@ def _oracle_leg(conn, wname, overrides, nq, seconds, full_max_n, sample_iters):
                 if threads == 1:
                     out["solutions"] = np.stack(sols)
             else:
-                t = time.perf_counter()
-                K = K0 if threads == 1 else oprob.stiffness(w, xis[0])
-                t_asm = time.perf_counter() - t + (t_asm0 if threads == 1 else 0.0)
+                K, t_asm = K0, t_asm0[threads]
                 t = time.perf_counter()
                 M = setup(K)
                 t_setup = time.perf_counter() - t
@@ -370,7 +332,7 @@ def main(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2",
+    ap.add_argument("--workload", default="c5",
                     help="c1, c2, c3, c4a, c4b, c4c, c5; c4 = the serving stream")
     ap.add_argument("--queries", type=int, default=8, help="distinct query parameters cycled")
     ap.add_argument("--kernel", default=None, choices=sorted(KERNELS),
@@ -390,6 +352,8 @@ def main(argv=None):
                     help="load the offline basis from this file if it exists, else compute it "
                          "and save it there (for repeated runs of one workload, e.g. profiling "
                          "passes)")
+    ap.add_argument("--tuning", default=None,
+                    help="launch parameters as JSON (names as pcg_plan_config) instead of tuning")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default launch parameters (no timing of candidates)")
     ap.add_argument("--warm", default="noisy", choices=["noisy", "rom", "zero"],
@@ -423,7 +387,7 @@ def main(argv=None):
 
     import numpy as np
     import torch
-    from paper_2207_02543_amd import capi as L, pipeline, profiling
+    from paper_2207_02543_amd import capi as L, pipeline, profiling, roofline as R
 
     mixed = w.precision == "mixed"
     if args.kernel is None:
@@ -436,12 +400,15 @@ def main(argv=None):
     # ---- offline phase and query inputs (untimed) -----------------------------
     prob = pipeline.Problem(w, dev)
     t0 = time.perf_counter()
+    Q = max(args.queries, w.batch)
+    xis = I.query_xis(w, Q)
     if args.basis_file and os.path.exists(args.basis_file):
-        P = torch.load(args.basis_file, weights_only=True).to(dev)
-        if tuple(P.shape) != (w.k, w.n):
-            raise ValueError(f"{args.basis_file}: basis of shape {tuple(P.shape)}, "
-                             f"expected {(w.k, w.n)}")
-        log(f"[bench] offline basis loaded from {args.basis_file}")
+        saved = torch.load(args.basis_file, weights_only=True)
+        P, ustar = saved["P"].to(dev), saved["ustar"].to(dev)
+        if tuple(P.shape) != (w.k, w.n) or tuple(ustar.shape) != (Q, w.n):
+            raise ValueError(f"{args.basis_file}: basis {tuple(P.shape)} and solutions "
+                             f"{tuple(ustar.shape)}, expected {(w.k, w.n)} and {(Q, w.n)}")
+        log(f"[bench] offline basis and query solutions loaded from {args.basis_file}")
     else:
         P, lam, U, train_iters = pipeline.offline_basis(prob,
                                                         progress=lambda m: log(f"[bench] {m}"))
@@ -450,12 +417,13 @@ def main(argv=None):
             f"in {time.perf_counter() - t0:.1f} s; lambda_k/lambda_1 = "
             f"{float(lam[w.k - 1] / lam[0]):.2e}")
         del U
+        t0 = time.perf_counter()
+        ustar = pipeline.exact_solutions(prob, xis, P, rtol=1e-12)
+        torch.cuda.synchronize()
+        log(f"[bench] {Q} tight query solutions in {time.perf_counter() - t0:.1f} s")
         if args.basis_file:
-            torch.save(P.cpu(), args.basis_file)
-    Q = max(args.queries, w.batch)
-    xis = I.query_xis(w, Q)
+            torch.save({"P": P.cpu(), "ustar": ustar.cpu()}, args.basis_file)
     t0 = time.perf_counter()
-    ustar = pipeline.exact_solutions(prob, xis, P, rtol=1e-12)
     g = torch.tensor(np.stack([I.noise(w, j) for j in range(Q)]), device=dev)
     x0 = torch.stack([I.warm_start(ustar[j], g[j], w.noise) for j in range(Q)])
     xi_d = torch.tensor(xis, device=dev)
@@ -473,15 +441,20 @@ def main(argv=None):
     stats = {"iters": [], "relres": [], "err": []}
     plan = None
     tuning = None
+    plan_cfg = None
     if args.chunk > 0 and args.solver == "pcg":
         # capture the PCG iterations once: every step reuses these buffers
         sysm.xi.copy_(xi_d[:w.batch])
         prob.assemble(sysm)
         prec0 = prob.setup(sysm, P, precision=precision, smoother=smoother)
         plan = prob.plan(sysm, prec0, u, chunk=args.chunk, timer=timer)
-        if not args.no_tune:
+        if args.tuning:
+            plan.configure(**json.loads(args.tuning))
+        elif not args.no_tune:
             tuning = plan.tune()
             log(f"[bench] tuned launch parameters: {tuning}")
+        plan_cfg = plan.config()
+        log(f"[bench] launch parameters: {plan_cfg}")
 
     def step(i, timed):
         idx = [(i * w.batch + b) % Q for b in range(w.batch)]
@@ -562,8 +535,7 @@ def main(argv=None):
     avg_s = (ms_k / cnt) / 1e3 if cnt else float("nan")
     # the update fused with the second pre-sweep: as tuned, else the library's
     # default (small problems, Jacobi relaxation)
-    fuse_upd = (tuning["fuse_upd"] if tuning else w.n * w.batch <= (1 << 20)) and args.smoother == "jacobi"
-    nbytes = kernel_bytes(w, args.kernel, mixed, bool(fuse_upd))
+    nbytes = R.kernel_bytes(w, args.kernel, plan_cfg, args.smoother)
     achieved = nbytes / avg_s / 1e9 if cnt else None
     log(f"[bench] {solves} solves in {dt:.3f} s; mean iterations "
         f"{np.mean(stats['iters']):.1f}; {args.kernel}: {cnt} timed launches, "
@@ -588,8 +560,8 @@ def main(argv=None):
                    "relres_max": float(np.max(stats["relres"])),
                    "err_vs_exact_max": float(np.max(stats["err"])),
                    "oracle_check": oracle_check},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS if achieved else None,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": R.HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / R.HBM_PEAK_GBS if achieved else None,
                      "traffic": profiling.traffic_lookup(os.path.join(ROOT, "profiles"), w.name,
                                                          args.kernel),
                      "kernel": args.kernel, "bytes_per_launch": nbytes,

@@ -9,13 +9,18 @@ same region (rocprofv3 ``--pmc`` output).
 ``python -m paper_2207_02543_amd.profiling calib`` runs, between markers,
 three plain device copies of 256 MiB (torch ``copy_``): the reference that
 scales the FETCH_SIZE / WRITE_SIZE counters to bytes.
-``python -m paper_2207_02543_amd.profiling run --workload W --kernel K
---out DIR`` drives rocprofv3 (as child processes) over ``bench.py`` for
-that workload: one kernel trace, one FETCH_SIZE pass, one WRITE_SIZE pass
-and the two calibration passes, and prints a report with the commands, the
-trace summary, the kernel's counters, the calibration and a line
-``traffic <workload> <kernel> <bytes per launch> source <digest>`` that
-bench.py reads back while the library sources are unchanged.
+``python -m paper_2207_02543_amd.profiling run --workload W --out DIR``
+drives rocprofv3 (as child processes) over ``bench.py`` for that workload:
+one kernel trace, one FETCH_SIZE pass and one WRITE_SIZE pass over every
+iteration and setup kernel, one pass of MFMA counters over the batched
+products (batched FP32 workloads) and the two calibration passes.  The
+offline basis is computed once, outside the profiler, and loaded by every
+pass; the counter passes run the launch parameters the traced run tuned.
+It prints a report with the commands, the trace summary, per kernel the
+counter traffic against the algorithmic bytes (``roofline``), the MFMA
+counters, and one line ``traffic <workload> <kernel> <bytes per launch>
+source <digest>`` per kernel that bench.py reads back while the library
+sources are unchanged.
 """
 from __future__ import annotations
 
@@ -77,16 +82,26 @@ def calib(mib=256, reps=3):
     print(f"copied {reps} x {mib} MiB")
 
 
-# kernel name patterns of the timed kernels (bench.py --kernel)
-KERNEL_PATTERNS = {
-    "sweep": r"k_sweep<\d, \w+, false>",
-    "sweep_final": r"k_sweep<\d, \w+, true>",
-    "spmv_pq": r"k_spmv_pq<",
-    "restrict": r"k_resid32<|k_restrict<",
-    "prolong": r"k_prolong",
-    "update": r"k_update<",
-}
+from .roofline import KERNEL_PATTERNS  # noqa: E402  (kernel key -> name pattern)
+
 CALIB_BYTES = 256 * 2 ** 20   # one calibration copy reads and writes this much
+# counters of the batched MFMA products' pass (rocprofv3 --pmc; one pass
+# holds at most 8 SQ counters)
+MFMA_COUNTERS = ["SQ_INSTS_VALU_MFMA_MOPS_F32", "SQ_INSTS_VALU_MFMA_F32",
+                 "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAVES", "GRBM_GUI_ACTIVE"]
+
+
+def available(names):
+    """The counters of `names` that this GPU's profiler lists (rocprofv3 -L)."""
+    import subprocess
+    try:
+        txt = subprocess.run(["rocprofv3", "-L"], capture_output=True, text=True,
+                             timeout=120).stdout
+    except (subprocess.SubprocessError, OSError):
+        return list(names)
+    import re
+    have = set(re.findall(r"\b[A-Z][A-Z0-9_]+\b", txt))
+    return [c for c in names if c in have] or list(names)
 
 
 def source_digest():
@@ -118,60 +133,136 @@ def per_dispatch(path, pattern, counter):
     return (sum(v) / len(v), len(v)) if v else (float("nan"), 0)
 
 
-def run(workload, kernel, out, steps, extra, trace_only=False):
-    """Profile bench.py on one workload (see the module docstring)."""
+def trace_means(path):
+    """Mean duration (us) and count per kernel key over the marked region."""
+    import re
+    rows = _region(list(csv.DictReader(open(path))))
+    out = {}
+    for key, pat in KERNEL_PATTERNS.items():
+        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows
+             if re.search(pat, r["Kernel_Name"])]
+        if d:
+            out[key] = (sum(d) / len(d), len(d))
+    return out
+
+
+def run(workload, out, steps, extra, trace_only=False, mfma=True):
+    """Profile bench.py on one workload (see the module docstring): a kernel
+    trace, FETCH_SIZE and WRITE_SIZE passes over every iteration and setup
+    kernel, a pass of MFMA counters (batched workloads) and the two
+    calibration copies; returns the report text."""
     import os
+    import shlex
     import subprocess
+    from . import inputs as I, roofline as R
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    bench = [sys.executable, os.path.join(root, "bench.py"), "--workload", workload,
-             "--steps", str(steps), "--warmup", "1", "--no-cpu-baseline", "--markers",
-             "--kernel", kernel] + extra
-    calib_cmd = [sys.executable, "-m", "paper_2207_02543_amd.profiling", "calib"]
-    env = dict(os.environ, TMPDIR="/tmp", PYTHONPATH=root)
     out = os.path.abspath(out)   # the profiler runs from /tmp
     os.makedirs(out, exist_ok=True)
+    # raw profiler output (large) under /tmp; progress logs under `out`
+    raw = os.path.join("/tmp", "pod2g_prof_" + os.path.basename(out))
+    basis = os.path.join("/tmp", f"pod2g_basis_{workload}.pt")
+    bench = [sys.executable, os.path.join(root, "bench.py"), "--workload", workload,
+             "--steps", str(steps), "--warmup", "1", "--no-cpu-baseline", "--markers",
+             "--compare-plain", "0", "--basis-file", basis] + extra
+    calib_cmd = [sys.executable, "-m", "paper_2207_02543_amd.profiling", "calib"]
+    env = dict(os.environ, TMPDIR="/tmp", PYTHONPATH=root)
     cmds = []
 
     def prof(args, prog, sub, limit):
-        d = os.path.join(out, sub)
+        d = os.path.join(raw, sub)
         cmd = ["rocprofv3"] + args + ["--output-format", "csv", "-d", d, "-o", "p", "--"] + prog
-        cmds.append(" ".join(cmd))
+        cmds.append(shlex.join(cmd))
         print(f"[profiling] {sub}", file=sys.stderr, flush=True)
-        subprocess.run(cmd, check=True, env=env, cwd="/tmp", timeout=limit)
+        with open(os.path.join(out, f"{sub}_stderr.txt"), "w") as err:
+            subprocess.run(cmd, check=True, env=env, cwd="/tmp", timeout=limit, stderr=err)
         return d
 
-    pat = KERNEL_PATTERNS[kernel]
+    if not os.path.exists(basis):
+        # the offline phase once, outside the profiler
+        prep = bench[:2] + ["--workload", workload, "--steps", "1", "--warmup", "0",
+                            "--no-cpu-baseline", "--compare-plain", "0", "--basis-file", basis]
+        cmds.append(shlex.join(prep))
+        print("[profiling] offline basis", file=sys.stderr, flush=True)
+        with open(os.path.join(out, "prep_stderr.txt"), "w") as err:
+            subprocess.run(prep, check=True, env=env, timeout=1200, stderr=err)
+    allpat = "|".join(KERNEL_PATTERNS.values()) + "|k_mark"
     t = prof(["--kernel-trace"], bench, "trace", 900)
+    # the counter passes run the launch parameters the traced run tuned
+    tuning = _tuning_from(os.path.join(out, "trace_stderr.txt"))
+    if tuning is not None:
+        import json
+        bench = bench + ["--tuning", json.dumps(tuning)]
+    tfile = os.path.join(t, "p_kernel_trace.csv")
+    head = [f"# rocprofv3 summary: workload {workload}, every iteration and setup kernel",
+            "# made by (from the repository root, on the GPU machine): python -m "
+            "paper_2207_02543_amd.profiling " + shlex.join(sys.argv[1:]),
+            "# commands (run from /tmp with TMPDIR=/tmp, PYTHONPATH=<repo>; the first run",
+            "# computes the offline basis and stores it in the --basis-file, the others load it):"]
     if trace_only:
-        lines = [f"# rocprofv3 kernel trace: workload {workload}",
-                 "# commands (run from /tmp with TMPDIR=/tmp, PYTHONPATH=<repo>):"]
-        lines += [f"#   {c}" for c in cmds]
+        lines = head + [f"#   {c}" for c in cmds]
         lines += ["", "## kernel trace of the timed region (between the markers)",
-                  trace_summary(os.path.join(t, "p_kernel_trace.csv"))]
+                  trace_summary(tfile)]
         return "\n".join(lines)
-    f = prof(["--pmc", "FETCH_SIZE", "--kernel-include-regex", f"{pat}|k_mark"], bench, "fetch", 900)
-    w = prof(["--pmc", "WRITE_SIZE", "--kernel-include-regex", f"{pat}|k_mark"], bench, "write", 900)
+    f = prof(["--pmc", "FETCH_SIZE", "--kernel-include-regex", allpat], bench, "fetch", 900)
+    wr = prof(["--pmc", "WRITE_SIZE", "--kernel-include-regex", allpat], bench, "write", 900)
+    w = I.WORKLOADS[workload]
+    m, mnote = None, ""
+    if mfma and w.precision == "mixed" and w.batch >= 4:
+        names = available(MFMA_COUNTERS)
+        try:
+            m = prof(["--pmc"] + names + ["--kernel-include-regex",
+                                          r"k_ptr_b\(|k_prolong_b\(|k_mark"],
+                     bench, "mfma", 900)
+        except (subprocess.SubprocessError, OSError) as e:
+            mnote = f"MFMA counter pass failed ({names}): {e}"
     cf = prof(["--pmc", "FETCH_SIZE"], calib_cmd, "calib_fetch", 120)
     cw = prof(["--pmc", "WRITE_SIZE"], calib_cmd, "calib_write", 120)
-    fetch, nf = per_dispatch(os.path.join(f, "p_counter_collection.csv"), pat, "FETCH_SIZE")
-    write, nw = per_dispatch(os.path.join(w, "p_counter_collection.csv"), pat, "WRITE_SIZE")
     cfe, _ = per_dispatch(os.path.join(cf, "p_counter_collection.csv"), ".", "FETCH_SIZE")
     cwr, _ = per_dispatch(os.path.join(cw, "p_counter_collection.csv"), ".", "WRITE_SIZE")
     kf, kw = CALIB_BYTES / (cfe * 1024), CALIB_BYTES / (cwr * 1024)
-    traffic = fetch * 1024 * kf + write * 1024 * kw
-    lines = [f"# rocprofv3 summary: kernel {kernel} ({pat}), workload {workload}",
-             "# commands (run from /tmp with TMPDIR=/tmp, PYTHONPATH=<repo>):"]
-    lines += [f"#   {c}" for c in cmds]
-    lines += ["", "## kernel trace of the timed steps (between the markers)",
-              trace_summary(os.path.join(t, "p_kernel_trace.csv")), "",
-              "## counters of the timed steps, mean per dispatch (KiB)",
-              f"FETCH_SIZE {fetch:.1f} over {nf} dispatches",
-              f"WRITE_SIZE {write:.1f} over {nw} dispatches", "",
+    tm = trace_means(tfile)
+    lines = head + [f"#   {c}" for c in cmds]
+    lines += ["", "## kernel trace of the timed steps (between the markers)", trace_summary(tfile), "",
               f"## calibration: {CALIB_BYTES} B copies read FETCH_SIZE {cfe:.1f} KiB and write "
               f"WRITE_SIZE {cwr:.1f} KiB per dispatch",
               f"bytes per FETCH_SIZE KiB {kf * 1024:.1f}; bytes per WRITE_SIZE KiB {kw * 1024:.1f}", "",
-              f"traffic {workload} {kernel} {traffic:.0f} source {source_digest()}"]
+              "## per kernel, mean per dispatch: counter traffic (FETCH_SIZE + WRITE_SIZE, "
+              "calibrated) against the algorithmic bytes, and the algorithmic rate",
+              "kernel        calls   mean_us   algo_MB   fetch_MB   write_MB   traffic/algo   "
+              "algo_GB/s   of_8TB/s"]
+    traffic_lines = []
+    for key, pat in KERNEL_PATTERNS.items():
+        fe, nf = per_dispatch(os.path.join(f, "p_counter_collection.csv"), pat, "FETCH_SIZE")
+        wb, nw = per_dispatch(os.path.join(wr, "p_counter_collection.csv"), pat, "WRITE_SIZE")
+        if key not in tm or not nf:
+            continue
+        us, cnt = tm[key]
+        algo = R.kernel_bytes(w, key, tuning)
+        fb, wbb = fe * 1024 * kf, wb * 1024 * kw
+        rate = algo / (us * 1e-6) / 1e9
+        lines.append(f"{key:12s} {cnt:6d} {us:9.1f} {algo / 1e6:9.1f} {fb / 1e6:10.1f} "
+                     f"{wbb / 1e6:10.1f} {(fb + wbb) / algo:14.3f} {rate:11.0f} "
+                     f"{rate / R.HBM_PEAK_GBS:10.3f}")
+        traffic_lines.append(f"traffic {workload} {key} {fb + wbb:.0f} source {source_digest()}")
+    if m is not None:
+        lines += ["", "## MFMA counters of the batched products, mean per dispatch",
+                  counter_summary(os.path.join(m, "p_counter_collection.csv"))]
+    elif mnote:
+        lines += ["", "## " + mnote]
+    lines += ["", f"## launch parameters of the plan: {tuning}", ""] + traffic_lines
     return "\n".join(lines)
+
+
+def _tuning_from(path):
+    """The plan's launch parameters as bench.py logged them (None if absent)."""
+    import ast
+    import os
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        if "[bench] launch parameters:" in line:
+            return ast.literal_eval(line.split("launch parameters:", 1)[1].split("  (+")[0].strip())
+    return None
 
 
 def traffic_lookup(profiles_dir, workload, kernel):
@@ -198,12 +289,12 @@ if __name__ == "__main__":
         ap = argparse.ArgumentParser()
         ap.add_argument("run")
         ap.add_argument("--workload", required=True)
-        ap.add_argument("--kernel", default="sweep")
         ap.add_argument("--out", required=True)
-        ap.add_argument("--steps", type=int, default=2)
+        ap.add_argument("--steps", type=int, default=1)
         ap.add_argument("--trace-only", action="store_true")
+        ap.add_argument("--no-mfma", action="store_true")
         a, extra = ap.parse_known_args()
-        print(run(a.workload, a.kernel, a.out, a.steps, extra, a.trace_only))
+        print(run(a.workload, a.out, a.steps, extra, a.trace_only, not a.no_mfma))
     else:
         path = sys.argv[2]
         print(trace_summary(path) if kind == "trace" else counter_summary(path))

@@ -128,7 +128,7 @@ def test_traffic_is_reported_only_for_the_measured_sources(tmp_path):
 
 
 def test_algorithmic_bytes():
-    b = _bench()
+    from paper_2207_02543_amd import roofline as R
     w = I.WORKLOADS["c2"]
     n, nn, k = w.n, w.n_nodes_free, w.k
     assert (n, nn, k) == (131584, 65792, 20)
@@ -136,16 +136,27 @@ def test_algorithmic_bytes():
     idx = 9 * nn * 4           # block-column indices
     # restriction: K, x, b read, r' written (for the first post-sweep with
     # K P), P read once
-    assert b.kernel_bytes(w, "restrict", False) == idx + K + 3 * n * 8 + k * n * 8
-    assert b.kernel_bytes(w, "restrict", False) == 45528064
+    assert R.kernel_bytes(w, "restrict") == idx + K + 3 * n * 8 + k * n * 8
+    assert R.kernel_bytes(w, "restrict") == 45528064
     # FP32 cycle in 2D keeps the plain post-sweep: no r' to save
-    assert b.kernel_bytes(w, "restrict", True) == idx + k * n * 4 + n * 9 * 2 * 4 + 2 * n * 4
+    wm = I.with_(w, precision="mixed")
+    assert R.kernel_bytes(wm, "restrict") == idx + k * n * 4 + n * 9 * 2 * 4 + 2 * n * 4
     # outer SpMV with the direction update folded in: K, s, p_old read, p, q written
-    assert b.kernel_bytes(w, "spmv_pq", False) == idx + K + 4 * n * 8
+    assert R.kernel_bytes(w, "spmv_pq") == idx + K + 4 * n * 8
+    assert R.kernel_bytes(w, "spmv_pq", {"fuse_dir": 0}) == idx + K + 2 * n * 8
     w3 = I.WORKLOADS["c3"]
-    n3, nn3, B = w3.n, w3.n_nodes_free, w3.batch
+    n3, nn3, B, k3 = w3.n, w3.n_nodes_free, w3.batch, w3.k
     K3 = n3 * 27 * 3 * 8
     # large batch: the direction update is its own pass; p read, q written
-    assert b.kernel_bytes(w3, "spmv_pq", True) == 27 * nn3 * 4 + B * (K3 + 2 * n3 * 8)
+    assert R.kernel_bytes(w3, "spmv_pq") == 27 * nn3 * 4 + B * (K3 + 2 * n3 * 8)
+    assert R.kernel_bytes(w3, "pdir") == B * 3 * n3 * 8
+    # batched restriction products: the FP32 basis once, r' per instance
+    assert R.kernel_bytes(w3, "ptr_b") == k3 * n3 * 4 + B * n3 * 4
+    # setup: K per instance, P once, K P written per instance
+    assert R.kernel_bytes(w3, "kp") == 27 * nn3 * 4 + k3 * n3 * 8 + B * (K3 + k3 * n3 * 8)
     # the fused update costs the second sweep's matrix pass on top of the update
-    assert b.kernel_bytes(w, "update", False, fuse_upd=True) > b.kernel_bytes(w, "update", False) + K
+    assert R.kernel_bytes(w, "update", {"fuse_upd": 1}) > R.kernel_bytes(w, "update", {"fuse_upd": 0}) + K
+    # Gauss-Seidel relaxation never fuses the update with a Jacobi sweep
+    assert R.kernel_bytes(w, "update", {"fuse_upd": 1}, "sgs") == R.kernel_bytes(w, "update", {"fuse_upd": 0})
+    for key in R.KERNEL_PATTERNS:
+        assert R.kernel_bytes(w3, key) > 0
