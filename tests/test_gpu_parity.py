@@ -4,7 +4,7 @@ for the workload sizes)."""
 import numpy as np
 import pytest
 
-from gpu_helpers import block_ell_expected, flush, relerr
+from gpu_helpers import block_ell_expected, flush, maxrel, relerr
 from oracle import fem, pcg as opcg, pod as opod, problem as oprob, twogrid
 from paper_2207_02543_amd import inputs as I
 
@@ -74,9 +74,12 @@ def test_spmv_and_jacobi_match_oracle(env, dim, N):
     for b in range(3):
         K = oprob.stiffness(w, xis[b])
         ref = K @ x[b]
-        assert relerr(yd[b].cpu().numpy(), ref) < 1e-14
+        # element by element, within the rounding bound of a dot product of
+        # at most 81 terms (either side's summation order)
+        bound = 2 * 81 * np.finfo(float).eps * (abs(K) @ np.abs(x[b]))
+        assert np.all(np.abs(yd[b].cpu().numpy() - ref) <= bound)
         refj = twogrid.jacobi_sweeps(K, 1.0 / K.diagonal(), bb[b], x[b], w.omega, 3)
-        assert relerr(xj[b].cpu().numpy(), refj) < 1e-13
+        assert maxrel(xj[b].cpu().numpy(), refj) < 1e-13
 
 
 def _basis(w):
@@ -110,8 +113,12 @@ def test_cycle_matches_oracle(env, dim, N, k, nu1, nu2, prec):
         K = oprob.stiffness(w, xis[b])
         M = twogrid.TwoGrid(K, P, w.omega, nu1, nu2, precision="fp32" if prec == "mixed" else "fp64")
         ref = M(r[b])
-        tol = 1e-12 if prec == "fp64" else 2e-6
-        assert relerr(sd[b].cpu().numpy(), ref) < tol
+        # element by element (FP32: 24-bit rounding through four sweeps of
+        # up to 81-term rows and the basis products)
+        tol = 1e-12 if prec == "fp64" else 5e-6
+        got = sd[b].cpu().numpy()
+        flush(f"  {b}: max elementwise {maxrel(got, ref):.2e}, norm {relerr(got, ref):.2e}")
+        assert maxrel(got, ref) < tol
 
 
 @pytest.mark.parametrize("dim,N,k", [(2, 32, 10), (3, 5, 6)])

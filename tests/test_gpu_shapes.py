@@ -1,0 +1,193 @@
+"""Oracle parity at the launch shapes the full-size workloads take.
+
+The full-size workloads run code paths that small meshes never reach:
+
+* the batched MFMA products with two batch tiles (c3: 32 queries) and four
+  basis tiles (c5: k = 50), and ragged batches (17, 31);
+* reductions over more than 32 workgroups (multi-member arrival groups) and
+  more than 48 partials, with the sums finished by the producers or by the
+  consumers, the vector update fused with the second sweep or not;
+* the full c2 and c3 problems themselves.
+
+Each case compares the GPU with the oracle on the same seeded inputs: the
+cycle element by element, PCG by its iteration count (within 2 of the
+oracle's in the same cycle precision), its solution (within 1e-6 of the
+oracle's FP64 solution) and its true residual.  Where the oracle's direct
+solves would be too slow (c2, c3), the GPU's basis is the shared input."""
+import numpy as np
+import pytest
+
+from gpu_helpers import flush, maxrel, relerr
+from oracle import problem as oprob, twogrid
+from paper_2207_02543_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(w, P, xis, mixed):
+    import torch
+    from paper_2207_02543_amd import capi, pipeline
+    prob = pipeline.Problem(w)
+    B = len(xis)
+    sysm = prob.alloc_system(B, fp32=mixed)
+    prob.assemble(sysm, xis)
+    Pd = torch.tensor(np.ascontiguousarray(P.T), device="cuda")
+    pr = prob.setup(sysm, Pd, precision=capi.MIXED if mixed else capi.FP64)
+    assert capi.pod2g_setup_status(pr)[0] == [capi.OK] * B
+    return prob, sysm, pr
+
+
+def _cycle_check(w, P, xis, prob, pr, mixed, tol):
+    import torch
+    B = len(xis)
+    r = np.random.default_rng(21).standard_normal((B, w.n)) * 1e-2
+    rd = torch.tensor(r, device="cuda")
+    sd = torch.empty_like(rd)
+    prob.apply(pr, rd, sd)
+    s = sd.cpu().numpy()
+    worst = 0.0
+    for b in range(B):
+        K = oprob.stiffness(w, xis[b])
+        ref = twogrid.TwoGrid(K, P, w.omega, w.nu_pre, w.nu_post,
+                              precision="fp32" if mixed else "fp64")(r[b])
+        worst = max(worst, maxrel(s[b], ref))
+    flush(f"  cycle: max elementwise error over {B} instances {worst:.2e}")
+    assert worst < tol
+
+
+def _pcg_check(w, P, xis, prob, sysm, pr, mixed, plan_cfg=None, chunk=8):
+    import torch
+    from paper_2207_02543_amd import capi
+    B = len(xis)
+    queries = [oprob.query(w, xis[j], I.noise(w, j)) for j in range(B)]
+    u = torch.tensor(np.stack([q.x0 for q in queries]), device="cuda")
+    plan = prob.plan(sysm, pr, u, chunk=chunk)
+    if plan_cfg:
+        plan.configure(**plan_cfg)
+    u.copy_(torch.tensor(np.stack([q.x0 for q in queries])))
+    ret, it, rr, st = plan.solve(w.tol)
+    plan.close()
+    assert ret == capi.OK, st
+    uh = u.cpu().numpy()
+    for j, q in enumerate(queries):
+        ref = oprob.solve_query(w, q, P, precision="fp32" if mixed else "fp64",
+                                beta="pr" if mixed else "fr")
+        ref64 = ref if not mixed else oprob.solve_query(w, q, P, precision="fp64", beta="fr")
+        err = relerr(uh[j], ref64.u)
+        res = np.linalg.norm(q.f - q.K @ uh[j]) / np.linalg.norm(q.f)
+        flush(f"  {j}: gpu {it[j]} oracle {ref.iters}; error {err:.1e}; residual {res:.2e}")
+        assert abs(it[j] - ref.iters) <= 2
+        assert err <= 1e-6
+        assert res <= 1.01 * w.tol and abs(rr[j] - res) <= 1e-3 * res
+
+
+# (dim, N, k, batch): c3's shape (32 queries = two 16-wide batch tiles,
+# k = 30 = two basis tiles), c5's (k = 50 = four basis tiles, 8 queries; in
+# 3D the first post-sweep from K P), ragged batches
+@pytest.mark.parametrize("dim,N,k,batch", [(3, 5, 30, 32), (3, 6, 50, 8), (2, 12, 50, 8),
+                                           (2, 12, 20, 17), (3, 4, 30, 31)])
+def test_batched_mfma_shapes(dim, N, k, batch):
+    flush(f"batched MFMA shape dim={dim} N={N} k={k} batch={batch}")
+    w = I.small(dim, N, k=k, n_train=k + 4, precision="mixed")
+    P, lam, U = oprob.basis(w, I.train_xis(w))
+    xis = I.query_xis(w, batch)
+    prob, sysm, pr = _gpu(w, P, xis, True)
+    _cycle_check(w, P, xis, prob, pr, True, 5e-6)
+    _pcg_check(w, P, xis, prob, sysm, pr, True)
+
+
+# more than 32 workgroups per instance (2D N=128: 129 row and 65 node
+# workgroups; 3D N=16: 55 and 28+), in both places the scalar sums can be
+# finished and with the update fused or not
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("dim,N,batch,mixed", [(2, 128, 1, False), (2, 128, 4, True),
+                                               (3, 16, 1, False), (3, 16, 4, True)])
+def test_many_workgroups(dim, N, batch, mixed):
+    flush(f"many workgroups dim={dim} N={N} batch={batch} {'mixed' if mixed else 'fp64'}")
+    w = I.small(dim, N, k=8, n_train=12, precision="mixed" if mixed else "fp64")
+    P, lam, U = oprob.basis(w, I.train_xis(w))
+    xis = I.query_xis(w, batch)
+    prob, sysm, pr = _gpu(w, P, xis, mixed)
+    _cycle_check(w, P, xis, prob, pr, mixed, 5e-6 if mixed else 1e-12)
+    for cfg in ({"cons": 0, "fuse_upd": 0}, {"cons": 1, "fuse_upd": 1}):
+        flush(f"  launch parameters {cfg}")
+        _pcg_check(w, P, xis, prob, sysm, pr, mixed, cfg)
+
+
+def _workload_basis(w):
+    """The GPU's offline basis of workload w (shared input of both sides)."""
+    from paper_2207_02543_amd import pipeline
+    prob = pipeline.Problem(w)
+    P, lam, U, its = pipeline.offline_basis(prob)
+    del U
+    flush(f"  basis from {w.n_train} training solves ({sum(its)} iterations)")
+    return prob, P
+
+
+@pytest.mark.timeout(600)
+def test_full_size_c2_against_oracle():
+    """Two c2 queries (2D 256x256, FP64, one query per solve) in the timed
+    launch configuration against the oracle."""
+    import torch
+    from paper_2207_02543_amd import capi
+    w = I.WORKLOADS["c2"]
+    flush(f"full-size c2 against the oracle: n {w.n}")
+    prob, Pd = _workload_basis(w)
+    P = np.ascontiguousarray(Pd.cpu().numpy().T)
+    for j in range(2):
+        xi = I.query_xis(w, j + 1)[j:j + 1]
+        sysm = prob.alloc_system(1)
+        prob.assemble(sysm, xi)
+        pr = prob.setup(sysm, Pd)
+        q = oprob.query(w, xi[0], I.noise(w, j))
+        u = torch.tensor(q.x0[None], device="cuda")
+        plan = prob.plan(sysm, pr, u, chunk=8)
+        u.copy_(torch.tensor(q.x0[None]))
+        ret, it, rr, st = plan.solve(w.tol)
+        plan.close()
+        assert ret == capi.OK, st
+        ref = oprob.solve_query(w, q, P)
+        err = relerr(u[0].cpu().numpy(), ref.u)
+        flush(f"  query {j}: gpu {it[0]} oracle {ref.iters}; error {err:.1e}; "
+              f"residual {rr[0]:.2e}")
+        assert abs(it[0] - ref.iters) <= 2 and err <= 1e-6 and rr[0] <= w.tol
+
+
+@pytest.mark.timeout(900)
+def test_full_size_c3_query_against_oracle():
+    """The c3 batch (3D 64^3, 32 queries, FP32 cycle and MFMA products) in
+    the timed launch configuration; query 0 against the oracle's FP32-cycle
+    PCG (iterations) and FP64 PCG (solution)."""
+    import torch
+    from paper_2207_02543_amd import capi
+    w = I.WORKLOADS["c3"]
+    flush(f"full-size c3 against the oracle: n {w.n}, batch {w.batch}")
+    prob, Pd = _workload_basis(w)
+    P = np.ascontiguousarray(Pd.cpu().numpy().T)
+    xis = I.query_xis(w, w.batch)
+    # warm starts from the GPU's tight solutions (a direct solve of the 3D
+    # problem is beyond the oracle's time budget); the oracle gets the same x0
+    from paper_2207_02543_amd import pipeline
+    ustar = pipeline.exact_solutions(prob, xis, Pd)
+    g = torch.tensor(np.stack([I.noise(w, j) for j in range(w.batch)]), device="cuda")
+    x0 = torch.stack([I.warm_start(ustar[j], g[j], w.noise) for j in range(w.batch)])
+    sysm = prob.alloc_system(w.batch, fp32=True)
+    prob.assemble(sysm, xis)
+    pr = prob.setup(sysm, Pd, precision=capi.MIXED)
+    u = torch.empty_like(x0)
+    plan = prob.plan(sysm, pr, u, chunk=8)
+    u.copy_(x0)
+    ret, it, rr, st = plan.solve(w.tol)
+    plan.close()
+    assert ret == capi.OK, st
+    K = oprob.stiffness(w, xis[0])
+    from oracle import fem
+    f = fem.traction_load(w.dim, w.N)
+    q = oprob.Query(xis[0], K, f, ustar[0].cpu().numpy(), x0[0].cpu().numpy())
+    flush("  oracle query assembled")
+    ref32 = oprob.solve_query(w, q, P, precision="fp32", beta="pr")
+    flush(f"  oracle FP32-cycle PCG: {ref32.iters} iterations")
+    ref64 = oprob.solve_query(w, q, P, precision="fp64", beta="fr")
+    err = relerr(u[0].cpu().numpy(), ref64.u)
+    flush(f"  query 0: gpu {it[0]} oracle {ref32.iters}; error {err:.1e}; residual {rr[0]:.2e}")
+    assert abs(it[0] - ref32.iters) <= 2 and err <= 1e-6 and rr[0] <= w.tol

@@ -221,3 +221,34 @@ def test_replacement_below_attainable_accuracy_ends_at_the_limit():
     true = np.linalg.norm(q.f - q.K @ res.u) / np.linalg.norm(q.f)
     assert res.relres == true
     assert 1e-16 < true < 1e-13
+
+
+def test_basis_from_snapshots_solved_to_1e8():
+    """Snapshots solved iteratively to a relative residual of 1e-8 (the c5
+    training tolerance) instead of exactly: the POD basis (Sec. 3.3) moves
+    by far less than its weakest retained direction, and PCG with it takes
+    the same number of iterations on the queries."""
+    w = I.small(2, 24, k=8, n_train=16)
+    xis = I.train_xis(w)
+    f = fem.traction_load(w.dim, w.N)
+    U_exact = problem.snapshots(w, xis)
+    cols = []
+    for xi in xis:
+        K = problem.stiffness(w, xi)
+        r = pcg.pcg(K, f, np.zeros(w.n), None, tol=1e-8, maxit=20000)
+        assert r.status == pcg.OK and r.relres <= 1e-8
+        cols.append(r.u)
+    U_loose = np.stack(cols, axis=1)
+    P1, lam1 = problem.pod.pod_basis(U_exact, w.k)
+    P2, lam2 = problem.pod.pod_basis(U_loose, w.k)
+    # largest sine of the principal angles between the two spans
+    sin_max = np.linalg.norm(P2 - P1 @ (P1.T @ P2), axis=0).max()
+    # (observed 3e-8; snapshots to 1e-5 already give 3e-5)
+    assert sin_max < 1e-6
+    assert np.allclose(lam1[:w.k], lam2[:w.k], rtol=1e-7)
+    for j in range(3):
+        q = problem.query(w, I.query_xi(w, j), I.noise(w, j))
+        a = problem.solve_query(w, q, P1)
+        b = problem.solve_query(w, q, P2)
+        assert abs(a.iters - b.iters) <= 1
+        assert np.linalg.norm(a.u - b.u) <= 1e-6 * np.linalg.norm(a.u)
