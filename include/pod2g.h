@@ -190,6 +190,24 @@ size_t pod2g_apply_bytes(const pod2g_prec *prec);
 int pod2g_apply(const pod2g_prec *prec, const double *r, double *s,
                 void *work, size_t bytes, hipStream_t stream);
 
+/* ---- one cycle without allocation or workspace -----------------------------
+ * For callers that cannot allocate device memory or pass a workspace: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  pod2g_apply without the workspace: the cycle runs in a scratch
+ * array of POD2G_NOALLOC_SCRATCH_BYTES that the library holds on every GPU
+ * it runs on until the process ends (the GPU current at the call, which must
+ * be the stream's; the first call on a GPU looks the array's address up,
+ * so make it outside stream capture).  Nothing is allocated.  Every call on
+ * one GPU shares that GPU's array, which keeps the last call's contents (a
+ * call clears the state it needs itself): calls in order on one stream are
+ * safe, calls that overlap on one GPU (several streams or host threads)
+ * race and give wrong results.  Asynchronous.  Errors: EINVAL, EHIP, and
+ * ESIZE when pod2g_apply_bytes(prec) exceeds the array (FP64: about 1e6
+ * unknowns x instances).                                                   */
+#define POD2G_NOALLOC_SCRATCH_BYTES (64 * 1024 * 1024)
+int pod2g_apply_noalloc(const pod2g_prec *prec, const double *r, double *s,
+                        hipStream_t stream);
+
 /* ---- PCG (Sec. 3.4 Alg. 3; Sec. 2.1 Alg. 1 when prec == NULL) ------------
  * Solves K_b u_b = f for b < batch from the initial guesses in u (overwritten
  * by the solutions).  Stops when ||r|| <= rtol ||f|| on the recursive

@@ -106,6 +106,7 @@ _f = {
     "pod2g_setup_status": _sig("pod2g_setup_status", _i, [_PR, C.POINTER(_i), C.POINTER(_d), _vp]),
     "pod2g_apply_bytes": _sig("pod2g_apply_bytes", _sz, [_PR]),
     "pod2g_apply": _sig("pod2g_apply", _i, [_PR, _vp, _vp, _vp, _sz, _vp]),
+    "pod2g_apply_noalloc": _sig("pod2g_apply_noalloc", _i, [_PR, _vp, _vp, _vp]),
     "pcg_solve_bytes": _sig("pcg_solve_bytes", _sz, [_PP, _i, _i, _i]),
     "pcg_solve": _sig("pcg_solve", _i, [_PP, _vp, _i, _PR, _vp, _vp, _d, _i, _i, C.POINTER(_i),
                                         C.POINTER(_d), C.POINTER(_i), _vp, _sz, _vp]),
@@ -229,6 +230,13 @@ def pod2g_apply_bytes(prec: Prec) -> int:
 
 def pod2g_apply(prec: Prec, r, s, work, nbytes, stream=None) -> int:
     return _f["pod2g_apply"](C.byref(prec), _ptr(r), _ptr(s), _ptr(work), nbytes, _stream(stream))
+
+
+NOALLOC_SCRATCH_BYTES = 64 * 1024 * 1024   # POD2G_NOALLOC_SCRATCH_BYTES
+
+
+def pod2g_apply_noalloc(prec: Prec, r, s, stream=None) -> int:
+    return _f["pod2g_apply_noalloc"](C.byref(prec), _ptr(r), _ptr(s), _stream(stream))
 
 
 def pcg_solve_bytes(pat: Pattern, batch: int, k: int, precision: int) -> int:

@@ -13,6 +13,7 @@
 
 #include <math.h>
 #include <string.h>
+#include <mutex>
 #include <vector>
 
 namespace pod2g {
@@ -2594,11 +2595,12 @@ __global__ void k_apply_init(InstState *st, Arrival *arr, int batch, const doubl
   st[b] = s;
 }
 
-int pod2g_apply(const pod2g_prec *prec, const double *r, double *s, void *work, size_t bytes,
-                hipStream_t stream) {
-  if (!prec || !r || !s || !work) return POD2G_EINVAL;
-  if (check_prec(prec)) return POD2G_EINVAL;
-  if (bytes < pod2g_apply_bytes(prec)) return POD2G_ESIZE;
+}  // extern "C"
+
+// One cycle s = B r on the caller's arrays with the workspace `work`
+// (arguments already checked).
+static int apply_run(const pod2g_prec *prec, const double *r, double *s, void *work,
+                     hipStream_t stream) {
   Ctx c;
   fill_ctx(c, &prec->pat, prec->vals, prec->batch, prec, nullptr, nullptr, work);
   // the cycle reads r from c.r and writes c.s; run it on the caller's arrays
@@ -2615,6 +2617,49 @@ int pod2g_apply(const pod2g_prec *prec, const double *r, double *s, void *work, 
   }
   POD2G_HIP_CHECK(hipGetLastError());
   return POD2G_OK;
+}
+
+// Scratch of pod2g_apply_noalloc: one array per GPU the library runs on,
+// held until the process ends.  On the host its name is only a stand-in:
+// host code uses the device address hipGetSymbolAddress gives for the
+// current device (kept per device), never the name itself.
+static __device__ __align__(256) unsigned char scratch[POD2G_NOALLOC_SCRATCH_BYTES];
+constexpr int SCRATCH_MAXDEV = 64;
+static std::mutex scratch_mu;
+static void *scratch_ptr[SCRATCH_MAXDEV];
+
+static int scratch_address(void **out) {
+  int dev = -1;
+  POD2G_HIP_CHECK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAXDEV) return POD2G_EINVAL;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return POD2G_EHIP;
+    scratch_ptr[dev] = p;
+  }
+  *out = scratch_ptr[dev];
+  return POD2G_OK;
+}
+
+extern "C" {
+
+int pod2g_apply(const pod2g_prec *prec, const double *r, double *s, void *work, size_t bytes,
+                hipStream_t stream) {
+  if (!prec || !r || !s || !work) return POD2G_EINVAL;
+  if (check_prec(prec)) return POD2G_EINVAL;
+  if (bytes < pod2g_apply_bytes(prec)) return POD2G_ESIZE;
+  return apply_run(prec, r, s, work, stream);
+}
+
+int pod2g_apply_noalloc(const pod2g_prec *prec, const double *r, double *s, hipStream_t stream) {
+  if (!prec || !r || !s) return POD2G_EINVAL;
+  if (check_prec(prec)) return POD2G_EINVAL;
+  if (pod2g_apply_bytes(prec) > (size_t)POD2G_NOALLOC_SCRATCH_BYTES) return POD2G_ESIZE;
+  void *work = nullptr;
+  const int st = scratch_address(&work);
+  if (st) return st;
+  return apply_run(prec, r, s, work, stream);
 }
 
 int pod2g_spmv(const pod2g_pattern *pat, const double *vals, int batch, const double *x, double *y,
