@@ -157,7 +157,8 @@ int pod2g_assemble(const pod2g_pattern *pat, const double *xi, int batch,
  * L (pivot <= 0 -> POD2G_ENOTSPD in status[b]); with power_iters > 0 also a
  * power-iteration estimate of lambda_max(D^-1 K) from the all-ones vector
  * (omega * lambda >= 2 -> POD2G_ESMOOTHER).  MIXED also makes FP32 copies of
- * P and D^-1.  k = 0 gives the smoother-only cycle.  vals32 may be NULL for
+ * P and D^-1.  k = 0 gives the smoother-only cycle.  P must be 16-byte
+ * aligned (EINVAL otherwise; any torch or hipMalloc allocation is).  vals32 may be NULL for
  * FP64.  The handle *out points into work, which must outlive it.
  * Asynchronous: per-instance errors land in out->status and are reported by
  * pcg_solve / pod2g_setup_status.  Returns EINVAL/ESIZE/EHIP synchronously. */
@@ -306,7 +307,7 @@ int pcg_plan_destroy(pod2g_plan *plan);
 /* Launch-parameter tuning of a plan on its own buffers: times `trials`
  * (2..1000) PCG iterations from a fresh start for each candidate value of
  * one parameter at a time and keeps the fastest, then recaptures the plan:
- * the workgroups of the batched restriction (128..1024, batched FP32 cycle
+ * the workgroups of the batched restriction (256..2048, batched FP32 cycle
  * only), the direction update folded into the outer SpMV or run as its own
  * pass, the vector update fused with the second Jacobi pre-relaxation
  * sweep or not, the scalar sums r^T s and p^T q finished by the kernels that read
@@ -328,7 +329,7 @@ int pcg_plan_tune(pod2g_plan *plan, int trials, pod2g_tuning *out, hipStream_t s
 
 /* Set a plan's launch parameters explicitly (for instance values an earlier
  * pcg_plan_tune chose) and recapture it; pcg_plan_config reads them
- * (ms_per_iteration = 0).  bgrid in 1..min(workgroups of n rows, 1024);
+ * (ms_per_iteration = 0).  bgrid in 1..min(workgroups of n rows, 2048);
  * fuse_dir, cons and fuse_upd 0 or 1; igroup a divisor of the batch up to
  * 8; xwin 0, or positive for LDS staging (2D only: the library sets the
  * window); ms_per_iteration is ignored.  Anything else: POD2G_EINVAL and

@@ -9,12 +9,13 @@
 
 namespace pod2g {
 
-constexpr int KP_CH = 8;   // columns of K P per pass over K
-constexpr int KC_TR = 64;  // rows per LDS tile of the coarse-matrix kernel
+constexpr int KP_CH = 16;  // the node-major basis copy pads k to a multiple of this
+constexpr int KC_TR = 64;  // LDS of the coarse-matrix kernel: MAXK x KC_TR doubles twice
+constexpr int KC_WG = 256; // workgroups per instance of the coarse-matrix kernel, at most
 
 struct SetupLayout {
   size_t status, lam, pst, arr, kp, L, Linv, kcpart, ppart, p32, d32, kp32, pt, pw, total;
-  int nbk, rows_per_wg;
+  int nbk;
 };
 
 static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -25,16 +26,16 @@ static bool want_kp32(int dim, int k, int precision) {
   return precision == POD2G_MIXED && dim == 3 && k > 0;
 }
 
-// columns of the node-major basis copy: k rounded up to whole passes of
-// K P, zero-padded, so a pass loads whole rows without bounds tests
+// columns of the node-major basis copy: k rounded up to a multiple of 16,
+// zero-padded, so the K P kernel loads whole pieces without bounds tests
 static int kp_pad(int k) { return (k + KP_CH - 1) / KP_CH * KP_CH; }
 
 static SetupLayout setup_layout(int n, int k, int batch, int precision, int dim) {
   SetupLayout S;
-  int rpt = n / (NT * 1024);
-  if (rpt < 1) rpt = 1;
-  S.rows_per_wg = NT * rpt;
-  S.nbk = ceil_div(n, S.rows_per_wg);
+  // workgroups per instance of the coarse-matrix kernel: at least 8192 rows
+  // each, at most KC_WG
+  S.nbk = ceil_div(n, 8192);
+  if (S.nbk > KC_WG) S.nbk = KC_WG;
   const size_t ntri = (size_t)k * (k + 1) / 2;
   size_t o = 0;
   S.status = o; o += align256(sizeof(int) * batch);
@@ -68,9 +69,9 @@ __global__ void k_setup_init(InstState *pst, Arrival *arr, int *status, double *
   lam[b] = 0.0;
 }
 
-// Node-major copy of the basis: Pt[node][j][d] = P[j][node dim + d] for
+// Node-major copy of the basis: Pt[node][d][j] = P[j][node dim + d] for
 // j < k and 0 up to kpad columns, so that the values K P needs at a
-// neighbour node are contiguous.
+// neighbour node are contiguous per component.
 template <int DIM>
 __global__ void __launch_bounds__(NT) k_pt(int n, int k, int kpad, const double *__restrict__ P,
                                            double *__restrict__ Pt) {
@@ -78,59 +79,89 @@ __global__ void __launch_bounds__(NT) k_pt(int n, int k, int kpad, const double 
   for (size_t t = (size_t)blockIdx.x * NT + threadIdx.x; t < total; t += (size_t)gridDim.x * NT) {
     const size_t node = t / ((size_t)kpad * DIM);
     const int rem = (int)(t - node * kpad * DIM);
-    const int j = rem / DIM, d = rem % DIM;
+    const int d = rem / kpad, j = rem % kpad;
     Pt[t] = j < k ? P[(size_t)j * n + node * DIM + d] : 0.0;
   }
 }
 
-// KP[:, j0 .. j0 + KP_CH) = K P[:, j0 ..] for one instance per grid row,
-// one thread per node (its DIM rows): per neighbour slot the KP_CH x DIM
-// basis entries of the neighbour node (contiguous in Pt) meet the node's
-// DIM x DIM block of K.  Each entry sums over slots and components in the
+// K P for one instance per grid row, eight lanes per node (its DIM rows):
+// lane q forms columns 16 m + 2 q and 16 m + 2 q + 1 for m < M (kpad =
+// 16 M).  The eight lanes of a node load the same K values (one request
+// per wave serves them), so K is read from memory once for all k columns;
+// for each component of the neighbour node the eight lanes read 16
+// consecutive basis values (128 bytes, one 16-byte load each) from the
+// node-major copy Pt.  Each entry sums over slots and components in the
 // order of a row-wise product.
-template <int DIM>
+constexpr int KP_LANES = 8;
+typedef double kd2 __attribute__((ext_vector_type(2)));
+
+template <int DIM, int M>
 __global__ void __launch_bounds__(NT) k_kp(int n, int nn, int k, long long vstride,
                                            const int *__restrict__ colblk,
                                            const double *__restrict__ vals,
                                            const double *__restrict__ Pt, double *__restrict__ KP) {
   const int b = blockIdx.y;
-  const int node = xcd_block(blockIdx.x, gridDim.x) * NT + threadIdx.x;
-  const int j0 = blockIdx.z * KP_CH;
+  const int t = xcd_block(blockIdx.x, gridDim.x) * NT + threadIdx.x;
+  const int node = t / KP_LANES, q = t % KP_LANES;
   if (node >= nn) return;
+  constexpr int kpad = 16 * M;
   const double *v = vals + (size_t)b * vstride + (size_t)node * DIM;
-  double acc[DIM][KP_CH];
+  double acc[DIM][2 * M];
 #pragma unroll
   for (int r = 0; r < DIM; ++r)
 #pragma unroll
-    for (int jj = 0; jj < KP_CH; ++jj) acc[r][jj] = 0.0;
-  const int jn = k - j0 < KP_CH ? k - j0 : KP_CH;
-  const int kpad = (k + KP_CH - 1) / KP_CH * KP_CH;
+    for (int jj = 0; jj < 2 * M; ++jj) acc[r][jj] = 0.0;
 #pragma unroll 3
   for (int s = 0; s < Stencil<DIM>::S; ++s) {
     const int c = colblk[s * nn + node];
-    const double *pc = Pt + ((size_t)c * kpad + j0) * DIM;
-    double pv[KP_CH][DIM];
+    const double *pc = Pt + (size_t)c * kpad * DIM + 2 * q;
+    kd2 pv[DIM][M];
 #pragma unroll
-    for (int jj = 0; jj < KP_CH; ++jj)
+    for (int bc = 0; bc < DIM; ++bc)
 #pragma unroll
-      for (int bc = 0; bc < DIM; ++bc) pv[jj][bc] = pc[jj * DIM + bc];
+      for (int m = 0; m < M; ++m) pv[bc][m] = *(const kd2 *)(pc + bc * kpad + 16 * m);
 #pragma unroll
     for (int bc = 0; bc < DIM; ++bc) {
       double a[DIM];
 #pragma unroll
       for (int r = 0; r < DIM; ++r) a[r] = v[(size_t)(s * DIM + bc) * n + r];
 #pragma unroll
-      for (int jj = 0; jj < KP_CH; ++jj)
+      for (int m = 0; m < M; ++m)
 #pragma unroll
-        for (int r = 0; r < DIM; ++r) acc[r][jj] += a[r] * pv[jj][bc];
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+          for (int r = 0; r < DIM; ++r) acc[r][2 * m + e] += a[r] * pv[bc][m][e];
     }
   }
   double *out = KP + (size_t)b * k * n + (size_t)node * DIM;
 #pragma unroll
-  for (int jj = 0; jj < KP_CH; ++jj)
-    if (jj < jn)
+  for (int m = 0; m < M; ++m)
 #pragma unroll
-      for (int r = 0; r < DIM; ++r) out[(size_t)(j0 + jj) * n + r] = acc[r][jj];
+    for (int e = 0; e < 2; ++e) {
+      const int j = 16 * m + 2 * q + e;
+      if (j < k)
+#pragma unroll
+        for (int r = 0; r < DIM; ++r) out[(size_t)j * n + r] = acc[r][2 * m + e];
+    }
+}
+
+template <int DIM, int M>
+static void launch_kp_t(const pod2g_pattern *pat, int cnt, int k, const double *vals,
+                        const double *Pt, double *KP, hipStream_t stream) {
+  dim3 g(ceil_div(pat->n_nodes * KP_LANES, NT), cnt);
+  hipLaunchKernelGGL((k_kp<DIM, M>), g, dim3(NT), 0, stream, pat->n, pat->n_nodes, k, pat->nvals,
+                     pat->colblk, vals, Pt, KP);
+}
+
+template <int DIM>
+static void launch_kp(const pod2g_pattern *pat, int cnt, int k, const double *vals,
+                      const double *Pt, double *KP, hipStream_t stream) {
+  switch (kp_pad(k) / 16) {
+    case 1: launch_kp_t<DIM, 1>(pat, cnt, k, vals, Pt, KP, stream); break;
+    case 2: launch_kp_t<DIM, 2>(pat, cnt, k, vals, Pt, KP, stream); break;
+    case 3: launch_kp_t<DIM, 3>(pat, cnt, k, vals, Pt, KP, stream); break;
+    default: launch_kp_t<DIM, 4>(pat, cnt, k, vals, Pt, KP, stream); break;
+  }
 }
 
 __device__ __forceinline__ void tri_index(int e, int &j, int &l) {
@@ -142,63 +173,105 @@ __device__ __forceinline__ void tri_index(int e, int &j, int &l) {
   l = e - jj * (jj + 1) / 2;
 }
 
-// Lower triangle of K_c = P^T (K P): per-workgroup partial sums over a row
-// range; the last workgroup of an instance sums them (fixed order) and
-// factors K_c = L L^T in LDS.
-__global__ void __launch_bounds__(NT) k_kc(int n, int k, int rows_per_wg, int nbk,
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+// Lower triangle of K_c = P^T (K P) on FP64 MFMA (v_mfma_f64_16x16x4f64).
+// In step s of a group of four MFMA steps over rows r0 .. r0 + 15, lane
+// i + 16 kk holds A[i][kk] = P[j0 + i][r0 + 4 kk + s] and
+// B[kk][i] = KP[l0 + i][r0 + 4 kk + s]: a lane's operands of the four steps
+// are four consecutive doubles of one row (two 16-byte loads; n is even, so
+// each pair lies wholly below or wholly above n).  Every wave accumulates
+// the tiles on and below the diagonal over its share of the row groups;
+// the workgroup's waves are summed tile by tile in LDS into one partial per
+// lower-triangle entry e = j (j + 1) / 2 + l; the last workgroup of an
+// instance sums the partials (fixed order) and factors K_c = L L^T in LDS.
+// TJ = ceil(k / 16).
+template <int TJ>
+__global__ void __launch_bounds__(NT) k_kc(int n, int k, int nbk,
                                            const double *__restrict__ P,
                                            const double *__restrict__ KP, double *__restrict__ part,
                                            double *__restrict__ Lout, double *__restrict__ Linv,
                                            int *__restrict__ status, Arrival *arr) {
-  constexpr int MAXE = (MAXK * (MAXK + 1) / 2 + NT - 1) / NT;
   __shared__ double sp[MAXK * KC_TR];
   __shared__ double skp[MAXK * KC_TR];
   __shared__ int flag;
   __shared__ int fail;
+  constexpr int NTILE = TJ * (TJ + 1) / 2;
   const int b = blockIdx.y, wg = blockIdx.x;
   const int ntri = k * (k + 1) / 2;
   const double *KPb = KP + (size_t)b * k * n;
-  int ej[MAXE], el[MAXE];
-  double acc[MAXE];
+  const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+  const int li = lane & 15, kk = lane >> 4;
+  const double *pa[TJ];
+  const double *pb[TJ];
 #pragma unroll
-  for (int m = 0; m < MAXE; ++m) {
-    acc[m] = 0.0;
-    const int e = threadIdx.x + m * NT;
-    if (e < ntri) tri_index(e, ej[m], el[m]);
-    else { ej[m] = 0; el[m] = 0; }
+  for (int t = 0; t < TJ; ++t) {
+    const int j = min(t * 16 + li, k - 1);   // rows j >= k: clamped, never used
+    pa[t] = P + (size_t)j * n;
+    pb[t] = KPb + (size_t)j * n;
   }
-  const int r_begin = wg * rows_per_wg;
-  const int r_end = r_begin + rows_per_wg < n ? r_begin + rows_per_wg : n;
-  for (int r0 = r_begin; r0 < r_end; r0 += KC_TR) {
-    for (int t = threadIdx.x; t < k * KC_TR; t += NT) {
-      const int j = t / KC_TR, rr = r0 + t % KC_TR;
-      sp[t] = rr < r_end ? P[(size_t)j * n + rr] : 0.0;
-      skp[t] = rr < r_end ? KPb[(size_t)j * n + rr] : 0.0;
-    }
-    __syncthreads();
+  d4 acc[NTILE];
 #pragma unroll
-    for (int m = 0; m < MAXE; ++m) {
-      if (threadIdx.x + m * NT < ntri) {
-        const double *a = sp + ej[m] * KC_TR, *c = skp + el[m] * KC_TR;
-        double s = 0.0;
-        for (int rr = 0; rr < KC_TR; ++rr) s += a[rr] * c[rr];
-        acc[m] += s;
+  for (int m = 0; m < NTILE; ++m) acc[m] = d4{0.0, 0.0, 0.0, 0.0};
+  const long long ngroups = (n + 15) / 16, nwaves = (long long)nbk * NWAVE;
+  const long long per = (ngroups + nwaves - 1) / nwaves;
+  const long long wv = (long long)wg * NWAVE + w;
+  const long long gend = min(ngroups, wv * per + per);
+  for (long long g0 = wv * per; g0 < gend; ++g0) {
+    const int r = (int)(g0 * 16) + 4 * kk;
+    const bool ok0 = r < n, ok1 = r + 2 < n;
+    d4 a[TJ], c[TJ];
+#pragma unroll
+    for (int t = 0; t < TJ; ++t) {
+      const d2 a0 = *(const d2 *)(pa[t] + (ok0 ? r : 0));
+      const d2 a1 = *(const d2 *)(pa[t] + (ok1 ? r + 2 : 0));
+      const d2 c0 = *(const d2 *)(pb[t] + (ok0 ? r : 0));
+      const d2 c1 = *(const d2 *)(pb[t] + (ok1 ? r + 2 : 0));
+      a[t] = d4{ok0 ? a0[0] : 0.0, ok0 ? a0[1] : 0.0, ok1 ? a1[0] : 0.0, ok1 ? a1[1] : 0.0};
+      c[t] = d4{c0[0], c0[1], c1[0], c1[1]};
+    }
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      int m = 0;
+#pragma unroll
+      for (int t = 0; t < TJ; ++t)
+#pragma unroll
+        for (int u = 0; u <= t; ++u, ++m)
+          acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t][s4], c[u][s4], acc[m], 0, 0, 0);
+    }
+  }
+  // D[i][jj] of an FP64 tile sits in lane jj + 16 (i % 4), register i / 4
+  // (measured; the FP32 16x16x4 layout has lane jj + 16 (i / 4), register i % 4)
+  double *buf = sp;   // [NWAVE][16][16]
+  double *pw = part + ((size_t)b * nbk + wg) * ntri;
+  {
+    int m = 0;
+#pragma unroll
+    for (int t = 0; t < TJ; ++t)
+#pragma unroll
+      for (int u = 0; u <= t; ++u, ++m) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) buf[(w * 16 + kk + 4 * v) * 16 + li] = acc[m][v];
+        __syncthreads();
+        const int i = threadIdx.x / 16, jj = threadIdx.x % 16;
+        const int j = t * 16 + i, l = u * 16 + jj;
+        if (j < k && l <= j) {
+          double sum = 0.0;
+#pragma unroll
+          for (int ww = 0; ww < NWAVE; ++ww) sum += buf[(ww * 16 + i) * 16 + jj];
+          put_partial(pw + j * (j + 1) / 2 + l, sum);
+        }
+        __syncthreads();
       }
-    }
-    __syncthreads();
   }
-  double *pb = part + (size_t)b * nbk * ntri;
-#pragma unroll
-  for (int m = 0; m < MAXE; ++m) {
-    const int e = threadIdx.x + m * NT;
-    if (e < ntri) put_partial(pb + (size_t)wg * ntri + e, acc[m]);
-  }
+  double *pbk = part + (size_t)b * nbk * ntri;
   if (!arrive_last(arr + (size_t)b * 2, wg, nbk, &flag)) return;
   // K_c into LDS (full symmetric), then Cholesky
   double *A = sp;  // k x k, row-major
   for (int e = threadIdx.x; e < ntri; e += NT) {
     double s = 0.0;
-    for (int w = 0; w < nbk; ++w) s += pb[(size_t)w * ntri + e];
+    for (int ww = 0; ww < nbk; ++ww) s += pbk[(size_t)ww * ntri + e];
     int j, l;
     tri_index(e, j, l);
     A[j * k + l] = s;
@@ -345,15 +418,18 @@ static int setup_run(const pod2g_prec &pr, const SetupLayout &S, char *w, int b0
       else
         hipLaunchKernelGGL(k_pt<3>, dim3(2048), dim3(NT), 0, stream, n, k, kp_pad(k), pr.P, Pt);
     }
-    dim3 gk(ceil_div(pat->n_nodes, NT), cnt, ceil_div(k, KP_CH));
-    if (dim == 2)
-      hipLaunchKernelGGL(k_kp<2>, gk, dim3(NT), 0, stream, n, pat->n_nodes, k, pat->nvals,
-                         pat->colblk, vals, (const double *)Pt, KP);
-    else
-      hipLaunchKernelGGL(k_kp<3>, gk, dim3(NT), 0, stream, n, pat->n_nodes, k, pat->nvals,
-                         pat->colblk, vals, (const double *)Pt, KP);
-    hipLaunchKernelGGL(k_kc, dim3(S.nbk, cnt), dim3(NT), 0, stream, n, k, S.rows_per_wg, S.nbk,
-                       pr.P, (const double *)KP, kcpart, L, Linv, status, arr);
+    if (dim == 2) launch_kp<2>(pat, cnt, k, vals, (const double *)Pt, KP, stream);
+    else launch_kp<3>(pat, cnt, k, vals, (const double *)Pt, KP, stream);
+    {
+      const dim3 gc(S.nbk, cnt);
+      const double *kpc = KP;
+      switch ((k + 15) / 16) {
+        case 1: hipLaunchKernelGGL(k_kc<1>, gc, dim3(NT), 0, stream, n, k, S.nbk, pr.P, kpc, kcpart, L, Linv, status, arr); break;
+        case 2: hipLaunchKernelGGL(k_kc<2>, gc, dim3(NT), 0, stream, n, k, S.nbk, pr.P, kpc, kcpart, L, Linv, status, arr); break;
+        case 3: hipLaunchKernelGGL(k_kc<3>, gc, dim3(NT), 0, stream, n, k, S.nbk, pr.P, kpc, kcpart, L, Linv, status, arr); break;
+        default: hipLaunchKernelGGL(k_kc<4>, gc, dim3(NT), 0, stream, n, k, S.nbk, pr.P, kpc, kcpart, L, Linv, status, arr); break;
+      }
+    }
     if (convert_p && pr.precision == POD2G_MIXED)
       hipLaunchKernelGGL(k_to_f32, dim3(1024), dim3(NT), 0, stream, (size_t)k * n, pr.P, pr.P32);
     if (pr.KP32)
@@ -390,6 +466,7 @@ int pod2g_setup(const pod2g_pattern *pat, const double *vals, const float *vals3
                 pod2g_prec *out, hipStream_t stream) {
   if (!pat || !vals || !dinv || !work || !out) return POD2G_EINVAL;
   if (k < 0 || k > MAXK || (k > 0 && !P) || batch < 1 || batch > 65535) return POD2G_EINVAL;
+  if (k > 0 && ((uintptr_t)P & 15)) return POD2G_EINVAL;   // read in 16-byte pieces
   if (precision != POD2G_FP64 && precision != POD2G_MIXED) return POD2G_EINVAL;
   if (precision == POD2G_MIXED && !vals32) return POD2G_EINVAL;
   if (!(omega > 0.0) || nu_pre < 0 || nu_post < 0 || nu_pre > 64 || nu_post > 64 || power_iters < 0)

@@ -835,103 +835,110 @@ __global__ void __launch_bounds__(NT) k_update_sweep(Ctx c, const double *__rest
 // ---------------------------------------------------------------------------
 
 // Restriction for all instances at once: C[j][b] = sum_rows P[j][row] R[b][row]
-// with R the residuals r'_b (FP32, [batch][n]).  Every wave owns 64
-// consecutive rows of the workgroup's row range, stages them for all live
-// instances in LDS and accumulates all 16 x 16 output tiles on MFMA; the
-// waves' tiles are summed per workgroup into one FP64 partial per output
-// (k_ptr_sum sums the workgroups, k_coarse_b applies the coarse solves).
-constexpr int PW_LD = NT + 1;     // padded LDS strides: no bank conflicts between
-constexpr int RW_LD = WAVE + 1;   // the 16 columns an MFMA operand reads at once
+// with R the residuals r'_b (FP32, [batch][n]), on MFMA with the operands
+// loaded straight from memory.  In step s of a group of four MFMA steps over
+// rows r0 .. r0 + 15, lane i + 16 kk holds A[i][kk] = P[j0 + i][r0 + 4 kk + s]
+// and B[kk][i] = R[b0 + i][r0 + 4 kk + s]: a lane's operands of the four
+// steps are four consecutive floats of one row of P (or R), one 16-byte
+// load, and the contraction over the group's 16 rows is complete.  No LDS
+// staging and no barriers in the loop: every wave accumulates all output
+// tiles over its own contiguous share of the row groups, with GRP groups'
+// loads in flight together.  Output rows j >= k and columns b >= batch (and
+// finished instances) are computed from clamped addresses and never used;
+// rows >= n are zeroed.  The workgroup's four waves are summed in FP64 into
+// one partial per output (k_ptr_sum sums the workgroups, k_coarse_b applies
+// the coarse solves).  VEC: n % 4 == 0, so a group's 16-byte loads are
+// aligned and lie wholly below or wholly above n.
+constexpr int PTR_GRP = 2;        // 16-row groups per wave iteration
 
+template <bool VEC>
+__device__ __forceinline__ f4 ptr_load(const float *__restrict__ row_base, int r, int n) {
+  if (VEC) {
+    const bool ok = r < n;
+    f4 v = *(const f4 *)(row_base + (ok ? r : 0));
+    return ok ? v : f4{0.f, 0.f, 0.f, 0.f};
+  } else {
+    f4 v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const bool ok = r + e < n;
+      const float x = row_base[ok ? r + e : 0];
+      v[e] = ok ? x : 0.f;
+    }
+    return v;
+  }
+}
+
+// TJ = ceil(k / 16) basis tiles, TB = ceil(batch / 16) batch tiles.
+template <int TJ, int TB, bool VEC>
 __global__ void __launch_bounds__(NT) k_ptr_b(Ctx c, const float *__restrict__ R) {
-  __shared__ float Rw[NWAVE][MAXB][RW_LD];  // 33 KB
-  extern __shared__ float Pw[];             // [k][PW_LD] basis rows of the block (dynamic)
-  __shared__ int live[MAXB];
+  __shared__ float Cs[NWAVE][TJ * 16][TB * 16];   // the waves' tiles (at most 32 KB)
   __shared__ int nlive;
   const int B = c.batch, k = c.k, n = c.n;
   const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-  if (threadIdx.x < B) live[threadIdx.x] = !c.st[threadIdx.x].done;
+  if (threadIdx.x == 0) nlive = 0;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int m = 0;
-    for (int b = 0; b < B; ++b) m += live[b];
-    nlive = m;
-  }
+  if (threadIdx.x < B && !c.st[threadIdx.x].done) atomicAdd(&nlive, 1);
   __syncthreads();
   if (nlive == 0) return;
-  const int tj = (k + 15) / 16, tb = (B + 15) / 16, ntile = tj * tb;
-  constexpr int MT = 8;   // every wave accumulates all tiles (at most 4 x 2) over its rows
-  f4 acc[MT];
+  f4 acc[TJ][TB];
 #pragma unroll
-  for (int m = 0; m < MT; ++m) acc[m] = f4{0.f, 0.f, 0.f, 0.f};
-  const int g = xcd_block(blockIdx.x, c.bgrid);
-  const int per = (c.nb + c.bgrid - 1) / c.bgrid;
-  const int blk_end = min(c.nb, (g + 1) * per);
+  for (int t = 0; t < TJ; ++t)
+#pragma unroll
+    for (int u = 0; u < TB; ++u) acc[t][u] = f4{0.f, 0.f, 0.f, 0.f};
+  const int li = lane & 15, kk = lane >> 4;
+  // operand rows of this lane: basis row j (clamped to k - 1) per j tile,
+  // residual row b (clamped to batch - 1) per batch tile
   const float *P = (const float *)c.sP;
-  for (int blk = g * per; blk < blk_end; ++blk) {
-    const int row = blk * NT + w * WAVE + lane;
-    // the block's residuals and basis rows, sixteen loads in flight at a
-    // time: the addresses are clamped into range so that every load is
-    // unconditional (a guarded load becomes a branch, and the compiler then
-    // waits for each load before the next), and entries past the batch, k
-    // or n are zeroed afterwards
-    constexpr int LG = 16;
-    const int rowc = row < n ? row : n - 1;
-    for (int b0 = 0; b0 < B; b0 += LG) {
-      float v[LG];
+  const float *pa[TJ];
+  const float *rb[TB];
 #pragma unroll
-      for (int u = 0; u < LG; ++u) v[u] = R[(size_t)(b0 + u < B ? b0 + u : B - 1) * n + rowc];
+  for (int t = 0; t < TJ; ++t) pa[t] = P + (size_t)min(t * 16 + li, k - 1) * n;
 #pragma unroll
-      for (int u = 0; u < LG; ++u)
-        if (b0 + u < B) Rw[w][b0 + u][lane] = (live[b0 + u] && row < n) ? v[u] : 0.f;
+  for (int u = 0; u < TB; ++u) rb[u] = R + (size_t)min(u * 16 + li, B - 1) * n;
+  // this wave's share of the 16-row groups
+  const int g = xcd_block(blockIdx.x, c.bgrid);
+  const long long ngroups = (n + 15) / 16, nwaves = (long long)c.bgrid * NWAVE;
+  const long long per = (ngroups + nwaves - 1) / nwaves;
+  const long long wv = (long long)g * NWAVE + w;
+  const long long gbeg = wv * per, gend = min(ngroups, gbeg + per);
+  for (long long g0 = gbeg; g0 < gend; g0 += PTR_GRP) {
+    f4 a[PTR_GRP][TJ], bv[PTR_GRP][TB];
+#pragma unroll
+    for (int q = 0; q < PTR_GRP; ++q) {
+      // a group past the share (its rows may exist) or past n loads zeros
+      const int r = (g0 + q < gend) ? (int)((g0 + q) * 16) + 4 * kk : n;
+#pragma unroll
+      for (int t = 0; t < TJ; ++t) a[q][t] = ptr_load<VEC>(pa[t], r, n);
+#pragma unroll
+      for (int u = 0; u < TB; ++u) bv[q][u] = ptr_load<VEC>(rb[u], r, n);
     }
-    for (int j0 = 0; j0 < k; j0 += LG) {
-      float v[LG];
 #pragma unroll
-      for (int u = 0; u < LG; ++u) v[u] = P[(size_t)(j0 + u < k ? j0 + u : k - 1) * n + rowc];
+    for (int q = 0; q < PTR_GRP; ++q)
 #pragma unroll
-      for (int u = 0; u < LG; ++u)
-        if (j0 + u < k) Pw[(j0 + u) * PW_LD + threadIdx.x] = row < n ? v[u] : 0.f;
-    }
-    __syncthreads();
+      for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      const int t = m;
-      if (t < ntile) {
-        const int j = (t / tb) * 16 + (lane & 15), bb = (t % tb) * 16 + (lane & 15);
-        for (int s4 = 0; s4 < WAVE / 4; ++s4) {
-          const int rr = 4 * s4 + (lane >> 4);
-          const float a = j < k ? Pw[j * PW_LD + w * WAVE + rr] : 0.f;
-          const float bvl = bb < B ? Rw[w][bb][rr] : 0.f;
-          acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bvl, acc[m], 0, 0, 0);
-        }
-      }
-    }
-    __syncthreads();
+        for (int t = 0; t < TJ; ++t)
+#pragma unroll
+          for (int u = 0; u < TB; ++u)
+            acc[t][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[q][t][s4], bv[q][u][s4], acc[t][u], 0, 0, 0);
   }
-  // sum the four waves' tiles of this workgroup (LDS reused), then write
-  float *Cs = &Rw[0][0][0];   // [k_pad][B_pad] accumulators, tj*16 x tb*16 <= 64 x 32
-  const int ldc = tb * 16;
-  for (int t = threadIdx.x; t < tj * 16 * ldc; t += NT) Cs[t] = 0.f;
+  // D[i][jb] of tile (t, u) sits in lane jb + 16 (i / 4), register i % 4
+#pragma unroll
+  for (int t = 0; t < TJ; ++t)
+#pragma unroll
+    for (int u = 0; u < TB; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Cs[w][t * 16 + 4 * kk + v][u * 16 + li] = acc[t][u][v];
   __syncthreads();
-  for (int ww = 0; ww < NWAVE; ++ww) {
-    if (w == ww) {
-#pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        const int t = m;
-        if (t < ntile) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int i = (t / tb) * 16 + 4 * (lane >> 4) + v, jj = (t % tb) * 16 + (lane & 15);
-            Cs[i * ldc + jj] += acc[m][v];
-          }
-        }
-      }
-    }
-    __syncthreads();
-  }
   double *gp = c.bpart + (size_t)g * k * B;
-  for (int t = threadIdx.x; t < k * B; t += NT) gp[t] = (double)Cs[(t / B) * ldc + t % B];
+  for (int o = threadIdx.x; o < k * B; o += NT) {
+    const int j = o / B, b = o % B;
+    double sum = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < NWAVE; ++ww) sum += (double)Cs[ww][j][b];
+    gp[o] = sum;
+  }
 }
 
 // r_c of every (j, b): the workgroup partials of k_ptr_b summed by 16 threads
@@ -1447,7 +1454,7 @@ struct Layout {
 };
 
 constexpr int BGRID_DEFAULT = 512;    // workgroups of the batched restriction
-constexpr int BGRID_MAX = 1024;       // largest the tuner tries (workspace is sized for it)
+constexpr int BGRID_MAX = 2048;       // largest the tuner tries (workspace is sized for it)
 constexpr long long FUSE_DIR_MAX = 1ll << 20;   // rows x instances with the fused update
 // consumer-side sums while (row workgroups x instances) x partials stays
 // below this (the partial loads every consumer workgroup repeats)
@@ -1484,6 +1491,30 @@ static Layout layout(int n, int batch, int k, int precision) {
 template <typename T>
 static unsigned xlds(const Ctx &c) {
   return c.xwin ? (unsigned)(sizeof(T) * (size_t)(NT + 2 * c.xwin) * (c.n / c.nn)) : 0u;
+}
+
+template <int TJ, int TB>
+static void launch_ptr_b_t(const Ctx &c, const float *R, hipStream_t stream) {
+  if (c.n % 4 == 0)
+    hipLaunchKernelGGL((k_ptr_b<TJ, TB, true>), dim3(c.bgrid), dim3(NT), 0, stream, c, R);
+  else
+    hipLaunchKernelGGL((k_ptr_b<TJ, TB, false>), dim3(c.bgrid), dim3(NT), 0, stream, c, R);
+}
+
+// the batched restriction with as many basis and batch tiles as k and the
+// batch need (k <= 64, 4 <= batch <= 32)
+static void launch_ptr_b(const Ctx &c, const float *R, hipStream_t stream) {
+  const int tj = (c.k + 15) / 16, tb = (c.batch + 15) / 16;
+  switch (tj * 2 + tb - 1) {
+    case 2: launch_ptr_b_t<1, 1>(c, R, stream); break;
+    case 3: launch_ptr_b_t<1, 2>(c, R, stream); break;
+    case 4: launch_ptr_b_t<2, 1>(c, R, stream); break;
+    case 5: launch_ptr_b_t<2, 2>(c, R, stream); break;
+    case 6: launch_ptr_b_t<3, 1>(c, R, stream); break;
+    case 7: launch_ptr_b_t<3, 2>(c, R, stream); break;
+    case 8: launch_ptr_b_t<4, 1>(c, R, stream); break;
+    default: launch_ptr_b_t<4, 2>(c, R, stream); break;
+  }
 }
 
 // 2D: stage x around each node block in LDS when the window fits in 48 KB
@@ -1603,12 +1634,10 @@ static void launch_cycle(const Ctx &c, const pod2g_prec *pr, hipStream_t stream,
     // shared basis, many instances: one MFMA contraction over the batch
     if (have) {
       launch(tm, POD2G_TK_RESTRICT, k_resid32<DIM>, gridn, blk, xlds<float>(c), stream, c, (const float *)cur);
-      hipLaunchKernelGGL(k_ptr_b, dim3(c.bgrid), blk, sizeof(float) * c.k * PW_LD, stream, c,
-                         (const float *)c.rbuf);
+      launch_ptr_b(c, (const float *)c.rbuf, stream);
     } else {
       // x = 0: the residual is the cycle input itself
-      hipLaunchKernelGGL(k_ptr_b, dim3(c.bgrid), blk, sizeof(float) * c.k * PW_LD, stream, c,
-                         (const float *)c.b32);
+      launch_ptr_b(c, (const float *)c.b32, stream);
     }
     hipLaunchKernelGGL(k_ptr_sum, dim3(ceil_div((long long)c.k * c.batch * PTR_TPO, NT)), blk, 0,
                        stream, c);
@@ -1709,11 +1738,9 @@ static void launch_cycle_sgs(const Ctx &c, const pod2g_prec *pr, hipStream_t str
     if (batched_products<T>(c)) {
       if (have) {
         launch(tm, POD2G_TK_RESTRICT, k_resid32<DIM>, gridn, blk, xlds<float>(c), stream, c, (const float *)x);
-        hipLaunchKernelGGL(k_ptr_b, dim3(c.bgrid), blk, sizeof(float) * c.k * PW_LD, stream, c,
-                           (const float *)c.rbuf);
+        launch_ptr_b(c, (const float *)c.rbuf, stream);
       } else {
-        hipLaunchKernelGGL(k_ptr_b, dim3(c.bgrid), blk, sizeof(float) * c.k * PW_LD, stream, c,
-                           (const float *)c.b32);
+        launch_ptr_b(c, (const float *)c.b32, stream);
       }
       hipLaunchKernelGGL(k_ptr_sum, dim3(ceil_div((long long)c.k * c.batch * PTR_TPO, NT)), blk, 0,
                          stream, c);
@@ -2253,7 +2280,7 @@ int pcg_plan_tune(pod2g_plan *pl, int trials, pod2g_tuning *out, hipStream_t str
   std::vector<int> grids;
   if (pr && pr->precision == POD2G_MIXED && batched_products<float>(c) && c.k > 0) {
     const int cap = batched_grid(c.n, BGRID_MAX);
-    for (int g : {128, 256, 512, 1024})
+    for (int g : {256, 512, 1024, 2048})
       if (g <= cap) grids.push_back(g);
   }
   for (int g : grids) {

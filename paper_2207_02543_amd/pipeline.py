@@ -62,6 +62,8 @@ class Problem:
         self.n = self.pat.n
         self.nvals = self.pat.nvals
         self._work = {}
+        self._guarded = set()       # omegas the smoother guard has passed
+        self.lambda_max = None
 
     # -- scratch buffers, reused between calls of the same kind ----------------
     def work(self, key, nbytes):
@@ -91,16 +93,27 @@ class Problem:
         return sysm
 
     # -- preconditioner -----------------------------------------------------------
+    # power iterations of the damped-Jacobi stability guard, run on the first
+    # setup of each damping weight of a problem class
+    GUARD_ITERS = 100
+
     def setup(self, sysm: System, P, k=None, precision=L.FP64, omega=None, nu_pre=None,
               nu_post=None, power_iters=0, key="setup", smoother=L.SMOOTHER_JACOBI,
               stream=None) -> L.Prec:
+        """pod2g_setup on these instances.  The first Jacobi setup with a
+        given omega also estimates lambda_max(D^-1 K) of the first instance
+        and raises Pod2gError(ESMOOTHER) if omega * lambda_max >= 2 (the
+        estimate depends on the mesh and the Poisson ratio, hardly on theta,
+        so one check covers the class)."""
         w = self.w
         k = (P.shape[0] if P is not None else 0) if k is None else k
+        om = w.omega if omega is None else omega
+        if smoother == L.SMOOTHER_JACOBI and om not in self._guarded:
+            self.check_smoother(sysm, om)
         nb = L.pod2g_setup_bytes(self.pat, k, sysm.batch, precision)
         wk = self.work(key, nb)
         prec = L.Prec()
-        L.check(L.pod2g_setup(self.pat, sysm.vals, sysm.vals32, sysm.dinv, P, k,
-                              w.omega if omega is None else omega,
+        L.check(L.pod2g_setup(self.pat, sysm.vals, sysm.vals32, sysm.dinv, P, k, om,
                               w.nu_pre if nu_pre is None else nu_pre,
                               w.nu_post if nu_post is None else nu_post,
                               precision, sysm.batch, power_iters, wk, nb, prec, stream),
@@ -108,6 +121,22 @@ class Problem:
         L.check(L.pod2g_set_smoother(prec, smoother), "pod2g_set_smoother")
         prec._keepalive = (wk, P, sysm)
         return prec
+
+    def check_smoother(self, sysm: System, omega: float):
+        """The damped-Jacobi guard on instance 0 of sysm (smoother-only setup
+        with GUARD_ITERS power iterations); raises on ESMOOTHER."""
+        one = System(1, sysm.xi[:1], sysm.vals[:1], None, sysm.dinv[:1], sysm.f)
+        nb = L.pod2g_setup_bytes(self.pat, 0, 1, L.FP64)
+        wk = _bytes(nb, self.device)
+        prec = L.Prec()
+        L.check(L.pod2g_setup(self.pat, one.vals, None, one.dinv, None, 0, omega, 1, 1, L.FP64, 1,
+                              self.GUARD_ITERS, wk, nb, prec, None), "pod2g_setup (guard)")
+        st, lam = L.pod2g_setup_status(prec)
+        if st[0] != L.OK:
+            raise L.Pod2gError(st[0], f"damped Jacobi with omega = {omega:.4g}: "
+                                      f"omega * lambda_max(D^-1 K) ~ {omega * lam[0]:.3f}")
+        self._guarded.add(omega)
+        self.lambda_max = lam[0]
 
     # -- solve --------------------------------------------------------------------
     def solve(self, sysm: System, prec, u, rtol=None, maxit=5000, beta=None, key="pcg",

@@ -55,9 +55,14 @@ class ServedClass:
     """One problem class: pattern, basis P and `slots` resident queries."""
 
     def __init__(self, w: I.Workload, P: torch.Tensor, slots: int, precision="mixed",
-                 power_iters=0, device="cuda"):
+                 power_iters=0, device="cuda", guard=True):
+        """guard: check the damped-Jacobi stability of the class once (on the
+        first placeholder instance) and raise on ESMOOTHER; power_iters:
+        the per-slot guard of pod2g_setup_slot (0: none)."""
         self.w = w
         self.prob = Problem(w, device)
+        if not guard:
+            self.prob._guarded.add(w.omega)
         self.P = P
         self.k = P.shape[0]
         self.slots = slots

@@ -166,7 +166,15 @@ def test_setup_errors(env):
     prob3 = pipeline.Problem(w3)
     s3 = prob3.alloc_system(1)
     prob3.assemble(s3, I.query_xis(w3, 1))
-    pr3 = prob3.setup(s3, torch.tensor(np.ascontiguousarray(P3.T), device="cuda"), power_iters=300)
+    P3d = torch.tensor(np.ascontiguousarray(P3.T), device="cuda")
+    # the host path checks the smoother once per class and refuses it
+    with pytest.raises(capi.Pod2gError) as e:
+        prob3.setup(s3, P3d)
+    assert e.value.status == capi.ESMOOTHER
+    assert prob3.lambda_max is None
+    # the library's own per-instance guard
+    prob3._guarded.add(w3.omega)
+    pr3 = prob3.setup(s3, P3d, power_iters=300)
     st3, lam3 = capi.pod2g_setup_status(pr3)
     assert st3 == [capi.ESMOOTHER] and lam3[0] * 2 / 3 > 2.0
     # argument errors are reported, not crashed on

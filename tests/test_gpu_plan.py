@@ -83,7 +83,7 @@ def test_tuned_plan_solves_like_eager(dim, N, prec, batch):
     plan = prob.plan(sysm, pr, u, chunk=8)
     t = plan.tune(trials=4)
     flush(f"  tuning {t}")
-    assert t["bgrid"] in (128, 256, 512, 1024) or t["bgrid"] <= 512
+    assert t["bgrid"] in (256, 512, 1024, 2048) or t["bgrid"] <= 512
     assert t["fuse_dir"] in (0, 1) and batch % t["igroup"] == 0 and t["ms_per_iteration"] > 0
     u.copy_(x0)
     ret, it, rr, st = plan.solve(w.tol)

@@ -143,7 +143,12 @@ def test_stream_completes_every_request(two_classes, independent):
 def test_setup_failure_is_reported_per_slot():
     from paper_2207_02543_amd import capi, serve
     w = I.small(2, 12, k=4, n_train=8, omega=1.95)
-    c, P = _class(w, power_iters=30)
+    # the class-level guard refuses the class outright
+    with pytest.raises(capi.Pod2gError) as e:
+        _class(w)
+    assert e.value.status == capi.ESMOOTHER
+    # without it, the per-slot guard fails the slot
+    c, P = _class(w, power_iters=30, guard=False)
     pool, qs = _pool(w, 1)
     srv = serve.Server([c], chunk=2)
     flush("serve: slot whose smoother guard fails")
@@ -176,4 +181,16 @@ def test_replacement_and_limit_match_one_shot():
     assert info[1]["iter"] == it[0]
     assert info[1]["relres"] == rr[0]
     np.testing.assert_array_equal(c.u[1].cpu().numpy(), u[0].cpu().numpy())
+    # the oracle (FP32-emulated cycle, flexible PR) on the same input: its
+    # exit checks replace the recursive residual, it ends at the limit, and
+    # the served result agrees with it at the attainable accuracy
+    ref = oprob.solve_query(w, qs[0], P, precision="fp32", beta="pr", tol=1e-16, maxit=120)
+    uh = c.u[1].cpu().numpy()
+    flush(f"  oracle {ref.iters} {ref.status}, replacements at {ref.replacements}; "
+          f"true residual served {info[1]['relres']:.2e} oracle {ref.relres:.2e}; "
+          f"difference {relerr(uh, ref.u):.1e}")
+    assert ref.status == capi.EMAXIT and ref.iters == info[1]["iter"] == 120
+    assert ref.replacements
+    assert info[1]["relres"] < 1e-10 and ref.relres < 1e-10
+    assert relerr(uh, ref.u) < 1e-9
     srv.close()
