@@ -41,11 +41,19 @@
  *   i + (N+1) j + (N+1)^2 (l-1) in 3D; DOF = dim * rank + component.
  *
  * Matrix layout (block-ELL, one slot per neighbour offset in {-1,0,1}^dim,
- * slot s = (dx+1) + 3 (dy+1) [+ 9 (dz+1)]):
+ * slot s = (dx+1) + 3 (dy+1) [+ 9 (dz+1)], S = n_slots, H = S / 2 the
+ * node's own block):
  *   colblk[s * n_nodes + node] = free-node rank of the neighbour, or the
- *     node itself for an absent neighbour (its values are zero);
- *   vals[(s * dim + b) * n + row] = K(row, dim * colblk[s][row / dim] + b).
- *   nvals = n * n_slots * dim values per instance; batched values are
+ *     node itself for an absent neighbour;
+ *   K is symmetric, so vals stores only the blocks of slots s >= H (the
+ *   own block and the neighbours at a positive offset in (dz, dy, dx)
+ *   order), in planes of ns = n + dim rows whose last dim rows (a "zero
+ *   node") are zero:
+ *     vals[((s - H) * dim + b) * ns + row] = K(row, dim * colblk[s][row / dim] + b),
+ *   and a block of a slot s < H is read transposed from the neighbour j:
+ *     K(dim i + r, dim j + b) = vals[((H - s) * dim + r) * ns + dim j + b]
+ *   (the zero node for an absent neighbour).
+ *   nvals = ns * (H + 1) * dim values per instance; batched values are
  *   [batch][nvals].
  * P is n x k column-major (column j at P + j * n), shared by all instances.
  */

@@ -137,7 +137,9 @@ __global__ void __launch_bounds__(NT) k_young(int N, int ne, int n_terms, double
   E[(size_t)b * ne + e] = exp(kl_scale * g);
 }
 
-// One thread per scalar row: all n_slots * DIM stored values of the row.
+// One thread per scalar row: the row's stored values (centre and upper
+// slots of the symmetric half storage; see Half in common.hpp); the first
+// DIM threads also clear the zero node of every plane.
 template <int DIM>
 __global__ void __launch_bounds__(NT) k_assemble(int N, int n, int nn, int ne, long long vstride,
                                                  const double *__restrict__ E,
@@ -156,9 +158,16 @@ __global__ void __launch_bounds__(NT) k_assemble(int N, int n, int nn, int ne, l
   double *vb = vals + (size_t)b * vstride;
   float *v32 = vals32 ? vals32 + (size_t)b * vstride : nullptr;
   const int node = row / DIM, a = row % DIM;
+  const size_t ns = (size_t)n + DIM;
+  constexpr int H = Half<DIM>::H;
+  if (row < DIM)
+    for (int p = 0; p < Half<DIM>::SH * DIM; ++p) {
+      vb[(size_t)p * ns + n + row] = 0.0;
+      if (v32) v32[(size_t)p * ns + n + row] = 0.f;
+    }
   int ci[3];
   node_coords<DIM>(N, node, ci[0], ci[1], ci[2]);
-  for (int s = 0; s < S; ++s) {
+  for (int s = H; s < S; ++s) {
     const int dd[3] = {s % 3 - 1, (s / 3) % 3 - 1, DIM == 3 ? s / 9 - 1 : 0};
     const int nb = node_rank<DIM>(N, ci[0] + dd[0], ci[1] + dd[1], ci[2] + dd[2]);
     double acc[DIM];
@@ -186,11 +195,11 @@ __global__ void __launch_bounds__(NT) k_assemble(int N, int n, int nn, int ne, l
           }
     }
     for (int bc = 0; bc < DIM; ++bc) {
-      const size_t idx = (size_t)(s * DIM + bc) * n + row;
+      const size_t idx = (size_t)((s - H) * DIM + bc) * ns + row;
       vb[idx] = acc[bc];
       if (v32) v32[idx] = (float)acc[bc];
     }
-    if (s == S / 2) dinv[(size_t)b * n + row] = 1.0 / acc[a];
+    if (s == H) dinv[(size_t)b * n + row] = 1.0 / acc[a];
   }
 }
 
@@ -258,7 +267,7 @@ int pod2g_pattern_build(const pod2g_mesh *m, void *dbuf, size_t bytes, pod2g_pat
   p.n = dim * p.n_nodes;
   p.n_slots = dim == 2 ? 9 : 27;
   p.n_elems = dim == 2 ? N * N : N * N * N;
-  p.nvals = (long long)p.n * p.n_slots * dim;
+  p.nvals = (long long)(p.n + dim) * (p.n_slots / 2 + 1) * dim;   // symmetric half storage
   p.colblk = (int *)dbuf;
   p.kref = (double *)((char *)dbuf + align256((size_t)p.n_slots * p.n_nodes * sizeof(int)));
   const int ED = dim * (1 << dim);

@@ -217,50 +217,111 @@ template <int DIM> struct Stencil {
   static constexpr int ED = DIM * NE;           // element DOFs
 };
 
-// (K x)_row for the block-ELL layout; x is gathered at the neighbour DOFs.
+// Symmetric (half) block-ELL storage.  K is symmetric, so only the centre
+// slot and the "upper" slots of every node are stored -- slot s >= H = S/2,
+// i.e. neighbour offset (dz, dy, dx) > 0 in that order -- with a zero node
+// after the last node of every plane:
+//   vals[((s - H) DIM + b) ns + node DIM + r] = K(node DIM + r, nb_s(node) DIM + b),
+//   ns = n + DIM (plane stride).
+// A lower slot s < H of node i is the transpose of the upper slot S - 1 - s
+// of its neighbour j = nb_s(i): K(i DIM + r, j DIM + b) =
+// vals[((H - s) DIM + r) ns + j DIM + b].  An absent neighbour (colblk
+// points at the node itself) reads the zero node instead.  The values are
+// the same numbers full storage would hold (assembly is exactly symmetric),
+// so every product sums the same terms in the same order.
+template <int DIM> struct Half {
+  static constexpr int S = Stencil<DIM>::S;
+  static constexpr int H = S / 2;        // the centre slot
+  static constexpr int SH = H + 1;       // stored slots per node
+};
+
+// The DIM x DIM block K(node, nb_s(node)) as m[r][b]; c = colblk[s][node].
+// LOWER: s < H (read transposed at the neighbour), else s >= H; a compile-
+// time choice, so that callers iterate over the lower and the upper slots in
+// two loops and no load sits behind a run-time branch (the compiler would
+// then wait for it before going on).
+template <int DIM, typename T, bool LOWER>
+__device__ __forceinline__ void load_block(const T *__restrict__ vals, int s, int node, int c,
+                                           int nn, size_t ns, T m[DIM][DIM]) {
+  constexpr int H = Half<DIM>::H;
+  if (!LOWER) {
+    const T *v = vals + (size_t)((s - H) * DIM) * ns + (size_t)node * DIM;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b)
+#pragma unroll
+      for (int r = 0; r < DIM; ++r) m[r][b] = v[(size_t)b * ns + r];
+  } else {
+    const int j = c == node ? nn : c;
+    const T *v = vals + (size_t)((H - s) * DIM) * ns + (size_t)j * DIM;
+#pragma unroll
+    for (int r = 0; r < DIM; ++r)
+#pragma unroll
+      for (int b = 0; b < DIM; ++b) m[r][b] = v[(size_t)r * ns + b];
+  }
+}
+
+// (K x)_row; x is gathered at the neighbour DOFs.  Lower slots, then upper
+// ones: the same order s = 0 .. S - 1 as a row-wise product.
 template <int DIM, typename T, typename XT>
 __device__ __forceinline__ T row_dot(const int *__restrict__ colblk, const T *__restrict__ vals,
                                      const XT *__restrict__ x, int row, int node, int n, int nn) {
-  constexpr int S = Stencil<DIM>::S;
+  constexpr int S = Stencil<DIM>::S, H = Half<DIM>::H;
+  const size_t ns = (size_t)n + DIM;
+  const int r = row - node * DIM;
   T acc = T(0);
-#pragma unroll 9
-  for (int s = 0; s < S; ++s) {
-    const int c = colblk[s * nn + node];
 #pragma unroll
-    for (int b = 0; b < DIM; ++b)
-      acc += vals[(size_t)(s * DIM + b) * n + row] * (T)x[c * DIM + b];
+  for (int s = 0; s < H; ++s) {
+    const int c = colblk[s * nn + node];
+    const int j = c == node ? nn : c;
+    const T *v = vals + (size_t)((H - s) * DIM + r) * ns + (size_t)j * DIM;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) acc += v[b] * (T)x[c * DIM + b];
+  }
+#pragma unroll
+  for (int s = H; s < S; ++s) {
+    const int c = colblk[s * nn + node];
+    const T *v = vals + (size_t)((s - H) * DIM) * ns + row;
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) acc += v[(size_t)b * ns] * (T)x[c * DIM + b];
   }
   return acc;
 }
 
+// One slot's contribution to (K x) of the node's DIM rows.
+template <int DIM, typename T, bool LOWER, typename XG>
+__device__ __forceinline__ void node_slot(const int *__restrict__ colblk, const T *__restrict__ vals,
+                                          XG xg, int s, int node, int nn, size_t ns, T acc[DIM]) {
+  const int c = colblk[s * nn + node];
+  T xv[DIM];
+#pragma unroll
+  for (int b = 0; b < DIM; ++b) xv[b] = (T)xg((size_t)c * DIM + b);
+  T m[DIM][DIM];
+  load_block<DIM, T, LOWER>(vals, s, node, c, nn, ns, m);
+#pragma unroll
+  for (int b = 0; b < DIM; ++b)
+#pragma unroll
+    for (int r = 0; r < DIM; ++r) acc[r] += m[r][b] * xv[b];
+}
+
 // (K x) for the DIM rows of one node (row = node DIM + r): per neighbour
-// slot one index load, one DIM-wide gather xg(c DIM + b) and DIM DIM-wide
-// value loads (the node's rows are adjacent in every (slot, component)
-// plane).  Each row sums in the order of row_dot, so the results agree
-// with it bit for bit.  UNR: slots unrolled together; 0 = all (every
-// slot's loads in flight at once: in 3D the outer SpMV runs ~10% faster
-// than with 9), a smaller count for gathers that compute their value from
-// several vectors (all 27 slots of those need more than 256 registers).
+// slot one index load, one DIM-wide gather xg(c DIM + b) and the block's
+// DIM x DIM values (the node's rows are adjacent in every stored plane; a
+// lower block's rows are adjacent at the neighbour).  Each row sums in the
+// order of row_dot, so the results agree with it bit for bit.  UNR: slots
+// unrolled together; 0 = all (every slot's loads in flight at once), a
+// smaller count for gathers that compute their value from several vectors
+// (all 27 slots of those need more than 256 registers).
 template <int DIM, typename T, typename XG, int UNR = 0>
 __device__ __forceinline__ void node_dot(const int *__restrict__ colblk, const T *__restrict__ vals,
                                          XG xg, int node, int n, int nn, T acc[DIM]) {
-  constexpr int S = Stencil<DIM>::S;
+  constexpr int S = Stencil<DIM>::S, H = Half<DIM>::H;
+  const size_t ns = (size_t)n + DIM;
 #pragma unroll
   for (int r = 0; r < DIM; ++r) acc[r] = T(0);
-  const T *vn = vals + (size_t)node * DIM;
-#pragma unroll(UNR > 0 ? UNR : S)
-  for (int s = 0; s < S; ++s) {
-    const int c = colblk[s * nn + node];
-    T xv[DIM];
-#pragma unroll
-    for (int b = 0; b < DIM; ++b) xv[b] = (T)xg((size_t)c * DIM + b);
-#pragma unroll
-    for (int b = 0; b < DIM; ++b) {
-      const T *v = vn + (size_t)(s * DIM + b) * n;
-#pragma unroll
-      for (int r = 0; r < DIM; ++r) acc[r] += v[r] * xv[b];
-    }
-  }
+#pragma unroll(UNR > 0 ? UNR : H)
+  for (int s = 0; s < H; ++s) node_slot<DIM, T, true>(colblk, vals, xg, s, node, nn, ns, acc);
+#pragma unroll(UNR > 0 ? UNR : S - H)
+  for (int s = H; s < S; ++s) node_slot<DIM, T, false>(colblk, vals, xg, s, node, nn, ns, acc);
 }
 
 inline int ceil_div(long long a, int b) { return (int)((a + b - 1) / b); }

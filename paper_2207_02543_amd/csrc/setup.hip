@@ -7,6 +7,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <type_traits>
+
 namespace pod2g {
 
 constexpr int KP_CH = 16;  // the node-major basis copy pads k to a multiple of this
@@ -105,14 +107,14 @@ __global__ void __launch_bounds__(NT) k_kp(int n, int nn, int k, long long vstri
   const int node = t / KP_LANES, q = t % KP_LANES;
   if (node >= nn) return;
   constexpr int kpad = 16 * M;
-  const double *v = vals + (size_t)b * vstride + (size_t)node * DIM;
+  const double *vb = vals + (size_t)b * vstride;
+  const size_t ns = (size_t)n + DIM;
   double acc[DIM][2 * M];
 #pragma unroll
   for (int r = 0; r < DIM; ++r)
 #pragma unroll
     for (int jj = 0; jj < 2 * M; ++jj) acc[r][jj] = 0.0;
-#pragma unroll 3
-  for (int s = 0; s < Stencil<DIM>::S; ++s) {
+  auto slot = [&](int s, auto lower) {
     const int c = colblk[s * nn + node];
     const double *pc = Pt + (size_t)c * kpad * DIM + 2 * q;
     kd2 pv[DIM][M];
@@ -120,19 +122,23 @@ __global__ void __launch_bounds__(NT) k_kp(int n, int nn, int k, long long vstri
     for (int bc = 0; bc < DIM; ++bc)
 #pragma unroll
       for (int m = 0; m < M; ++m) pv[bc][m] = *(const kd2 *)(pc + bc * kpad + 16 * m);
+    double kb[DIM][DIM];
+    load_block<DIM, double, decltype(lower)::value>(vb, s, node, c, nn, ns, kb);
 #pragma unroll
-    for (int bc = 0; bc < DIM; ++bc) {
-      double a[DIM];
-#pragma unroll
-      for (int r = 0; r < DIM; ++r) a[r] = v[(size_t)(s * DIM + bc) * n + r];
+    for (int bc = 0; bc < DIM; ++bc)
 #pragma unroll
       for (int m = 0; m < M; ++m)
 #pragma unroll
         for (int e = 0; e < 2; ++e)
 #pragma unroll
-          for (int r = 0; r < DIM; ++r) acc[r][2 * m + e] += a[r] * pv[bc][m][e];
-    }
-  }
+          for (int r = 0; r < DIM; ++r) acc[r][2 * m + e] += kb[r][bc] * pv[bc][m][e];
+  };
+  // lower slots, then the own and upper ones: the order of a row-wise product
+  constexpr int H = Half<DIM>::H;
+#pragma unroll 3
+  for (int s = 0; s < H; ++s) slot(s, std::true_type());
+#pragma unroll 3
+  for (int s = H; s < Stencil<DIM>::S; ++s) slot(s, std::false_type());
   double *out = KP + (size_t)b * k * n + (size_t)node * DIM;
 #pragma unroll
   for (int m = 0; m < M; ++m)

@@ -1319,30 +1319,23 @@ __global__ void __launch_bounds__(NT) k_gs_colour(Ctx c, const T *__restrict__ r
                             : ((col.l0 + 2 * (rest / col.nj)) - 1) * (c.N + 1) * (c.N + 1) +
                                   j * (c.N + 1) + i;
   const size_t off = (size_t)b * c.n;
-  const T *vn = (const T *)c.svals + (size_t)b * c.vstride + (size_t)node * DIM;
+  const T *vb = (const T *)c.svals + (size_t)b * c.vstride;
+  const size_t ns = (size_t)c.n + DIM;
   T *xb = x + off;
   T acc[DIM];
 #pragma unroll
   for (int r = 0; r < DIM; ++r) acc[r] = T(0);
-#pragma unroll 9
-  for (int s = 0; s < S; ++s) {
-    if (s == SC) continue;
-    const int cn = c.colblk[s * c.nn + node];
+  // the other slots in order (lower, then upper past the own block)
 #pragma unroll
-    for (int bc = 0; bc < DIM; ++bc) {
-      const T xv = xb[(size_t)cn * DIM + bc];
-      const T *v = vn + (size_t)(s * DIM + bc) * c.n;
+  for (int s = 0; s < SC; ++s) node_slot<DIM, T, true>(c.colblk, vb, [xb](size_t i) { return xb[i]; },
+                                                       s, node, c.nn, ns, acc);
 #pragma unroll
-      for (int r = 0; r < DIM; ++r) acc[r] += v[r] * xv;
-    }
-  }
+  for (int s = SC + 1; s < S; ++s) node_slot<DIM, T, false>(c.colblk, vb, [xb](size_t i) { return xb[i]; },
+                                                            s, node, c.nn, ns, acc);
   T xo[DIM], kc[DIM][DIM];
 #pragma unroll
   for (int r = 0; r < DIM; ++r) xo[r] = xb[(size_t)node * DIM + r];
-#pragma unroll
-  for (int bc = 0; bc < DIM; ++bc)
-#pragma unroll
-    for (int r = 0; r < DIM; ++r) kc[r][bc] = vn[(size_t)(SC * DIM + bc) * c.n + r];
+  load_block<DIM, T, false>(vb, SC, node, node, c.nn, ns, kc);
   const T *rhs = (rhs_in ? rhs_in + off : cycle_rhs<T>(c, off)) + (size_t)node * DIM;
   const T *dv = (const T *)c.sdinv + off + (size_t)node * DIM;
 #pragma unroll

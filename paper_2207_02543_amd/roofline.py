@@ -1,7 +1,7 @@
 """Algorithmic HBM bytes of the library's kernels, per launch.
 
-Each stored matrix value, index and vector entry a kernel needs is counted
-once; what all instances of a batch share (block-column indices, the basis
+Each stored matrix value (the symmetric half of K), index and vector entry
+a kernel needs is counted once; what all instances of a batch share (block-column indices, the basis
 P) is counted once per launch.  Dividing by a launch's duration gives the
 rate that is compared with the 8 TB/s HBM3E peak; dividing the profiler's
 FETCH_SIZE + WRITE_SIZE bytes by the same count shows how far the kernel's
@@ -30,6 +30,13 @@ KERNEL_PATTERNS = {
 }
 
 
+def stored_values(w):
+    """Values of K stored per instance: the symmetric half of the block-ELL
+    layout (own and upper blocks, planes of n + dim rows)."""
+    S = 3 ** w.dim
+    return (w.n + w.dim) * (S // 2 + 1) * w.dim
+
+
 def _defaults(w, tuning):
     n, B = w.n, w.batch
     small = n * B <= (1 << 20)
@@ -44,7 +51,7 @@ def kernel_bytes(w, kernel, tuning=None, smoother="jacobi"):
     mixed = w.precision == "mixed"
     S = 3 ** w.dim
     n, nn, k, B = w.n, w.n_nodes_free, w.k, w.batch
-    nvals = n * S * w.dim
+    nvals = stored_values(w)
     batched = mixed and 4 <= B <= 32 and k > 0        # MFMA products over the batch
     fuse_dir, fuse_upd = _defaults(w, tuning)
     fuse_upd = fuse_upd and smoother == "jacobi"

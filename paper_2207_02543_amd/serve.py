@@ -35,7 +35,7 @@ assert SLOT_INFO.itemsize == 24
 def slot_bytes(w: I.Workload, k: int, precision: str) -> int:
     """Device bytes one resident query of class w occupies: its K (FP64 and,
     mixed, FP32), D^-1, K P, the coarse factors and the CG vectors."""
-    n, nvals = w.n, w.n * (3 ** w.dim) * w.dim
+    n, nvals = w.n, (w.n + w.dim) * (3 ** w.dim // 2 + 1) * w.dim   # symmetric half of K
     mixed = precision == "mixed"
     b = nvals * 8 + (nvals * 4 if mixed else 0)        # K
     b += n * 8 + (n * 4 if mixed else 0)               # D^-1

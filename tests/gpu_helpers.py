@@ -7,23 +7,27 @@ def flush(msg):
 
 
 def block_ell_expected(K, dim, N, colblk, n):
-    """The oracle's K laid out in the library's block-ELL order
-    vals[(s * dim + b) * n + row] (zero in absent-neighbour slots)."""
+    """The oracle's K laid out in the library's symmetric half block-ELL
+    order: vals[((s - H) * dim + b) * (n + dim) + row] for the own slot H
+    and the upper slots s > H (zero for an absent neighbour), and zero rows
+    n .. n + dim - 1 (the zero node) in every plane."""
     S = 3 ** dim
+    H = S // 2
     nn = n // dim
+    ns = n + dim
     rows = np.arange(n)
     nodes = rows // dim
-    out = np.zeros(S * dim * n)
-    center = S // 2
-    for s in range(S):
+    out = np.zeros((H + 1) * dim * ns)
+    for s in range(H, S):
         nb = colblk[s * nn + nodes]
-        valid = (nb != nodes) | (s == center)
+        valid = (nb != nodes) | (s == H)
         for b in range(dim):
             cols = dim * nb + b
             v = np.asarray(K[rows[valid], cols[valid]]).ravel()
             blk = np.zeros(n)
             blk[valid] = v
-            out[(s * dim + b) * n:(s * dim + b + 1) * n] = blk
+            p = (s - H) * dim + b
+            out[p * ns:p * ns + n] = blk
     return out
 
 

@@ -35,17 +35,26 @@ def _rows(w, count=48, seed=11):
 
 
 def _gpu_rows(prob, sysm, b, rows, torch):
-    """Row dicts {column: value} of instance b from the block-ELL arrays."""
+    """Row dicts {column: value} of instance b from the symmetric half
+    block-ELL arrays: own and upper blocks from the row's node, lower blocks
+    transposed from the neighbour's upper ones."""
     w = prob.w
     S, dim, n, nn = 3 ** w.dim, w.dim, w.n, w.n_nodes_free
+    H, ns = S // 2, w.n + w.dim
     colblk = prob.pat_buf[: S * nn * 4].view(torch.int32)
     rows_t = torch.tensor(rows, device="cuda", dtype=torch.long)
     nodes = rows_t // dim
+    r_t = rows_t - nodes * dim
     out = [dict() for _ in rows]
     for s in range(S):
         cb = colblk[s * nn + nodes].long()
         for c in range(dim):
-            v = sysm.vals[b][(s * dim + c) * n + rows_t].cpu().numpy()
+            if s >= H:
+                idx = ((s - H) * dim + c) * ns + rows_t
+            else:
+                j = torch.where(cb == nodes, torch.full_like(cb, nn), cb)
+                idx = ((H - s) * dim + r_t) * ns + j * dim + c
+            v = sysm.vals[b][idx].cpu().numpy()
             cols = (cb * dim + c).cpu().numpy()
             for i in range(len(rows)):
                 out[i][int(cols[i])] = out[i].get(int(cols[i]), 0.0) + float(v[i])

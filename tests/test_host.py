@@ -45,9 +45,10 @@ def test_slot_planning_shares_free_memory():
     from paper_2207_02543_amd import serve
     classes = [(I.WORKLOADS[nm], 20, "mixed") for nm in ("c4a", "c4b", "c4c")]
     sizes = [serve.slot_bytes(w, k, p) for (w, k, p) in classes]
-    # a c4c slot (3D 48^3, mixed) holds its FP64 and FP32 matrices
+    # a c4c slot (3D 48^3, mixed) holds its FP64 and FP32 matrices (the
+    # symmetric half: 14 of 27 blocks per node)
     w = I.WORKLOADS["c4c"]
-    assert sizes[2] > w.n * 81 * 12
+    assert sizes[2] > (w.n + 3) * 42 * 12
     assert serve.plan_slots(classes, 10 ** 15) == [32, 32, 32]
     assert serve.plan_slots(classes, 10 ** 15, max_slots=7) == [7, 7, 7]
     assert serve.plan_slots(classes, 1) == [1, 1, 1]
@@ -132,21 +133,23 @@ def test_algorithmic_bytes():
     w = I.WORKLOADS["c2"]
     n, nn, k = w.n, w.n_nodes_free, w.k
     assert (n, nn, k) == (131584, 65792, 20)
-    K = n * 9 * 2 * 8          # FP64 values, 9 block slots of 2x2 per node
+    # FP64 values: the own and 4 upper 2x2 blocks per node (symmetric half),
+    # planes of n + 2 rows
+    K = (n + 2) * 5 * 2 * 8
     idx = 9 * nn * 4           # block-column indices
     # restriction: K, x, b read, r' written (for the first post-sweep with
     # K P), P read once
     assert R.kernel_bytes(w, "restrict") == idx + K + 3 * n * 8 + k * n * 8
-    assert R.kernel_bytes(w, "restrict") == 45528064
+    assert R.kernel_bytes(w, "restrict") == 37106848
     # FP32 cycle in 2D keeps the plain post-sweep: no r' to save
     wm = I.with_(w, precision="mixed")
-    assert R.kernel_bytes(wm, "restrict") == idx + k * n * 4 + n * 9 * 2 * 4 + 2 * n * 4
+    assert R.kernel_bytes(wm, "restrict") == idx + k * n * 4 + (n + 2) * 5 * 2 * 4 + 2 * n * 4
     # outer SpMV with the direction update folded in: K, s, p_old read, p, q written
     assert R.kernel_bytes(w, "spmv_pq") == idx + K + 4 * n * 8
     assert R.kernel_bytes(w, "spmv_pq", {"fuse_dir": 0}) == idx + K + 2 * n * 8
     w3 = I.WORKLOADS["c3"]
     n3, nn3, B, k3 = w3.n, w3.n_nodes_free, w3.batch, w3.k
-    K3 = n3 * 27 * 3 * 8
+    K3 = (n3 + 3) * 14 * 3 * 8
     # large batch: the direction update is its own pass; p read, q written
     assert R.kernel_bytes(w3, "spmv_pq") == 27 * nn3 * 4 + B * (K3 + 2 * n3 * 8)
     assert R.kernel_bytes(w3, "pdir") == B * 3 * n3 * 8
