@@ -298,6 +298,8 @@ def serve_bench(args):
     wc = np.array([i for i, m in enumerate(slots) for _ in range(m)])
     serve.run_stream(srv, pools, np.zeros(nw), wc, np.arange(nw) % args.queries, rtol=1e-8,
                      realtime=False)
+    solo = serve.solo_latency(srv, pools, rtol=1e-8)
+    log(f"[serve] solo latency per class (ms): {dict(zip(names, [round(x, 1) for x in solo]))}")
     times, cls, qidx = I.arrivals(args.rate, args.serve_seconds, len(ws), args.queries)
     log(f"[serve] {len(times)} requests over {args.serve_seconds:.0f} s at {args.rate:.0f}/s")
     if args.markers:
@@ -306,7 +308,7 @@ def serve_bench(args):
     if args.markers:
         L.check(L.pod2g_mark(1), "pod2g_mark")
         torch.cuda.synchronize()
-    s = serve.summarize(res, names)
+    s = serve.summarize(res, names, solo)
     srv.close()
     log(f"[serve] {s['completed']} solves in {s['wall_s']:.1f} s; p50 {s['p50_ms']:.1f} ms, "
         f"p99 {s['p99_ms']:.1f} ms; {s['steps']} steps")

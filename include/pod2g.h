@@ -407,6 +407,14 @@ int pod2g_serve_step(pod2g_server *srv, pod2g_slot_info *info_h, hipStream_t str
  * Asynchronous.                                                            */
 int pod2g_serve_step_group(pod2g_server *srv, int group, pod2g_slot_info *info_h,
                            hipStream_t stream);
+/* pod2g_serve_step_group over the group's first slots only: the step graph
+ * of the smallest captured prefix (4, 8, 16, ... slots, else the whole
+ * group) that holds slots 0 .. nslots - 1, so free slots past the last live
+ * one cost no launches.  Slots at or past the prefix must not be running
+ * (they do not advance).  A slot gets the same bits from any prefix.
+ * Asynchronous.  Errors: EINVAL (nslots outside 0 .. group slots), EHIP.   */
+int pod2g_serve_step_prefix(pod2g_server *srv, int group, int nslots,
+                            pod2g_slot_info *info_h, hipStream_t stream);
 int pod2g_server_slots(const pod2g_server *srv);   /* total slots, or EINVAL */
 int pod2g_server_destroy(pod2g_server *srv);
 

@@ -101,6 +101,7 @@ _f = {
     "pod2g_server_admit": _sig("pod2g_server_admit", _i, [_vp, _i, _i, _d, _i, _i, _vp]),
     "pod2g_serve_step": _sig("pod2g_serve_step", _i, [_vp, _vp, _vp]),
     "pod2g_serve_step_group": _sig("pod2g_serve_step_group", _i, [_vp, _i, _vp, _vp]),
+    "pod2g_serve_step_prefix": _sig("pod2g_serve_step_prefix", _i, [_vp, _i, _i, _vp, _vp]),
     "pod2g_server_slots": _sig("pod2g_server_slots", _i, [_vp]),
     "pod2g_server_destroy": _sig("pod2g_server_destroy", _i, [_vp]),
     "pod2g_setup_status": _sig("pod2g_setup_status", _i, [_PR, C.POINTER(_i), C.POINTER(_d), _vp]),
@@ -365,6 +366,10 @@ def pod2g_serve_step(server, info, stream=None) -> int:
 
 def pod2g_serve_step_group(server, group, info, stream=None) -> int:
     return _f["pod2g_serve_step_group"](server, group, _ptr(info), _stream(stream))
+
+
+def pod2g_serve_step_prefix(server, group, nslots, info, stream=None) -> int:
+    return _f["pod2g_serve_step_prefix"](server, group, nslots, _ptr(info), _stream(stream))
 
 
 def pod2g_server_slots(server) -> int:

@@ -1862,6 +1862,11 @@ struct pod2g_server {
     size_t info_off;          // first slot of the group in the info array
     hipGraph_t graph;         // this group's step alone (pod2g_serve_step_group)
     hipGraphExec_t exec;
+    // the step of the first pre_n[i] slots only (pod2g_serve_step_prefix),
+    // for prefixes 4, 8, 16, ... below the group's slot count
+    std::vector<int> pre_n;
+    std::vector<hipGraph_t> pre_graph;
+    std::vector<hipGraphExec_t> pre_exec;
   };
   std::vector<Group> groups;
   int chunk, slots;
@@ -2491,15 +2496,37 @@ int pod2g_server_create(const pod2g_group *groups, int n_groups, int chunk, pod2
     ok = cap && ended;
   }
   if (ok && hipGraphInstantiate(&sv->exec, sv->graph, nullptr, nullptr, 0) != hipSuccess) ok = false;
-  // one graph per group as well, for groups stepped at their own pace
+  // one graph per group as well, for groups stepped at their own pace, and
+  // one per slot prefix: the same kernels and launch parameters over the
+  // first m slots (m >= 4 keeps the batched products, whose sums per slot
+  // do not depend on the batch width, so a slot gets the same bits from any
+  // prefix that holds it)
   for (int g = 0; ok && g < G; ++g) {
+    auto &gr = sv->groups[g];
     ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
     if (!ok) break;
-    serve_group_step(sv->groups[g], chunk, cs);
-    ok = hipStreamEndCapture(cs, &sv->groups[g].graph) == hipSuccess;
-    if (ok && hipGraphInstantiate(&sv->groups[g].exec, sv->groups[g].graph, nullptr, nullptr, 0) !=
-                  hipSuccess)
-      ok = false;
+    serve_group_step(gr, chunk, cs);
+    ok = hipStreamEndCapture(cs, &gr.graph) == hipSuccess;
+    if (ok && hipGraphInstantiate(&gr.exec, gr.graph, nullptr, nullptr, 0) != hipSuccess) ok = false;
+    // (a mixed group wider than the batched products' limit runs per
+    // instance, its prefixes would not: no prefixes then)
+    const bool same_path = !(gr.prec.precision == POD2G_MIXED && gr.c.batch > MAXB);
+    for (int m = BATCH_MFMA_MIN; ok && same_path && m < gr.c.batch; m *= 2) {
+      pod2g_server::Group pre = gr;
+      pre.c.batch = m;
+      hipGraph_t pg = nullptr;
+      hipGraphExec_t pe = nullptr;
+      ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+      if (!ok) break;
+      serve_group_step(pre, chunk, cs);
+      ok = hipStreamEndCapture(cs, &pg) == hipSuccess;
+      if (ok && hipGraphInstantiate(&pe, pg, nullptr, nullptr, 0) != hipSuccess) ok = false;
+      if (pg) {
+        gr.pre_n.push_back(m);
+        gr.pre_graph.push_back(pg);
+        gr.pre_exec.push_back(pe);
+      }
+    }
   }
   for (int g = 0; g < G; ++g) {
     if (done_ev[g]) (void)hipEventDestroy(done_ev[g]);
@@ -2549,6 +2576,23 @@ int pod2g_serve_step_group(pod2g_server *sv, int group, pod2g_slot_info *info_h,
   return POD2G_OK;
 }
 
+int pod2g_serve_step_prefix(pod2g_server *sv, int group, int nslots, pod2g_slot_info *info_h,
+                            hipStream_t stream) {
+  if (!sv || !info_h || group < 0 || group >= (int)sv->groups.size()) return POD2G_EINVAL;
+  const pod2g_server::Group &g = sv->groups[group];
+  if (nslots < 0 || nslots > g.c.batch) return POD2G_EINVAL;
+  hipGraphExec_t e = g.exec;
+  for (size_t i = 0; i < g.pre_n.size(); ++i)
+    if (nslots <= g.pre_n[i] && g.pre_exec[i]) {
+      e = g.pre_exec[i];
+      break;
+    }
+  POD2G_HIP_CHECK(hipGraphLaunch(e, stream));
+  POD2G_HIP_CHECK(hipMemcpyAsync(info_h + g.info_off, g.c.info,
+                                 sizeof(pod2g_slot_info) * g.c.batch, hipMemcpyDeviceToHost, stream));
+  return POD2G_OK;
+}
+
 int pod2g_server_slots(const pod2g_server *sv) { return sv ? sv->slots : POD2G_EINVAL; }
 
 int pod2g_server_destroy(pod2g_server *sv) {
@@ -2556,6 +2600,10 @@ int pod2g_server_destroy(pod2g_server *sv) {
   for (auto &g : sv->groups) {
     if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (g.graph) (void)hipGraphDestroy(g.graph);
+    for (auto e : g.pre_exec)
+      if (e) (void)hipGraphExecDestroy(e);
+    for (auto gr : g.pre_graph)
+      if (gr) (void)hipGraphDestroy(gr);
   }
   if (sv->exec) (void)hipGraphExecDestroy(sv->exec);
   if (sv->graph) (void)hipGraphDestroy(sv->graph);

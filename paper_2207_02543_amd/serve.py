@@ -117,8 +117,15 @@ class Server:
     def step(self, stream=None):
         L.check(L.pod2g_serve_step(self.handle, self.info, stream), "pod2g_serve_step")
 
-    def step_group(self, g: int, stream=None):
-        L.check(L.pod2g_serve_step_group(self.handle, g, self.info, stream), "pod2g_serve_step_group")
+    def step_group(self, g: int, nslots=None, stream=None):
+        """Step class g; with nslots, only its first nslots slots (the
+        smallest captured prefix holding them; the rest must be free)."""
+        if nslots is None:
+            L.check(L.pod2g_serve_step_group(self.handle, g, self.info, stream),
+                    "pod2g_serve_step_group")
+        else:
+            L.check(L.pod2g_serve_step_prefix(self.handle, g, nslots, self.info, stream),
+                    "pod2g_serve_step_prefix")
 
     def slot_info(self) -> np.ndarray:
         """The info copied by the last step (the caller synchronised)."""
@@ -267,13 +274,16 @@ def run_stream(server: Server, pools: list[Pool], times, cls, qidx, rtol, maxit=
 
 def _run_groups(server, pools, times, cls, qidx, rtol, maxit, check_first, realtime) -> RunResult:
     """run_stream with one stream per class: a class is admitted, stepped
-    and retired whenever its previous step has finished."""
+    and retired whenever its previous step has finished.  A request takes
+    the lowest free slot, and a step covers only the slots up to the last
+    live one (pod2g_serve_step_prefix)."""
+    import heapq
     classes = server.classes
     G = len(classes)
     reqs = [Request(i, int(cls[i]), int(qidx[i]), float(times[i]) if realtime else 0.0)
             for i in range(len(times))]
     streams = [torch.cuda.Stream() for _ in range(G)]
-    free = [list(range(c.slots))[::-1] for c in classes]
+    free = [list(range(c.slots)) for c in classes]       # min-heaps of free slots
     live = [dict() for _ in range(G)]           # slot -> request
     queues = [deque() for _ in range(G)]
     inflight = [None] * G
@@ -302,7 +312,7 @@ def _run_groups(server, pools, times, cls, qidx, rtol, maxit, check_first, realt
                             c.out[slot].copy_(c.u[slot], non_blocking=True)
                             r.iters, r.status = int(info[slot]["iter"]), int(info[slot]["status"])
                             r.relres = float(info[slot]["relres"])
-                            free[g].append(slot)
+                            heapq.heappush(free[g], slot)
                             done.append(r)
                     if done:
                         ev = torch.cuda.Event()
@@ -313,13 +323,13 @@ def _run_groups(server, pools, times, cls, qidx, rtol, maxit, check_first, realt
             with torch.cuda.stream(streams[g]):
                 while queues[g] and free[g]:
                     r = queues[g].popleft()
-                    slot = free[g].pop()
+                    slot = heapq.heappop(free[g])
                     p = pools[g]
                     server.admit(g, slot, p.xi[r.q], p.x0[r.q], rtol, maxit)
                     r.slot, r.t_admit = slot, time.perf_counter() - t0
                     live[g][slot] = r
                 if live[g]:
-                    server.step_group(g)
+                    server.step_group(g, nslots=max(live[g]) + 1)
                     ev = torch.cuda.Event()
                     ev.record(streams[g])
                     inflight[g] = ev
@@ -351,7 +361,22 @@ def _run_groups(server, pools, times, cls, qidx, rtol, maxit, check_first, realt
     return res
 
 
-def summarize(res: RunResult, names) -> dict:
+def solo_latency(server: Server, pools: list[Pool], rtol, repeats=3) -> list[float]:
+    """Per class, the median latency (ms) of one request served alone on an
+    otherwise idle server."""
+    out = []
+    for g in range(len(server.classes)):
+        lat = []
+        for rep in range(repeats):
+            res = run_stream(server, pools, np.zeros(1), np.array([g]), np.array([rep % len(pools[g].xi)]),
+                             rtol=rtol, realtime=False)
+            r = res.requests[0]
+            lat.append((r.t_done - r.t_arrive) * 1e3)
+        out.append(float(np.median(lat)))
+    return out
+
+
+def summarize(res: RunResult, names, solo_ms=None) -> dict:
     done = [r for r in res.requests if r.t_done >= 0]
     lat = np.array([r.t_done - r.t_arrive for r in done]) * 1e3
     out = {
@@ -382,4 +407,7 @@ def summarize(res: RunResult, names) -> dict:
             "live_slots_mean": float(np.mean(occ)) if occ else 0.0,
             "live_slots_max": int(max(occ)) if occ else 0,
         }
+        if solo_ms is not None:
+            out["per_class"][nm]["solo_ms"] = solo_ms[i]
+            out["per_class"][nm]["p50_over_solo"] = float(np.percentile(li, 50)) / solo_ms[i]
     return out

@@ -194,3 +194,31 @@ def test_replacement_and_limit_match_one_shot():
     assert info[1]["relres"] < 1e-10 and ref.relres < 1e-10
     assert relerr(uh, ref.u) < 1e-9
     srv.close()
+
+
+def test_prefix_steps_give_the_same_bits():
+    """A slot stepped through the graph of a slot prefix (the first four of
+    eight slots) and through the whole group's graph: same iterations, same
+    bits."""
+    import torch
+    from paper_2207_02543_amd import serve
+    w = I.small(2, 20, k=6, n_train=12)
+    c, P = _class(w, slots=8)
+    pool, qs = _pool(w, 1)
+    srv = serve.Server([c], chunk=4)
+    flush("serve: prefix of 4 of 8 slots against the whole group")
+    results = []
+    for nslots in (2, None):
+        srv.admit(0, 1, pool.xi[0], pool.x0[0], w.tol)
+        for _ in range(2000):
+            srv.step_group(0, nslots=nslots)
+            torch.cuda.synchronize()
+            info = srv.slot_info()
+            if info[1]["done"]:
+                break
+        assert info[1]["done"] and info[1]["status"] == 0
+        results.append((int(info[1]["iter"]), float(info[1]["relres"]), c.u[1].cpu().numpy().copy()))
+    flush(f"  prefix {results[0][0]} iterations, whole group {results[1][0]}")
+    assert results[0][0] == results[1][0] and results[0][1] == results[1][1]
+    np.testing.assert_array_equal(results[0][2], results[1][2])
+    srv.close()
