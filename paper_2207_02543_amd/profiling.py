@@ -161,9 +161,15 @@ def run(workload, out, steps, extra, trace_only=False, mfma=True):
     # raw profiler output (large) under /tmp; progress logs under `out`
     raw = os.path.join("/tmp", "pod2g_prof_" + os.path.basename(out))
     basis = os.path.join("/tmp", f"pod2g_basis_{workload}.pt")
-    bench = [sys.executable, os.path.join(root, "bench.py"), "--workload", workload,
-             "--steps", str(steps), "--warmup", "1", "--no-cpu-baseline", "--markers",
-             "--compare-plain", "0", "--basis-file", basis] + extra
+    serving = workload == "c4"     # the served stream: trace only, no basis file
+    if serving:
+        trace_only = True
+        bench = [sys.executable, os.path.join(root, "bench.py"), "--workload", workload,
+                 "--markers"] + extra
+    else:
+        bench = [sys.executable, os.path.join(root, "bench.py"), "--workload", workload,
+                 "--steps", str(steps), "--warmup", "1", "--no-cpu-baseline", "--markers",
+                 "--compare-plain", "0", "--basis-file", basis] + extra
     calib_cmd = [sys.executable, "-m", "paper_2207_02543_amd.profiling", "calib"]
     env = dict(os.environ, TMPDIR="/tmp", PYTHONPATH=root)
     cmds = []
@@ -177,7 +183,7 @@ def run(workload, out, steps, extra, trace_only=False, mfma=True):
             subprocess.run(cmd, check=True, env=env, cwd="/tmp", timeout=limit, stderr=err)
         return d
 
-    if not os.path.exists(basis):
+    if not serving and not os.path.exists(basis):
         # the offline phase once, outside the profiler
         prep = bench[:2] + ["--workload", workload, "--steps", "1", "--warmup", "0",
                             "--no-cpu-baseline", "--compare-plain", "0", "--basis-file", basis]
