@@ -217,7 +217,7 @@ def run(workload, out, steps, extra, trace_only=False, mfma=True):
         names = available(MFMA_COUNTERS)
         try:
             m = prof(["--pmc"] + names + ["--kernel-include-regex",
-                                          r"k_ptr_b\(|k_prolong_b\(|k_mark"],
+                                          r"k_ptr_b[<(]|k_prolong_b\(|k_mark"],
                      bench, "mfma", 900)
         except (subprocess.SubprocessError, OSError) as e:
             mnote = f"MFMA counter pass failed ({names}): {e}"

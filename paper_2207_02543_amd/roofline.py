@@ -22,11 +22,11 @@ KERNEL_PATTERNS = {
     "sweep": r"k_sweep<\d, \w+, false>",
     "sweep_final": r"k_sweep<\d, \w+, true>",
     "restrict": r"k_resid32<|k_restrict<",
-    "ptr_b": r"k_ptr_b\(",
+    "ptr_b": r"k_ptr_b[<(]",
     "prolong": r"k_prolong",
     "update": r"k_update<|k_update_sweep<",
     "kp": r"k_kp<",
-    "kc": r"k_kc\(",
+    "kc": r"k_kc[<(]",
 }
 
 
