@@ -179,8 +179,10 @@ def run(workload, out, steps, extra, trace_only=False, mfma=True):
         cmd = ["rocprofv3"] + args + ["--output-format", "csv", "-d", d, "-o", "p", "--"] + prog
         cmds.append(shlex.join(cmd))
         print(f"[profiling] {sub}", file=sys.stderr, flush=True)
-        with open(os.path.join(out, f"{sub}_stderr.txt"), "w") as err:
-            subprocess.run(cmd, check=True, env=env, cwd="/tmp", timeout=limit, stderr=err)
+        with open(os.path.join(out, f"{sub}_stderr.txt"), "w") as err, \
+                open(os.path.join(out, f"{sub}_stdout.txt"), "w") as sout:
+            subprocess.run(cmd, check=True, env=env, cwd="/tmp", timeout=limit, stderr=err,
+                           stdout=sout)
         return d
 
     if not serving and not os.path.exists(basis):
@@ -189,8 +191,9 @@ def run(workload, out, steps, extra, trace_only=False, mfma=True):
                             "--no-cpu-baseline", "--compare-plain", "0", "--basis-file", basis]
         cmds.append(shlex.join(prep))
         print("[profiling] offline basis", file=sys.stderr, flush=True)
-        with open(os.path.join(out, "prep_stderr.txt"), "w") as err:
-            subprocess.run(prep, check=True, env=env, timeout=1200, stderr=err)
+        with open(os.path.join(out, "prep_stderr.txt"), "w") as err, \
+                open(os.path.join(out, "prep_stdout.txt"), "w") as sout:
+            subprocess.run(prep, check=True, env=env, timeout=1200, stderr=err, stdout=sout)
     allpat = "|".join(KERNEL_PATTERNS.values()) + "|k_mark"
     t = prof(["--kernel-trace"], bench, "trace", 900)
     # the counter passes run the launch parameters the traced run tuned
