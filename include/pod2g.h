@@ -321,7 +321,8 @@ int pcg_plan_destroy(pod2g_plan *plan);
  * sweep or not, the scalar sums r^T s and p^T q finished by the kernels that read
  * them (each workgroup re-reads the partials) or by the producer's last
  * workgroup, the neighbourhood of each 2D node block staged in LDS or
- * gathered from the caches, and the instance grouping of the node-wise block order
+ * gathered from the caches, the row groups of the batched restriction loaded together
+ * (1, 2, 4), and the instance grouping of the node-wise block order
  * (divisors of the batch up to 8).  It overwrites u and the solve workspace: call it
  * before loading the initial guess.  Synchronous.  out may be NULL.       */
 typedef struct pod2g_tuning {
@@ -331,6 +332,8 @@ typedef struct pod2g_tuning {
   int xwin;                /* > 0: 2D node blocks gather x from LDS (+- xwin nodes staged) */
   int cons;                /* 1: r^T s and p^T q summed by every workgroup of their consumers */
   int fuse_upd;            /* 1: vector update fused with the second pre-relaxation sweep */
+  int ptr_grp;             /* 1, 2 or 4: 16-row groups of the batched restriction's MFMA
+                              contraction loaded together per wave iteration */
   float ms_per_iteration;  /* time of one iteration with the chosen values */
 } pod2g_tuning;
 int pcg_plan_tune(pod2g_plan *plan, int trials, pod2g_tuning *out, hipStream_t stream);
@@ -340,7 +343,7 @@ int pcg_plan_tune(pod2g_plan *plan, int trials, pod2g_tuning *out, hipStream_t s
  * (ms_per_iteration = 0).  bgrid in 1..min(workgroups of n rows, 2048);
  * fuse_dir, cons and fuse_upd 0 or 1; igroup a divisor of the batch up to
  * 8; xwin 0, or positive for LDS staging (2D only: the library sets the
- * window); ms_per_iteration is ignored.  Anything else: POD2G_EINVAL and
+ * window); ptr_grp 1, 2 or 4; ms_per_iteration is ignored.  Anything else: POD2G_EINVAL and
  * the plan is unchanged.  Only bgrid (the partition of the batched
  * restriction's sums) and fuse_upd (the grouping of the ||r||^2 and
  * r^T s_old partials) change rounding; the other parameters give the same

@@ -50,7 +50,8 @@ class Prec(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("bgrid", C.c_int), ("fuse_dir", C.c_int), ("igroup", C.c_int), ("xwin", C.c_int),
-                ("cons", C.c_int), ("fuse_upd", C.c_int), ("ms_per_iteration", C.c_float)]
+                ("cons", C.c_int), ("fuse_upd", C.c_int), ("ptr_grp", C.c_int),
+                ("ms_per_iteration", C.c_float)]
 
 
 class SlotInfo(C.Structure):

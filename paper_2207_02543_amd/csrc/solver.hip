@@ -28,6 +28,7 @@ struct Ctx {
   int cons;                      // r^T s and p^T q finished by their consumers (else by
                                  // the producer's last workgroup)
   int fuse_upd;                  // vector update fused with the second pre-relaxation sweep
+  int ptr_grp;                   // 16-row groups per wave iteration of the batched restriction
   int mixed;                     // FP32 cycle: its input is scaled by a power of two
   long long vstride;
   const int *colblk;
@@ -849,7 +850,7 @@ __global__ void __launch_bounds__(NT) k_update_sweep(Ctx c, const double *__rest
 // one partial per output (k_ptr_sum sums the workgroups, k_coarse_b applies
 // the coarse solves).  VEC: n % 4 == 0, so a group's 16-byte loads are
 // aligned and lie wholly below or wholly above n.
-constexpr int PTR_GRP = 2;        // 16-row groups per wave iteration
+constexpr int PTR_GRP = 2;        // 16-row groups per wave iteration (default; tunable)
 
 template <bool VEC>
 __device__ __forceinline__ f4 ptr_load(const float *__restrict__ row_base, int r, int n) {
@@ -869,8 +870,10 @@ __device__ __forceinline__ f4 ptr_load(const float *__restrict__ row_base, int r
   }
 }
 
-// TJ = ceil(k / 16) basis tiles, TB = ceil(batch / 16) batch tiles.
-template <int TJ, int TB, bool VEC>
+// TJ = ceil(k / 16) basis tiles, TB = ceil(batch / 16) batch tiles, GRP
+// row groups loaded together (a schedule choice: each wave still adds its
+// groups in order, so every GRP gives the same bits).
+template <int TJ, int TB, bool VEC, int GRP>
 __global__ void __launch_bounds__(NT) k_ptr_b(Ctx c, const float *__restrict__ R) {
   __shared__ float Cs[NWAVE][TJ * 16][TB * 16];   // the waves' tiles (at most 32 KB)
   __shared__ int nlive;
@@ -902,10 +905,10 @@ __global__ void __launch_bounds__(NT) k_ptr_b(Ctx c, const float *__restrict__ R
   const long long per = (ngroups + nwaves - 1) / nwaves;
   const long long wv = (long long)g * NWAVE + w;
   const long long gbeg = wv * per, gend = min(ngroups, gbeg + per);
-  for (long long g0 = gbeg; g0 < gend; g0 += PTR_GRP) {
-    f4 a[PTR_GRP][TJ], bv[PTR_GRP][TB];
+  for (long long g0 = gbeg; g0 < gend; g0 += GRP) {
+    f4 a[GRP][TJ], bv[GRP][TB];
 #pragma unroll
-    for (int q = 0; q < PTR_GRP; ++q) {
+    for (int q = 0; q < GRP; ++q) {
       // a group past the share (its rows may exist) or past n loads zeros
       const int r = (g0 + q < gend) ? (int)((g0 + q) * 16) + 4 * kk : n;
 #pragma unroll
@@ -914,7 +917,7 @@ __global__ void __launch_bounds__(NT) k_ptr_b(Ctx c, const float *__restrict__ R
       for (int u = 0; u < TB; ++u) bv[q][u] = ptr_load<VEC>(rb[u], r, n);
     }
 #pragma unroll
-    for (int q = 0; q < PTR_GRP; ++q)
+    for (int q = 0; q < GRP; ++q)
 #pragma unroll
       for (int s4 = 0; s4 < 4; ++s4)
 #pragma unroll
@@ -1486,12 +1489,19 @@ static unsigned xlds(const Ctx &c) {
   return c.xwin ? (unsigned)(sizeof(T) * (size_t)(NT + 2 * c.xwin) * (c.n / c.nn)) : 0u;
 }
 
+template <int TJ, int TB, int GRP>
+static void launch_ptr_b_g(const Ctx &c, const float *R, hipStream_t stream) {
+  if (c.n % 4 == 0)
+    hipLaunchKernelGGL((k_ptr_b<TJ, TB, true, GRP>), dim3(c.bgrid), dim3(NT), 0, stream, c, R);
+  else
+    hipLaunchKernelGGL((k_ptr_b<TJ, TB, false, GRP>), dim3(c.bgrid), dim3(NT), 0, stream, c, R);
+}
+
 template <int TJ, int TB>
 static void launch_ptr_b_t(const Ctx &c, const float *R, hipStream_t stream) {
-  if (c.n % 4 == 0)
-    hipLaunchKernelGGL((k_ptr_b<TJ, TB, true>), dim3(c.bgrid), dim3(NT), 0, stream, c, R);
-  else
-    hipLaunchKernelGGL((k_ptr_b<TJ, TB, false>), dim3(c.bgrid), dim3(NT), 0, stream, c, R);
+  if (c.ptr_grp == 1) launch_ptr_b_g<TJ, TB, 1>(c, R, stream);
+  else if (c.ptr_grp == 4) launch_ptr_b_g<TJ, TB, 4>(c, R, stream);
+  else launch_ptr_b_g<TJ, TB, 2>(c, R, stream);
 }
 
 // the batched restriction with as many basis and batch tiles as k and the
@@ -1548,6 +1558,7 @@ static void fill_ctx(Ctx &c, const pod2g_pattern *pat, const double *vals, int b
   c.fuse_dir = (long long)n * batch <= FUSE_DIR_MAX;
   c.cons = (long long)c.nb * batch * c.nbn <= CONS_MAX;
   c.fuse_upd = (long long)n * batch <= FUSE_DIR_MAX;
+  c.ptr_grp = PTR_GRP;
   c.ps = k > 4 ? k : 4;   // as in layout()
   c.vstride = pat->nvals;
   c.colblk = pat->colblk;
@@ -2327,6 +2338,18 @@ int pcg_plan_tune(pod2g_plan *pl, int trials, pod2g_tuning *out, hipStream_t str
       else c.xwin = keep;
     }
   }
+  if (!grids.empty()) {
+    // row groups of the batched restriction loaded together
+    for (int g : {1, 2, 4}) {
+      if (g == c.ptr_grp) continue;
+      const int keep = c.ptr_grp;
+      c.ptr_grp = g;
+      float ms;
+      if ((st = measure(&ms))) return st;
+      if (ms < best) best = ms;
+      else c.ptr_grp = keep;
+    }
+  }
   for (int g : {1, 2, 4, 8}) {
     if (g == c.igroup || c.batch % g) continue;
     const int keep = c.igroup;
@@ -2344,6 +2367,7 @@ int pcg_plan_tune(pod2g_plan *pl, int trials, pod2g_tuning *out, hipStream_t str
     out->xwin = c.xwin;
     out->cons = c.cons;
     out->fuse_upd = c.fuse_upd;
+    out->ptr_grp = c.ptr_grp;
     out->ms_per_iteration = best;
   }
   return POD2G_OK;
@@ -2356,6 +2380,7 @@ int pcg_plan_configure(pod2g_plan *pl, const pod2g_tuning *cfg) {
   if (cfg->bgrid < 1 || cfg->bgrid > gmax) return POD2G_EINVAL;
   if ((cfg->fuse_dir | cfg->cons | cfg->fuse_upd) & ~1) return POD2G_EINVAL;
   if (cfg->igroup < 1 || cfg->igroup > 8 || c.batch % cfg->igroup) return POD2G_EINVAL;
+  if (cfg->ptr_grp != 1 && cfg->ptr_grp != 2 && cfg->ptr_grp != 4) return POD2G_EINVAL;
   const int xw = cfg->xwin > 0 ? choose_xwin(&pl->pat) : 0;
   if (cfg->xwin < 0 || (cfg->xwin > 0 && xw == 0)) return POD2G_EINVAL;
   const Ctx keep = c;
@@ -2365,6 +2390,7 @@ int pcg_plan_configure(pod2g_plan *pl, const pod2g_tuning *cfg) {
   c.xwin = xw;
   c.cons = cfg->cons;
   c.fuse_upd = cfg->fuse_upd;
+  c.ptr_grp = cfg->ptr_grp;
   const int st = capture_plan(pl);
   if (st) c = keep;
   return st;
@@ -2378,6 +2404,7 @@ int pcg_plan_config(const pod2g_plan *pl, pod2g_tuning *out) {
   out->xwin = pl->c.xwin;
   out->cons = pl->c.cons;
   out->fuse_upd = pl->c.fuse_upd;
+  out->ptr_grp = pl->c.ptr_grp;
   out->ms_per_iteration = 0.f;
   return POD2G_OK;
 }

@@ -185,6 +185,10 @@ class Problem:
         return s
 
 
+# launch parameters of a plan (pod2g_tuning without the timing)
+PLAN_PARAMS = ("bgrid", "fuse_dir", "igroup", "xwin", "cons", "fuse_upd", "ptr_grp")
+
+
 class Plan:
     """Owner of a captured solve plan; keeps its buffers alive."""
 
@@ -200,12 +204,13 @@ class Plan:
         """Pick the launch parameters by timing (overwrites u: call before
         loading the initial guess)."""
         t = L.pcg_plan_tune(self.handle, trials, stream)
-        return {"bgrid": t.bgrid, "fuse_dir": t.fuse_dir, "igroup": t.igroup, "xwin": t.xwin,
-                "cons": t.cons, "fuse_upd": t.fuse_upd, "ms_per_iteration": t.ms_per_iteration}
+        out = {f: getattr(t, f) for f in PLAN_PARAMS}
+        out["ms_per_iteration"] = t.ms_per_iteration
+        return out
 
     def config(self) -> dict:
         t = L.pcg_plan_config(self.handle)
-        return {f: getattr(t, f) for f in ("bgrid", "fuse_dir", "igroup", "xwin", "cons", "fuse_upd")}
+        return {f: getattr(t, f) for f in PLAN_PARAMS}
 
     def configure(self, **params):
         """Set launch parameters (names as in config()); the rest keep their

@@ -99,8 +99,9 @@ def test_tuned_plan_solves_like_eager(dim, N, prec, batch):
 def test_launch_parameters_keep_the_result(dim, N, prec, batch):
     """Each launch parameter set explicitly, one at a time, on the same plan:
     the direction update fused or not, sums finished by consumers or
-    producers, the LDS-staged neighbourhood (2D), the instance grouping give
-    the same bits; the fused vector update (other grouping of the ||r||^2
+    producers, the LDS-staged neighbourhood (2D), the instance grouping and
+    the row groups of the batched restriction loaded together give the
+    same bits; the fused vector update (other grouping of the ||r||^2
     and r^T s_old partials) and the batched restriction's grid (other
     partition of its sums) change rounding only.  Invalid values are
     rejected and leave the plan as it was."""
@@ -136,6 +137,8 @@ def test_launch_parameters_keep_the_result(dim, N, prec, batch):
         variants.append(dict(igroup=2))
     if batch % 4 == 0:
         variants.append(dict(igroup=4))
+    # row groups of the batched restriction loaded together: schedule only
+    variants += [dict(ptr_grp=g) for g in (1, 2, 4) if g != base["ptr_grp"]]
     for v in variants:
         plan.configure(**{**base, **v})
         it, uv = run()
@@ -155,7 +158,8 @@ def test_launch_parameters_keep_the_result(dim, N, prec, batch):
             assert np.linalg.norm(uv[b] - u0[b]) <= 1e-7 * np.linalg.norm(u0[b])
     # invalid values: rejected, plan unchanged
     plan.configure(**base)
-    for bad in [dict(bgrid=0), dict(cons=2), dict(fuse_upd=-1), dict(igroup=3), dict(igroup=16)] + \
+    for bad in [dict(bgrid=0), dict(cons=2), dict(fuse_upd=-1), dict(igroup=3), dict(igroup=16),
+                dict(ptr_grp=3), dict(ptr_grp=0)] + \
             ([dict(xwin=1)] if dim == 3 else []):
         t = capi.Tuning(**{**base, **bad})
         assert capi.pcg_plan_configure(plan.handle, t) == capi.EINVAL, bad
