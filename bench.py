@@ -292,7 +292,8 @@ def serve_bench(args):
         torch.cuda.synchronize()
         log(f"[serve] class {w.name}: n {w.n}, k {w.k}, {m} slots, offline + pool "
             f"{time.perf_counter() - t0:.1f} s")
-    srv = serve.Server(classes, chunk=args.chunk if args.chunk > 0 else 8)
+    shares = [int(x) for x in args.cu_split.split(",")] if args.cu_split else None
+    srv = serve.Server(classes, chunk=args.chunk if args.chunk > 0 else 8, cu_shares=shares)
     # warm-up: every class, every slot once, queued at t = 0
     nw = sum(slots)
     wc = np.array([i for i, m in enumerate(slots) for _ in range(m)])
@@ -321,6 +322,7 @@ def serve_bench(args):
                                "256x256), c4c (3D 48x48x48), k=20 each, tol 1e-8",
                    "rate_per_s": args.rate, "duration_s": args.serve_seconds,
                    "slots": dict(zip(names, slots)), "graph_chunk": srv.chunk,
+                   "cu_split": args.cu_split,
                    "queries_per_class": args.queries},
         "serving": s,
         "roofline": None,
@@ -371,6 +373,9 @@ def main(argv=None):
     ap.add_argument("--hbm-fraction", type=float, default=0.5,
                     help="serving: share of the free HBM given to resident queries")
     ap.add_argument("--max-slots", type=int, default=32, help="serving: slots per class at most")
+    ap.add_argument("--cu-split", default=None,
+                    help="serving: compute units per class, comma-separated (c4a,c4b,c4c); each "
+                         "class then runs on its own share of the GPU")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver "

@@ -419,6 +419,15 @@ int pod2g_serve_step_group(pod2g_server *srv, int group, pod2g_slot_info *info_h
 int pod2g_serve_step_prefix(pod2g_server *srv, int group, int nslots,
                             pod2g_slot_info *info_h, hipStream_t stream);
 int pod2g_server_slots(const pod2g_server *srv);   /* total slots, or EINVAL */
+/* A HIP stream (default priority) whose kernels run only on compute units
+ * cu_first .. cu_first + cu_count - 1 of the current GPU, in the runtime's
+ * CU-mask numbering: a serving loop can give each problem class its own
+ * share of the GPU, so that the small, latency-bound kernels of one class do
+ * not wait for compute units behind the large kernels of another.  Release
+ * with pod2g_stream_destroy.  Errors: EINVAL (range outside the GPU's
+ * compute units), EHIP.                                                    */
+int pod2g_stream_create_cus(int cu_first, int cu_count, hipStream_t *out);
+int pod2g_stream_destroy(hipStream_t stream);
 int pod2g_server_destroy(pod2g_server *srv);
 
 /* ---- profiling markers -------------------------------------------------------

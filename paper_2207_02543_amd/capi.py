@@ -104,6 +104,8 @@ _f = {
     "pod2g_serve_step_group": _sig("pod2g_serve_step_group", _i, [_vp, _i, _vp, _vp]),
     "pod2g_serve_step_prefix": _sig("pod2g_serve_step_prefix", _i, [_vp, _i, _i, _vp, _vp]),
     "pod2g_server_slots": _sig("pod2g_server_slots", _i, [_vp]),
+    "pod2g_stream_create_cus": _sig("pod2g_stream_create_cus", _i, [_i, _i, C.POINTER(_vp)]),
+    "pod2g_stream_destroy": _sig("pod2g_stream_destroy", _i, [_vp]),
     "pod2g_server_destroy": _sig("pod2g_server_destroy", _i, [_vp]),
     "pod2g_setup_status": _sig("pod2g_setup_status", _i, [_PR, C.POINTER(_i), C.POINTER(_d), _vp]),
     "pod2g_apply_bytes": _sig("pod2g_apply_bytes", _sz, [_PR]),
@@ -371,6 +373,17 @@ def pod2g_serve_step_group(server, group, info, stream=None) -> int:
 
 def pod2g_serve_step_prefix(server, group, nslots, info, stream=None) -> int:
     return _f["pod2g_serve_step_prefix"](server, group, nslots, _ptr(info), _stream(stream))
+
+
+def pod2g_stream_create_cus(cu_first: int, cu_count: int) -> int:
+    """A stream on compute units [cu_first, cu_first + cu_count) (raw handle)."""
+    h = C.c_void_p()
+    check(_f["pod2g_stream_create_cus"](cu_first, cu_count, C.byref(h)), "pod2g_stream_create_cus")
+    return h.value
+
+
+def pod2g_stream_destroy(stream: int) -> int:
+    return _f["pod2g_stream_destroy"](stream)
 
 
 def pod2g_server_slots(server) -> int:

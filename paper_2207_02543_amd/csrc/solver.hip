@@ -2620,6 +2620,26 @@ int pod2g_serve_step_prefix(pod2g_server *sv, int group, int nslots, pod2g_slot_
   return POD2G_OK;
 }
 
+int pod2g_stream_create_cus(int cu_first, int cu_count, hipStream_t *out) {
+  if (!out || cu_first < 0 || cu_count < 1) return POD2G_EINVAL;
+  int dev = 0;
+  POD2G_HIP_CHECK(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  POD2G_HIP_CHECK(hipGetDeviceProperties(&prop, dev));
+  const int ncu = prop.multiProcessorCount;
+  if (cu_first + cu_count > ncu) return POD2G_EINVAL;
+  std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+  for (int cu = cu_first; cu < cu_first + cu_count; ++cu) mask[cu / 32] |= 1u << (cu % 32);
+  POD2G_HIP_CHECK(hipExtStreamCreateWithCUMask(out, (uint32_t)mask.size(), mask.data()));
+  return POD2G_OK;
+}
+
+int pod2g_stream_destroy(hipStream_t s) {
+  if (!s) return POD2G_EINVAL;
+  POD2G_HIP_CHECK(hipStreamDestroy(s));
+  return POD2G_OK;
+}
+
 int pod2g_server_slots(const pod2g_server *sv) { return sv ? sv->slots : POD2G_EINVAL; }
 
 int pod2g_server_destroy(pod2g_server *sv) {

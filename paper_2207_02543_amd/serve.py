@@ -95,10 +95,22 @@ class ServedClass:
 
 
 class Server:
-    """The library server over a list of ServedClass groups."""
+    """The library server over a list of ServedClass groups.  cu_shares: a
+    number of compute units per class (None: every class on the whole GPU);
+    each class then steps on a stream restricted to its own units."""
 
-    def __init__(self, classes: list[ServedClass], chunk=8):
+    def __init__(self, classes: list[ServedClass], chunk=8, cu_shares=None):
         self.classes = classes
+        self.cu_streams = None
+        if cu_shares is not None:
+            if len(cu_shares) != len(classes):
+                raise ValueError("one compute-unit share per class")
+            raw, first = [], 0
+            for n in cu_shares:
+                raw.append(L.pod2g_stream_create_cus(first, int(n)))
+                first += int(n)
+            self._raw_streams = raw
+            self.cu_streams = [torch.cuda.ExternalStream(h) for h in raw]
         self.handle = L.pod2g_server_create([c.group() for c in classes], chunk)
         self.chunk = chunk + (chunk & 1)
         self.base = np.cumsum([0] + [c.slots for c in classes])
@@ -135,6 +147,11 @@ class Server:
         if self.handle:
             L.pod2g_server_destroy(self.handle)
             self.handle = None
+        if self.cu_streams is not None:
+            torch.cuda.synchronize()
+            for h in self._raw_streams:
+                L.pod2g_stream_destroy(h)
+            self.cu_streams = None
 
     def __del__(self):
         try:
@@ -282,7 +299,7 @@ def _run_groups(server, pools, times, cls, qidx, rtol, maxit, check_first, realt
     G = len(classes)
     reqs = [Request(i, int(cls[i]), int(qidx[i]), float(times[i]) if realtime else 0.0)
             for i in range(len(times))]
-    streams = [torch.cuda.Stream() for _ in range(G)]
+    streams = server.cu_streams or [torch.cuda.Stream() for _ in range(G)]
     free = [list(range(c.slots)) for c in classes]       # min-heaps of free slots
     live = [dict() for _ in range(G)]           # slot -> request
     queues = [deque() for _ in range(G)]

@@ -222,3 +222,25 @@ def test_prefix_steps_give_the_same_bits():
     assert results[0][0] == results[1][0] and results[0][1] == results[1][1]
     np.testing.assert_array_equal(results[0][2], results[1][2])
     srv.close()
+
+
+def test_compute_unit_shares_keep_the_bits():
+    """A class stepped on a stream restricted to a share of the compute
+    units gives the same bits as on the whole GPU."""
+    import torch
+    from paper_2207_02543_amd import serve
+    w = I.small(2, 20, k=6, n_train=12)
+    c, P = _class(w)
+    pool, qs = _pool(w, 2)
+    out = []
+    for shares in (None, [64]):
+        srv = serve.Server([c], chunk=4, cu_shares=shares)
+        res = serve.run_stream(srv, [pool], np.zeros(2), np.zeros(2, dtype=int), np.arange(2),
+                               rtol=w.tol, realtime=False)
+        torch.cuda.synchronize()
+        out.append(([r.iters for r in res.requests], [c.out[r.slot].numpy().copy() for r in res.requests]))
+        srv.close()
+    flush(f"serve: iterations whole GPU {out[0][0]}, 64 compute units {out[1][0]}")
+    assert out[0][0] == out[1][0]
+    for a, b in zip(out[0][1], out[1][1]):
+        np.testing.assert_array_equal(a, b)
