@@ -424,8 +424,10 @@ int pod2g_server_slots(const pod2g_server *srv);   /* total slots, or EINVAL */
  * CU-mask numbering: a serving loop can give each problem class its own
  * share of the GPU, so that the small, latency-bound kernels of one class do
  * not wait for compute units behind the large kernels of another.  Release
- * with pod2g_stream_destroy.  Errors: EINVAL (range outside the GPU's
- * compute units), EHIP.                                                    */
+ * with pod2g_stream_destroy once nothing refers to the stream any more (no
+ * pending work, no runtime or framework object that recorded an event on
+ * it; a serving process keeps such streams to the end).  Errors: EINVAL
+ * (range outside the GPU's compute units), EHIP.                           */
 int pod2g_stream_create_cus(int cu_first, int cu_count, hipStream_t *out);
 int pod2g_stream_destroy(hipStream_t stream);
 int pod2g_server_destroy(pod2g_server *srv);

@@ -94,6 +94,20 @@ class ServedClass:
         self.u[slot].copy_(x0, non_blocking=True)
 
 
+# Streams restricted to a range of compute units, one per (device, first
+# unit, count), created once and kept for the life of the process: torch's
+# pinned-memory allocator keeps events of the non-blocking copies issued on
+# a stream, so a stream must outlive every pinned buffer ever copied on it.
+_CU_STREAMS: dict = {}
+
+
+def cu_stream(first: int, count: int) -> torch.cuda.ExternalStream:
+    key = (torch.cuda.current_device(), first, count)
+    if key not in _CU_STREAMS:
+        _CU_STREAMS[key] = torch.cuda.ExternalStream(L.pod2g_stream_create_cus(first, count))
+    return _CU_STREAMS[key]
+
+
 class Server:
     """The library server over a list of ServedClass groups.  cu_shares: a
     number of compute units per class (None: every class on the whole GPU);
@@ -105,12 +119,10 @@ class Server:
         if cu_shares is not None:
             if len(cu_shares) != len(classes):
                 raise ValueError("one compute-unit share per class")
-            raw, first = [], 0
+            first, self.cu_streams = 0, []
             for n in cu_shares:
-                raw.append(L.pod2g_stream_create_cus(first, int(n)))
+                self.cu_streams.append(cu_stream(first, int(n)))
                 first += int(n)
-            self._raw_streams = raw
-            self.cu_streams = [torch.cuda.ExternalStream(h) for h in raw]
         self.handle = L.pod2g_server_create([c.group() for c in classes], chunk)
         self.chunk = chunk + (chunk & 1)
         self.base = np.cumsum([0] + [c.slots for c in classes])
@@ -147,11 +159,6 @@ class Server:
         if self.handle:
             L.pod2g_server_destroy(self.handle)
             self.handle = None
-        if self.cu_streams is not None:
-            torch.cuda.synchronize()
-            for h in self._raw_streams:
-                L.pod2g_stream_destroy(h)
-            self.cu_streams = None
 
     def __del__(self):
         try:
