@@ -292,15 +292,28 @@ def serve_bench(args):
         torch.cuda.synchronize()
         log(f"[serve] class {w.name}: n {w.n}, k {w.k}, {m} slots, offline + pool "
             f"{time.perf_counter() - t0:.1f} s")
-    shares = [int(x) for x in args.cu_split.split(",")] if args.cu_split else None
-    srv = serve.Server(classes, chunk=args.chunk if args.chunk > 0 else 8, cu_shares=shares)
+    chunk = args.chunk if args.chunk > 0 else 8
+    shares = None
+    if args.cu_split and args.cu_split != "none":
+        shares = [int(x) for x in args.cu_split.split(",")]
+        if len(shares) != len(classes) or sum(shares) > torch.cuda.get_device_properties(dev).multi_processor_count:
+            raise ValueError(f"--cu-split {args.cu_split}: one share per class, within the GPU")
+    # solo latency of each class on the whole GPU, the reference of the
+    # stream's latencies
+    srv0 = serve.Server(classes, chunk=chunk)
+    solo_whole = serve.solo_latency(srv0, pools, rtol=1e-8)
+    srv0.close()
+    log(f"[serve] solo latency per class on the whole GPU (ms): "
+        f"{dict(zip(names, [round(x, 1) for x in solo_whole]))}")
+    srv = serve.Server(classes, chunk=chunk, cu_shares=shares)
     # warm-up: every class, every slot once, queued at t = 0
     nw = sum(slots)
     wc = np.array([i for i, m in enumerate(slots) for _ in range(m)])
     serve.run_stream(srv, pools, np.zeros(nw), wc, np.arange(nw) % args.queries, rtol=1e-8,
                      realtime=False)
     solo = serve.solo_latency(srv, pools, rtol=1e-8)
-    log(f"[serve] solo latency per class (ms): {dict(zip(names, [round(x, 1) for x in solo]))}")
+    log(f"[serve] solo latency per class on its share (ms): "
+        f"{dict(zip(names, [round(x, 1) for x in solo]))}")
     times, cls, qidx = I.arrivals(args.rate, args.serve_seconds, len(ws), args.queries)
     log(f"[serve] {len(times)} requests over {args.serve_seconds:.0f} s at {args.rate:.0f}/s")
     if args.markers:
@@ -309,7 +322,7 @@ def serve_bench(args):
     if args.markers:
         L.check(L.pod2g_mark(1), "pod2g_mark")
         torch.cuda.synchronize()
-    s = serve.summarize(res, names, solo)
+    s = serve.summarize(res, names, solo, solo_whole)
     srv.close()
     log(f"[serve] {s['completed']} solves in {s['wall_s']:.1f} s; p50 {s['p50_ms']:.1f} ms, "
         f"p99 {s['p99_ms']:.1f} ms; {s['steps']} steps")
@@ -373,9 +386,9 @@ def main(argv=None):
     ap.add_argument("--hbm-fraction", type=float, default=0.5,
                     help="serving: share of the free HBM given to resident queries")
     ap.add_argument("--max-slots", type=int, default=32, help="serving: slots per class at most")
-    ap.add_argument("--cu-split", default=None,
-                    help="serving: compute units per class, comma-separated (c4a,c4b,c4c); each "
-                         "class then runs on its own share of the GPU")
+    ap.add_argument("--cu-split", default="32,64,160",
+                    help="serving: compute units per class, comma-separated (c4a,c4b,c4c), each "
+                         "class on its own share of the GPU; 'none': all classes on the whole GPU")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the solver "

@@ -400,7 +400,10 @@ def solo_latency(server: Server, pools: list[Pool], rtol, repeats=3) -> list[flo
     return out
 
 
-def summarize(res: RunResult, names, solo_ms=None) -> dict:
+def summarize(res: RunResult, names, solo_ms=None, solo_whole_ms=None) -> dict:
+    """Completion, throughput and latency percentiles, overall and per
+    class; with solo latencies (on the class's own compute-unit share, and
+    on the whole GPU) also the p50 over each."""
     done = [r for r in res.requests if r.t_done >= 0]
     lat = np.array([r.t_done - r.t_arrive for r in done]) * 1e3
     out = {
@@ -434,4 +437,8 @@ def summarize(res: RunResult, names, solo_ms=None) -> dict:
         if solo_ms is not None:
             out["per_class"][nm]["solo_ms"] = solo_ms[i]
             out["per_class"][nm]["p50_over_solo"] = float(np.percentile(li, 50)) / solo_ms[i]
+        if solo_whole_ms is not None:
+            out["per_class"][nm]["solo_whole_gpu_ms"] = solo_whole_ms[i]
+            out["per_class"][nm]["p50_over_solo_whole_gpu"] = (float(np.percentile(li, 50))
+                                                               / solo_whole_ms[i])
     return out

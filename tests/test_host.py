@@ -84,6 +84,12 @@ def test_serving_summary():
     assert a["completed"] == 4 and a["p50_ms"] == pytest.approx(25.0) and a["iters_mean"] == 10
     assert b["relres_max"] == pytest.approx(2e-9)
     assert a["live_slots_mean"] == pytest.approx(3.0) and b["live_slots_max"] == 3
+    # against solo latencies (on the class's share and on the whole GPU)
+    s = serve.summarize(res, ["a", "b"], [12.5, 100.0], [10.0, 50.0])
+    a, b = s["per_class"]["a"], s["per_class"]["b"]
+    assert a["p50_over_solo"] == pytest.approx(2.0) and b["p50_over_solo"] == pytest.approx(1.5)
+    assert a["p50_over_solo_whole_gpu"] == pytest.approx(2.5)
+    assert b["solo_whole_gpu_ms"] == 50.0 and b["p50_over_solo_whole_gpu"] == pytest.approx(3.0)
 
 
 def _write_csv(path, header, rows):
