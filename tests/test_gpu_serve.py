@@ -244,3 +244,10 @@ def test_compute_unit_shares_keep_the_bits():
     assert out[0][0] == out[1][0]
     for a, b in zip(out[0][1], out[1][1]):
         np.testing.assert_array_equal(a, b)
+    # ranges outside the GPU's compute units are refused (no stream made)
+    from paper_2207_02543_amd import capi
+    ncu = torch.cuda.get_device_properties(0).multi_processor_count
+    for first, count in ((0, ncu + 1), (-1, 4), (ncu - 2, 3), (0, 0)):
+        with pytest.raises(capi.Pod2gError) as e:
+            capi.pod2g_stream_create_cus(first, count)
+        assert e.value.status == capi.EINVAL
