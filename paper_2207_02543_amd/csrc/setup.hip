@@ -86,34 +86,39 @@ __global__ void __launch_bounds__(NT) k_pt(int n, int k, int kpad, const double 
   }
 }
 
-// K P for one instance per grid row, eight lanes per node (its DIM rows):
-// lane q forms columns 16 m + 2 q and 16 m + 2 q + 1 for m < M (kpad =
-// 16 M).  The eight lanes of a node load the same K values (one request
-// per wave serves them), so K is read from memory once for all k columns;
-// for each component of the neighbour node the eight lanes read 16
-// consecutive basis values (128 bytes, one 16-byte load each) from the
-// node-major copy Pt.  Each entry sums over slots and components in the
-// order of a row-wise product.
+// K P, eight lanes per node (its DIM rows), G instances per thread (grid
+// row y holds instances G y .. G y + G - 1): lane q forms columns 16 m + 2 q
+// and 16 m + 2 q + 1 for m < M (kpad = 16 M).  The eight lanes of a node
+// load the same K values (one request per wave serves them), so K is read
+// from memory once for all k columns; for each component of the neighbour
+// node the eight lanes read 16 consecutive basis values (128 bytes, one
+// 16-byte load each) from the node-major copy Pt, once for the G instances.
+// Each entry sums over slots and components in the order of a row-wise
+// product.
 constexpr int KP_LANES = 8;
 typedef double kd2 __attribute__((ext_vector_type(2)));
 
-template <int DIM, int M>
-__global__ void __launch_bounds__(NT) k_kp(int n, int nn, int k, long long vstride,
+template <int DIM, int M, int G>
+__global__ void __launch_bounds__(NT) k_kp(int n, int nn, int k, int cnt, long long vstride,
                                            const int *__restrict__ colblk,
                                            const double *__restrict__ vals,
                                            const double *__restrict__ Pt, double *__restrict__ KP) {
-  const int b = blockIdx.y;
+  const int b0 = blockIdx.y * G;
   const int t = xcd_block(blockIdx.x, gridDim.x) * NT + threadIdx.x;
   const int node = t / KP_LANES, q = t % KP_LANES;
   if (node >= nn) return;
   constexpr int kpad = 16 * M;
-  const double *vb = vals + (size_t)b * vstride;
   const size_t ns = (size_t)n + DIM;
-  double acc[DIM][2 * M];
+  const double *vb[G];
 #pragma unroll
-  for (int r = 0; r < DIM; ++r)
+  for (int g = 0; g < G; ++g) vb[g] = vals + (size_t)min(b0 + g, cnt - 1) * vstride;   // tail: clamped, not stored
+  double acc[G][DIM][2 * M];
 #pragma unroll
-    for (int jj = 0; jj < 2 * M; ++jj) acc[r][jj] = 0.0;
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int r = 0; r < DIM; ++r)
+#pragma unroll
+      for (int jj = 0; jj < 2 * M; ++jj) acc[g][r][jj] = 0.0;
   auto slot = [&](int s, auto lower) {
     const int c = colblk[s * nn + node];
     const double *pc = Pt + (size_t)c * kpad * DIM + 2 * q;
@@ -122,41 +127,51 @@ __global__ void __launch_bounds__(NT) k_kp(int n, int nn, int k, long long vstri
     for (int bc = 0; bc < DIM; ++bc)
 #pragma unroll
       for (int m = 0; m < M; ++m) pv[bc][m] = *(const kd2 *)(pc + bc * kpad + 16 * m);
-    double kb[DIM][DIM];
-    load_block<DIM, double, decltype(lower)::value>(vb, s, node, c, nn, ns, kb);
 #pragma unroll
-    for (int bc = 0; bc < DIM; ++bc)
+    for (int g = 0; g < G; ++g) {
+      double kb[DIM][DIM];
+      load_block<DIM, double, decltype(lower)::value>(vb[g], s, node, c, nn, ns, kb);
 #pragma unroll
-      for (int m = 0; m < M; ++m)
+      for (int bc = 0; bc < DIM; ++bc)
 #pragma unroll
-        for (int e = 0; e < 2; ++e)
+        for (int m = 0; m < M; ++m)
 #pragma unroll
-          for (int r = 0; r < DIM; ++r) acc[r][2 * m + e] += kb[r][bc] * pv[bc][m][e];
+          for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int r = 0; r < DIM; ++r) acc[g][r][2 * m + e] += kb[r][bc] * pv[bc][m][e];
+    }
   };
   // lower slots, then the own and upper ones: the order of a row-wise product
   constexpr int H = Half<DIM>::H;
-#pragma unroll 3
+#pragma unroll(G == 1 ? 3 : 1)
   for (int s = 0; s < H; ++s) slot(s, std::true_type());
-#pragma unroll 3
+#pragma unroll(G == 1 ? 3 : 1)
   for (int s = H; s < Stencil<DIM>::S; ++s) slot(s, std::false_type());
-  double *out = KP + (size_t)b * k * n + (size_t)node * DIM;
 #pragma unroll
-  for (int m = 0; m < M; ++m)
+  for (int g = 0; g < G; ++g) {
+    if (b0 + g >= cnt) break;
+    double *out = KP + (size_t)(b0 + g) * k * n + (size_t)node * DIM;
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      const int j = 16 * m + 2 * q + e;
-      if (j < k)
+    for (int m = 0; m < M; ++m)
 #pragma unroll
-        for (int r = 0; r < DIM; ++r) out[(size_t)j * n + r] = acc[r][2 * m + e];
-    }
+      for (int e = 0; e < 2; ++e) {
+        const int j = 16 * m + 2 * q + e;
+        if (j < k)
+#pragma unroll
+          for (int r = 0; r < DIM; ++r) out[(size_t)j * n + r] = acc[g][r][2 * m + e];
+      }
+  }
 }
 
+// G: instances per thread, as many as keep the accumulators (G DIM 2M
+// doubles) within about 100 registers
 template <int DIM, int M>
 static void launch_kp_t(const pod2g_pattern *pat, int cnt, int k, const double *vals,
                         const double *Pt, double *KP, hipStream_t stream) {
-  dim3 g(ceil_div(pat->n_nodes * KP_LANES, NT), cnt);
-  hipLaunchKernelGGL((k_kp<DIM, M>), g, dim3(NT), 0, stream, pat->n, pat->n_nodes, k, pat->nvals,
-                     pat->colblk, vals, Pt, KP);
+  constexpr int G = DIM == 2 ? (M <= 2 ? 4 : 2) : 2;
+  dim3 g(ceil_div(pat->n_nodes * KP_LANES, NT), ceil_div(cnt, G));
+  hipLaunchKernelGGL((k_kp<DIM, M, G>), g, dim3(NT), 0, stream, pat->n, pat->n_nodes, k, cnt,
+                     pat->nvals, pat->colblk, vals, Pt, KP);
 }
 
 template <int DIM>
