@@ -318,14 +318,15 @@ def serve_bench(args):
     log(f"[serve] {len(times)} requests over {args.serve_seconds:.0f} s at {args.rate:.0f}/s")
     if args.markers:
         L.check(L.pod2g_mark(0), "pod2g_mark")
-    res = serve.run_stream(srv, pools, times, cls, qidx, rtol=1e-8, check_first=4)
+    res = serve.run_stream(srv, pools, times, cls, qidx, rtol=1e-8, check_first=4,
+                           max_queue=args.max_queue)
     if args.markers:
         L.check(L.pod2g_mark(1), "pod2g_mark")
         torch.cuda.synchronize()
     s = serve.summarize(res, names, solo, solo_whole)
     srv.close()
-    log(f"[serve] {s['completed']} solves in {s['wall_s']:.1f} s; p50 {s['p50_ms']:.1f} ms, "
-        f"p99 {s['p99_ms']:.1f} ms; {s['steps']} steps")
+    log(f"[serve] {s['completed']} solves in {s['wall_s']:.1f} s ({s['refused']} refused); "
+        f"p50 {s['p50_ms']:.1f} ms, p99 {s['p99_ms']:.1f} ms; {s['steps']} steps")
     result = {
         "metric": METRIC, "value": s["solves_per_s"], "unit": "solves/s", "n_gpus": 1,
         "steps": s["steps"], "warmup": nw, "ms_per_step": s["wall_s"] / max(1, s["steps"]) * 1e3,
@@ -335,7 +336,7 @@ def serve_bench(args):
                                "256x256), c4c (3D 48x48x48), k=20 each, tol 1e-8",
                    "rate_per_s": args.rate, "duration_s": args.serve_seconds,
                    "slots": dict(zip(names, slots)), "graph_chunk": srv.chunk,
-                   "cu_split": args.cu_split,
+                   "cu_split": args.cu_split, "max_queue": args.max_queue,
                    "queries_per_class": args.queries},
         "serving": s,
         "roofline": None,
@@ -386,6 +387,9 @@ def main(argv=None):
     ap.add_argument("--hbm-fraction", type=float, default=0.5,
                     help="serving: share of the free HBM given to resident queries")
     ap.add_argument("--max-slots", type=int, default=32, help="serving: slots per class at most")
+    ap.add_argument("--max-queue", type=int, default=None,
+                    help="serving: refuse a request when this many of its class already wait "
+                         "for a slot (default: queue without bound)")
     ap.add_argument("--cu-split", default="32,64,160",
                     help="serving: compute units per class, comma-separated (c4a,c4b,c4c), each "
                          "class on its own share of the GPU; 'none': all classes on the whole GPU")

@@ -208,17 +208,24 @@ class RunResult:
     wall: float = 0.0
 
 
+REFUSED = 1000    # Request.status of a request the loop turned away (queue full)
+
+
 def run_stream(server: Server, pools: list[Pool], times, cls, qidx, rtol, maxit=5000,
-               check_first=0, realtime=True, independent=True) -> RunResult:
+               check_first=0, realtime=True, independent=True, max_queue=None) -> RunResult:
     """Serve the request stream (arrival times in s from the start, class
     and pool index per request).  With realtime, requests become visible at
     their arrival times; otherwise all are queued at t = 0.  The results of
     the first `check_first` requests of every class are compared with u*
     (relative error); every result is copied to the host.  independent:
     every class is stepped on its own stream at its own pace (otherwise one
-    step advances all classes together)."""
+    step advances all classes together).  max_queue: a request that arrives
+    while its class already has this many requests waiting for a slot is
+    refused (status REFUSED, no result) instead of queued (independent
+    stepping only)."""
     if independent:
-        return _run_groups(server, pools, times, cls, qidx, rtol, maxit, check_first, realtime)
+        return _run_groups(server, pools, times, cls, qidx, rtol, maxit, check_first, realtime,
+                           max_queue)
     classes = server.classes
     reqs = [Request(i, int(cls[i]), int(qidx[i]), float(times[i]) if realtime else 0.0)
             for i in range(len(times))]
@@ -296,7 +303,8 @@ def run_stream(server: Server, pools: list[Pool], times, cls, qidx, rtol, maxit=
     return res
 
 
-def _run_groups(server, pools, times, cls, qidx, rtol, maxit, check_first, realtime) -> RunResult:
+def _run_groups(server, pools, times, cls, qidx, rtol, maxit, check_first, realtime,
+                max_queue=None) -> RunResult:
     """run_stream with one stream per class: a class is admitted, stepped
     and retired whenever its previous step has finished.  A request takes
     the lowest free slot, and a step covers only the slots up to the last
@@ -319,7 +327,11 @@ def _run_groups(server, pools, times, cls, qidx, rtol, maxit, check_first, realt
     while True:
         now = time.perf_counter() - t0
         while nxt < len(reqs) and reqs[nxt].t_arrive <= now:
-            queues[reqs[nxt].ci].append(reqs[nxt])
+            r = reqs[nxt]
+            if max_queue is not None and len(queues[r.ci]) >= max_queue:
+                r.status = REFUSED
+            else:
+                queues[r.ci].append(r)
             nxt += 1
         for g in range(G):
             c = classes[g]
@@ -409,6 +421,7 @@ def summarize(res: RunResult, names, solo_ms=None, solo_whole_ms=None) -> dict:
     out = {
         "requests": len(res.requests),
         "completed": len(done),
+        "refused": sum(1 for r in res.requests if r.status == REFUSED),
         "failed": sum(1 for r in done if r.status != L.OK),
         "wall_s": res.wall,
         "solves_per_s": len(done) / res.wall if res.wall > 0 else 0.0,

@@ -251,3 +251,21 @@ def test_compute_unit_shares_keep_the_bits():
         with pytest.raises(capi.Pod2gError) as e:
             capi.pod2g_stream_create_cus(first, count)
         assert e.value.status == capi.EINVAL
+
+
+def test_full_queue_refuses_requests():
+    """With a bound on the requests waiting for a slot, arrivals beyond it
+    are refused and the admitted ones complete."""
+    import torch
+    from paper_2207_02543_amd import serve
+    w = I.small(2, 16, k=6, n_train=12)
+    c, P = _class(w)
+    pool, qs = _pool(w, 2)
+    srv = serve.Server([c], chunk=4)
+    res = serve.run_stream(srv, [pool], np.zeros(10), np.zeros(10, dtype=int), np.arange(10) % 2,
+                           rtol=w.tol, realtime=False, max_queue=3)
+    torch.cuda.synchronize()
+    s = serve.summarize(res, ["a"])
+    flush(f"serve: {s['completed']} completed, {s['refused']} refused")
+    assert s["completed"] == 3 and s["refused"] == 7 and s["failed"] == 0
+    srv.close()

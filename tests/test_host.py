@@ -76,7 +76,7 @@ def test_serving_summary():
     res = serve.RunResult(requests=reqs, occupancy=[(0.0, [2, 1]), (1.0, [4, 3])], steps=7, wall=2.0)
     s = serve.summarize(res, ["a", "b"])
     all_lat = [10, 20, 30, 40, 100, 200]
-    assert s["requests"] == 7 and s["completed"] == 6 and s["failed"] == 0
+    assert s["requests"] == 7 and s["completed"] == 6 and s["failed"] == 0 and s["refused"] == 0
     assert s["solves_per_s"] == pytest.approx(3.0)
     assert s["p50_ms"] == pytest.approx(np.percentile(all_lat, 50))
     assert s["p99_ms"] == pytest.approx(np.percentile(all_lat, 99))
