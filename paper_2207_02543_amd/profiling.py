@@ -179,10 +179,22 @@ def run(workload, out, steps, extra, trace_only=False, mfma=True):
         cmd = ["rocprofv3"] + args + ["--output-format", "csv", "-d", d, "-o", "p", "--"] + prog
         cmds.append(shlex.join(cmd))
         print(f"[profiling] {sub}", file=sys.stderr, flush=True)
-        with open(os.path.join(out, f"{sub}_stderr.txt"), "w") as err, \
-                open(os.path.join(out, f"{sub}_stdout.txt"), "w") as sout:
-            subprocess.run(cmd, check=True, env=env, cwd="/tmp", timeout=limit, stderr=err,
-                           stdout=sout)
+        so = os.path.join(out, f"{sub}_stdout.txt")
+        with open(os.path.join(out, f"{sub}_stderr.txt"), "w") as err, open(so, "w") as sout:
+            rc = subprocess.run(cmd, env=env, cwd="/tmp", timeout=limit, stderr=err,
+                                stdout=sout).returncode
+        if rc != 0:
+            # the profiler can crash in its own teardown after the program
+            # has finished: accept the run only when the program's result
+            # line was printed and the profiler's tables were written
+            with open(so) as fh:
+                done = any(ln.startswith('{"metric"') for ln in fh)
+            tables = [x for x in (os.listdir(d) if os.path.isdir(d) else [])
+                      if x.endswith(".csv") and os.path.getsize(os.path.join(d, x)) > 0]
+            if rc not in (-11, 139) or not done or not tables:
+                raise subprocess.CalledProcessError(rc, cmd)
+            print(f"[profiling] {sub}: profiler ended with status {rc} after the program "
+                  f"finished; {len(tables)} result tables written", file=sys.stderr, flush=True)
         return d
 
     if not serving and not os.path.exists(basis):
