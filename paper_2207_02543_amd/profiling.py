@@ -49,7 +49,36 @@ def trace_summary(path):
     for name, d in sorted(agg.items(), key=lambda kv: -sum(kv[1])):
         out.append(f"{len(d):5d} {sum(d) / len(d):8.2f} {min(d):7.2f} {max(d):7.2f} "
                    f"{sum(d):9.0f}  {name}")
+    out.append(idle_summary(rows))
     return "\n".join(out)
+
+
+def idle_summary(rows):
+    """Where the device had no kernel running inside the region: wall time
+    from the first start to the last end, busy time (union of the kernels'
+    intervals) and the idle gaps between them; gaps above 20 us are counted
+    apart (the host's turn between captured chunks)."""
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows)
+    if not iv:
+        return "## idle: no dispatches in the region"
+    busy, gaps, cur_s, cur_e = 0, [], iv[0][0], iv[0][1]
+    for s, e in iv[1:]:
+        if s > cur_e:
+            busy += cur_e - cur_s
+            gaps.append((s - cur_e) / 1e3)
+            cur_s, cur_e = s, e
+        else:
+            cur_e = max(cur_e, e)
+    busy += cur_e - cur_s
+    wall = (cur_e - iv[0][0]) / 1e3
+    gaps.sort()
+    big = [g for g in gaps if g > 20.0]
+    small = [g for g in gaps if g <= 20.0]
+    med = small[len(small) // 2] if small else 0.0
+    return (f"## idle: wall {wall / 1e3:.2f} ms, kernels busy {busy / 1e6:.2f} ms "
+            f"({busy / 1e3 / wall:.1%}); {len(small)} gaps <= 20 us total "
+            f"{sum(small) / 1e3:.2f} ms (median {med:.2f} us); {len(big)} gaps > 20 us "
+            f"total {sum(big) / 1e3:.2f} ms")
 
 
 def counter_summary(path):
