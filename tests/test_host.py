@@ -109,7 +109,10 @@ def test_trace_and_counter_summaries_keep_the_marked_region(tmp_path):
             (7, "k_spmv_pq<3>", 16000, 99000)]
     _write_csv(tr, ["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"], rows)
     out = profiling.trace_summary(str(tr)).splitlines()
-    assert len(out) == 3
+    assert len(out) == 4
+    # the three region dispatches run back to back: busy all of the 7 us
+    assert out[3].startswith("## idle: wall 0.01 ms") and "(100.0%)" in out[3]
+    assert "0 gaps <= 20 us" in out[3] and "0 gaps > 20 us" in out[3]
     calls, mean, mn, mx, tot, name = out[1].split()
     assert name == "k_spmv_pq<3>" and int(calls) == 2
     assert float(mean) == pytest.approx(3.0) and float(mn) == 2.0 and float(mx) == 4.0
@@ -169,3 +172,14 @@ def test_algorithmic_bytes():
     assert R.kernel_bytes(w, "update", {"fuse_upd": 1}, "sgs") == R.kernel_bytes(w, "update", {"fuse_upd": 0})
     for key in R.KERNEL_PATTERNS:
         assert R.kernel_bytes(w3, key) > 0
+
+
+def test_idle_summary_counts_gaps_and_overlaps():
+    from paper_2207_02543_amd import profiling
+    # two overlapping kernels (one busy stretch), a 0.5 us gap, a 56 us host turn
+    rows = [{"Start_Timestamp": str(a), "End_Timestamp": str(b)}
+            for a, b in [(0, 1000), (1500, 3000), (2500, 4000), (60000, 61000)]]
+    line = profiling.idle_summary(rows)
+    assert "wall 0.06 ms" in line and "(7.4%)" in line
+    assert "1 gaps <= 20 us total 0.00 ms (median 0.50 us)" in line
+    assert "1 gaps > 20 us total 0.06 ms" in line
