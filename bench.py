@@ -41,9 +41,12 @@ DOMINANT = {"c1": "restrict", "c2": "restrict", "c4a": "restrict", "c4b": "restr
             "c3": "spmv_pq", "c4c": "spmv_pq", "c5": "spmv_pq"}
 
 
-def plain_baseline(prob, P, xi_d, x0, ustar, count, chunk):
+def plain_baseline(prob, P, xi_d, x0, ustar, count, chunk, sample64=None):
     """The one-solve-at-a-time FP64 path on the same queries: assembly,
-    FP64 setup and a captured FP64 PCG per query (batch 1)."""
+    FP64 setup and a captured FP64 PCG per query (batch 1).  With the
+    oracle's FP64 iterate of query 0 after m iterations (sample64), the
+    same path is stopped after m iterations from the same warm start and
+    the two iterates are compared."""
     import numpy as np
     import torch
     from paper_2207_02543_amd import capi as L
@@ -75,10 +78,23 @@ def plain_baseline(prob, P, xi_d, x0, ustar, count, chunk):
     dt = time.perf_counter() - t0
     for j in [count - 1]:
         errs.append(float(torch.linalg.norm(u[0] - ustar[j]) / torch.linalg.norm(ustar[j])))
+    out = {"value": count / dt, "unit": "solves/s", "solves": count,
+           "iters_mean": float(np.mean(iters)), "err_vs_fp64_last": errs[0],
+           "path": "FP64 cycle and PCG, one query per solve (batch 1), captured chunks"}
+    if sample64 is not None:
+        m = int(sample64["iters"])
+        sysm.xi.copy_(xi_d[:1])
+        prob.assemble(sysm)
+        prob.setup(sysm, P, key="setup_plain")
+        u.copy_(x0[:1])
+        ret, its, rr, st = plan.solve(w.tol, maxit=m, beta=L.BETA_FR)
+        ug, ur, x00 = u[0].cpu().numpy(), sample64["u"], x0[0].cpu().numpy()
+        d = float(np.linalg.norm(ug - ur))
+        out["oracle_iterate"] = {"iters_gpu": int(its[0]), "iters_oracle": m,
+                                 "rel_diff": d / float(np.linalg.norm(ur)),
+                                 "rel_diff_of_correction": d / float(np.linalg.norm(ur - x00))}
     plan.close()
-    return {"value": count / dt, "unit": "solves/s", "solves": count,
-            "iters_mean": float(np.mean(iters)), "err_vs_fp64_last": errs[0],
-            "path": "FP64 cycle and PCG, one query per solve (batch 1), captured chunks"}
+    return out
 
 
 # ---- CPU baseline: the oracle on the host's cores ------------------------------
@@ -175,6 +191,16 @@ def _oracle_leg(conn, wname, overrides, nq, seconds, full_max_n, sample_iters):
                 t_iter = (time.perf_counter() - t) / max(1, r.iters)
                 run.update(kind="sampled", t_assembly=t_asm, t_setup=t_setup, t_iter=t_iter,
                            iters=r.iters)
+                if threads == 1:
+                    # the iterate after the sampled iterations, for the parity
+                    # checks, and the FP64 method's (the plain path's) beside it
+                    out["iterate"] = {"u": r.u, "iters": r.iters}
+                    if mixed:
+                        M64 = twogrid.TwoGrid(K, P, w.omega, w.nu_pre, w.nu_post, precision="fp64")
+                        r64 = opcg.pcg(K, f, x0s[0], M64, tol=w.tol, maxit=sample_iters, beta="fr")
+                        out["iterate64"] = {"u": r64.u, "iters": r64.iters}
+                    else:
+                        out["iterate64"] = out["iterate"]
                 print(f"[bench] oracle ({threads} thread{'s' * (threads > 1)}): assembly "
                       f"{t_asm:.1f} s, setup {t_setup:.1f} s, {t_iter:.2f} s per PCG iteration "
                       f"({r.iters} timed)", file=sys.stderr, flush=True)
@@ -228,6 +254,11 @@ class OracleLeg:
             self.proc.join(5)
             if self.proc.is_alive():
                 self.proc.kill()
+
+    def iterate(self, fp64=False):
+        """The oracle's iterate of query 0 after the sampled iterations
+        (sampled runs; fp64: the FP64 method's), or None."""
+        return None if self.result is None else self.result.get("iterate64" if fp64 else "iterate")
 
     def summary(self, gpu_iters_mean):
         """The cpu_baseline entry: solves/s on every usable core, with the
@@ -550,6 +581,29 @@ def main(argv=None):
                         "iters_diff_max": int(max(abs(g - o) for g, o in zip(gpu_its, o_its)))}
         log(f"[bench] against the oracle on {m} queries: rel. error <= {max(errs):.2e}, "
             f"iterations GPU {gpu_its} oracle {o_its}")
+    sample = leg.iterate() if leg is not None else None
+    if sample is not None and args.solver == "pcg" and args.warm == "noisy":
+        # too large for a full oracle solve: the GPU batch holding query 0, in
+        # the timed launch configuration, stopped after as many iterations as
+        # the oracle ran from the same warm start; query 0's iterates compared
+        ids = [b % Q for b in range(w.batch)]
+        sysm.xi.copy_(xi_d[ids])
+        prob.assemble(sysm)
+        prec = prob.setup(sysm, P, precision=precision, smoother=smoother)
+        u.copy_(x0[ids])
+        m_it = int(sample["iters"])
+        ret, its, rr, st = (plan.solve(w.tol, maxit=m_it) if plan is not None
+                            else prob.solve(sysm, prec, u, maxit=m_it))
+        ug, ur, x00 = u[0].cpu().numpy(), sample["u"], x0[0].cpu().numpy()
+        d = float(np.linalg.norm(ug - ur))
+        oracle_check = {"queries": 1, "kind": f"iterate after {m_it} iterations from the same "
+                        "warm start (a full oracle solve exceeds the bounded sample)",
+                        "iters_gpu": [int(its[0])], "iters_oracle": [m_it],
+                        "rel_diff": d / float(np.linalg.norm(ur)),
+                        "rel_diff_of_correction": d / float(np.linalg.norm(ur - x00))}
+        log(f"[bench] against the oracle's iterate after {m_it} iterations (query 0): "
+            f"GPU {its[0]} iterations, |u_gpu - u_oracle| / |u_oracle - x0| = "
+            f"{oracle_check['rel_diff_of_correction']:.2e}")
     if plan is not None:
         plan.close()
     L.pod2g_timer_destroy(timer)
@@ -594,11 +648,18 @@ def main(argv=None):
     ncmp = args.compare_plain if args.compare_plain is not None else (4 if w.batch > 1 else 0)
     if ncmp > 0:
         log(f"[bench] timing {ncmp} one-at-a-time FP64 solves of the same queries ...")
-        pl = plain_baseline(prob, P, xi_d, x0, ustar, ncmp, args.chunk if args.chunk > 0 else 8)
+        s64 = leg.iterate(fp64=True) if leg is not None and args.warm == "noisy" else None
+        pl = plain_baseline(prob, P, xi_d, x0, ustar, ncmp, args.chunk if args.chunk > 0 else 8,
+                            sample64=s64)
         pl["speedup_batched"] = value / pl["value"]
         result["plain_fp64"] = pl
         log(f"[bench] plain FP64: {pl['value']:.2f} solves/s ({pl['iters_mean']:.1f} iterations); "
             f"batched {w.precision}: x{pl['speedup_batched']:.2f}")
+        if "oracle_iterate" in pl:
+            oi = pl["oracle_iterate"]
+            log(f"[bench] plain FP64 path against the oracle's FP64 iterate after "
+                f"{oi['iters_oracle']} iterations (query 0): |u_gpu - u_oracle| / |u_oracle - x0| "
+                f"= {oi['rel_diff_of_correction']:.2e}")
     if leg is not None:
         result["cpu_baseline"] = leg.summary(float(np.mean(stats["iters"])))
     print(json.dumps(result), flush=True)
