@@ -96,6 +96,22 @@ def test_batched_mfma_shapes(dim, N, k, batch):
     _pcg_check(w, P, xis, prob, sysm, pr, True)
 
 
+# the coarse sizes at the limits: k = 64 (POD2G_MAX_K: four full 16-column
+# tiles, no padding) and k = 1 (one column in a 16-wide tile), batched mixed
+# (MFMA products) and one-query FP64
+@pytest.mark.parametrize("dim,N,k,batch,mixed", [(2, 12, 64, 8, True), (3, 4, 64, 4, True),
+                                                 (2, 12, 64, 1, False), (2, 10, 1, 4, True),
+                                                 (3, 4, 1, 1, False)])
+def test_coarse_size_limits(dim, N, k, batch, mixed):
+    flush(f"coarse size limit dim={dim} N={N} k={k} batch={batch} {'mixed' if mixed else 'fp64'}")
+    w = I.small(dim, N, k=k, n_train=k + 4, precision="mixed" if mixed else "fp64")
+    P, lam, U = oprob.basis(w, I.train_xis(w))
+    xis = I.query_xis(w, batch)
+    prob, sysm, pr = _gpu(w, P, xis, mixed)
+    _cycle_check(w, P, xis, prob, pr, mixed, 5e-6 if mixed else 1e-12)
+    _pcg_check(w, P, xis, prob, sysm, pr, mixed)
+
+
 # more than 32 workgroups per instance (2D N=128: 129 row and 65 node
 # workgroups; 3D N=16: 55 and 28+), in both places the scalar sums can be
 # finished and with the update fused or not
