@@ -582,7 +582,7 @@ def main(argv=None):
         log(f"[bench] against the oracle on {m} queries: rel. error <= {max(errs):.2e}, "
             f"iterations GPU {gpu_its} oracle {o_its}")
     sample = leg.iterate() if leg is not None else None
-    if sample is not None and args.solver == "pcg" and args.warm == "noisy":
+    if sample is not None and args.solver == "pcg":
         # too large for a full oracle solve: the GPU batch holding query 0, in
         # the timed launch configuration, stopped after as many iterations as
         # the oracle ran from the same warm start; query 0's iterates compared
@@ -648,7 +648,7 @@ def main(argv=None):
     ncmp = args.compare_plain if args.compare_plain is not None else (4 if w.batch > 1 else 0)
     if ncmp > 0:
         log(f"[bench] timing {ncmp} one-at-a-time FP64 solves of the same queries ...")
-        s64 = leg.iterate(fp64=True) if leg is not None and args.warm == "noisy" else None
+        s64 = leg.iterate(fp64=True) if leg is not None else None
         pl = plain_baseline(prob, P, xi_d, x0, ustar, ncmp, args.chunk if args.chunk > 0 else 8,
                             sample64=s64)
         pl["speedup_batched"] = value / pl["value"]
