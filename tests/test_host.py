@@ -183,3 +183,42 @@ def test_idle_summary_counts_gaps_and_overlaps():
     assert "wall 0.06 ms" in line and "(7.4%)" in line
     assert "1 gaps <= 20 us total 0.00 ms (median 0.50 us)" in line
     assert "1 gaps > 20 us total 0.06 ms" in line
+
+
+def test_oracle_leg_samples_and_returns_the_iterates():
+    """The CPU-baseline leg run in this process on c1 with the sampled
+    branch forced (full_max_n = 0): it returns query 0's iterates after the
+    sampled iterations, in the workload's precision and in FP64, equal to
+    the oracle's own runs from the same start; the summary extrapolates
+    assembly + setup + iterations to the given iteration count."""
+    import multiprocessing as mp
+    import threading
+    import bench
+    from oracle import fem, pcg as opcg, problem as oprob, twogrid
+    from paper_2207_02543_amd import inputs as I
+    w = I.with_(I.WORKLOADS["c1"], precision="mixed")
+    P, lam, U = oprob.basis(w, I.train_xis(w))
+    q = oprob.query(w, I.query_xis(w, 1)[0], I.noise(w, 0))
+    a, b = mp.Pipe()
+    t = threading.Thread(target=a.send, args=({"P": P, "x0": q.x0[None]},), daemon=True)
+    t.start()
+    bench._oracle_leg(b, "c1", {"precision": "mixed"}, 1, 1.0, 0, 4)
+    out = a.recv()
+    t.join(5)
+    assert all(r["kind"] == "sampled" and r["iters"] == 4 for r in out["runs"].values())
+    f = fem.traction_load(w.dim, w.N)
+    want = opcg.pcg(q.K, f, q.x0, twogrid.TwoGrid(q.K, P, w.omega, w.nu_pre, w.nu_post,
+                                                  precision="fp32"), tol=w.tol, maxit=4, beta="pr")
+    want64 = opcg.pcg(q.K, f, q.x0, twogrid.TwoGrid(q.K, P, w.omega, w.nu_pre, w.nu_post,
+                                                    precision="fp64"), tol=w.tol, maxit=4, beta="fr")
+    assert out["iterate"]["iters"] == out["iterate64"]["iters"] == 4
+    np.testing.assert_array_equal(out["iterate"]["u"], want.u)
+    np.testing.assert_array_equal(out["iterate64"]["u"], want64.u)
+    assert np.linalg.norm(want.u - want64.u) > 0.0    # the two precisions differ
+    leg = object.__new__(bench.OracleLeg)
+    leg.w, leg.result = w, out
+    assert leg.iterate() is out["iterate"] and leg.iterate(fp64=True) is out["iterate64"]
+    s = leg.summary(100.0)
+    run = out["runs"][s["cores"]]
+    assert s["value"] == pytest.approx(1.0 / (run["t_assembly"] + run["t_setup"] + 100.0 * run["t_iter"]))
+    assert s["kind"] == "oracle" and "extrapolated" in s["sample"]
